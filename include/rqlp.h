@@ -1,0 +1,189 @@
+/*
+ * rqlp.h - C ABI of the MI355X (gfx950) randomized QLP library.
+ *
+ * The library computes the rank-l randomized QLP factorisation
+ *     A  ~=  Q T P^T
+ * of Wu & Xiang, "Randomized QLP algorithm and error analysis":
+ * Algorithm 2.1 (RQLP), Algorithm 2.2 (ERQLP, d inner QR steps) and
+ * Algorithm 4.1 (block RQLP).  A is m x n (k <= n <= m), l = k + p,
+ * Q is m x l and P is n x l with orthonormal columns, T is l x l triangular
+ * and diag(T) are the "L-values" (Section 1).  q >= 0 subspace iterations
+ * (Y <- A orth(A^T orth(Y))) may be added to the range finder of Section 2.
+ *
+ * Conventions for every entry point
+ *   - matrices are column-major with an explicit leading dimension
+ *     (element (i, j) of X is X[i + j * ldx]); ld >= rows;
+ *   - all matrix / vector pointers are DEVICE pointers unless marked "host";
+ *   - sizes are int64_t;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *     every call only enqueues work on it and returns without waiting,
+ *     except where stated;
+ *   - the caller owns every buffer, including the workspace `work`; the
+ *     library allocates and frees no device memory and keeps no per-call
+ *     state (it caches immutable device properties only);
+ *   - return value (synchronous, host): 0 on success, -i when argument i
+ *     (1-based, LAPACK style) is invalid, or one of the RQLP_E_* codes.
+ *     Numerical events found on the device are reported through the device
+ *     word *info (bit flags RQLP_INFO_*), valid once the stream has reached
+ *     the end of the call.
+ */
+#ifndef RQLP_H
+#define RQLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Arithmetic of the hot path.
+ *   RQLP_F64       : everything in FP64 (A, Q, P are double).
+ *   RQLP_F32       : A, Q, P float; GEMMs and orthonormalisation in FP32;
+ *                    CPQR and the second stage in FP64.
+ *   RQLP_MIXED_BF16: A, Q, P float; A, Omega and the orthonormal bases are
+ *                    rounded to bfloat16 for the MFMA GEMMs (FP32 accumulate),
+ *                    orthonormalisation by CholeskyQR2 with FP32 panels,
+ *                    CPQR / second stage / L in FP64.
+ *   RQLP_MIXED_FP16: as BF16 with IEEE half and per-column power-of-two
+ *                    scaling of A.
+ *   RQLP_MIXED_BF16X3: as BF16 with A and the bases split into hi + lo
+ *                    bfloat16 parts (three MFMA products per pass).       */
+enum rqlp_precision {
+    RQLP_F64 = 0,
+    RQLP_F32 = 1,
+    RQLP_MIXED_BF16 = 2,
+    RQLP_MIXED_FP16 = 3,
+    RQLP_MIXED_BF16X3 = 4
+};
+
+enum rqlp_status {
+    RQLP_OK = 0,
+    RQLP_E_WORKSPACE = -1000,   /* work_bytes smaller than rqlp_workspace_size() */
+    RQLP_E_HIP = -1001,         /* a HIP launch / runtime call failed            */
+    RQLP_E_UNSUPPORTED = -1002  /* valid arguments this build does not handle     */
+};
+
+/* bit flags written to *info (device int32) */
+#define RQLP_INFO_CHOLQR_SHIFTED   0x1  /* a Cholesky broke down; shifted retry used */
+#define RQLP_INFO_RANK_DEFICIENT   0x2  /* a CPQR stopped early: trailing L-values 0 */
+#define RQLP_INFO_NONFINITE        0x4  /* NaN / Inf met in A or an intermediate     */
+#define RQLP_INFO_BARRIER_TIMEOUT  0x8  /* a grid-wide wait exceeded its spin bound  */
+#define RQLP_INFO_CHOL_FAILED      0x10 /* Cholesky failed even after the shift      */
+
+/* Library version string (host, static storage). */
+const char* rqlp_version(void);
+
+/* Human-readable text for a return code (host, static storage). */
+const char* rqlp_status_string(int status);
+
+/* Bytes of device workspace rqlp_factor needs for these arguments
+ * (written to *bytes, a host pointer).  Arguments as for rqlp_factor. */
+int rqlp_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p, int q, int d, int b,
+                        int precision, size_t* bytes);
+
+/* Gaussian test matrix (Section 2, range finder step 1; Algorithm 2.1
+ * step 1): Omega (n x l, leading dimension ldo) with N(0,1) entries.
+ * Element (i, j) is Box-Muller applied to the first two 32-bit words of
+ * Philox4x32-10 (Salmon et al., SC'11) with counter (i, j, 0, 0) and key
+ * (low 32 bits of seed, high 32 bits of seed):
+ *     U1 = (w0 + 1) 2^-32,  U2 = w1 2^-32,
+ *     Omega(i, j) = sqrt(-2 ln U1) cos(2 pi U2),
+ * computed in FP64 and stored as double (RQLP_F64) or float (other
+ * precisions; mixed precisions round further to the 16-bit GEMM type, and
+ * store that exactly representable value as float). */
+int rqlp_generate_omega(int64_t n, int64_t l, uint64_t seed, int precision,
+                        void* Omega, int64_t ldo, void* stream);
+
+/* Randomized QLP of A (Algorithms 2.1, 2.2, 4.1).
+ *
+ *   A      m x n, lda >= m; double for RQLP_F64, float otherwise.  Read only.
+ *   k, p   target rank k >= 2 and oversampling p >= 2 (Algorithm 2.1 input),
+ *          l = k + p <= n <= m (Section 1 problem statement).
+ *   q      number of subspace iterations of the range finder, q >= 0.
+ *   d      0: RQLP, second factorisation pivoted (Algorithm 2.1 step 6);
+ *          d >= 1: ERQLP with d unpivoted inner QR steps (Algorithm 2.2).
+ *   b      0: unblocked; b >= 1: block RQLP with blocks of b columns of
+ *          Omega (Algorithm 4.1; the last block is ragged when b does not
+ *          divide l); requires d == 0.
+ *   precision  one of rqlp_precision.
+ *   seed   used when Omega == NULL (see rqlp_generate_omega).
+ *   Omega  optional n x l test matrix (ldo >= n), same element type as A;
+ *          NULL => generated from seed into the workspace.
+ *   Q      m x l output (ldq >= m), element type of A.
+ *   T      l x l output (ldt >= l), double: lower triangular ("L") for d = 0
+ *          and odd d, upper triangular for even d >= 2 (the inner-QR
+ *          assembly of Algorithm 2.2 puts R^(d) itself, not its transpose,
+ *          between the orthogonal factors when d is even); *uplo says which.
+ *          Block RQLP: T = blkdiag(L_1, ..., L_h).
+ *   P      n x l output (ldp >= n), element type of A.  Block RQLP: each
+ *          b-column block is orthonormal (the blocks are not mutually
+ *          orthogonal).
+ *   piv0   l int64 (may be NULL): the first l pivots of the CPQR of B
+ *          (original column indices of A, 0-based); block RQLP: per block.
+ *   piv1   l int64 (may be NULL): pivots of the second CPQR (d = 0), the
+ *          identity otherwise; block RQLP: per block, 0-based within it.
+ *   lvals  l doubles (may be NULL): diag(T) (>= 0).
+ *   info   device int32 (may be NULL): RQLP_INFO_* flags, overwritten.
+ *   uplo   host char (may be NULL): 'L' or 'U', the triangle of T.
+ *   work   device workspace of work_bytes >= rqlp_workspace_size(); its
+ *          contents on entry are ignored.  Alignment 256 bytes.
+ *
+ * Arguments are checked before any work is enqueued.  Outputs are written
+ * with plain stores; on RQLP_E_* nothing useful is in them. */
+int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int64_t p,
+                int q, int d, int b, int precision, uint64_t seed,
+                const void* Omega, int64_t ldo,
+                void* Q, int64_t ldq, double* T, int64_t ldt, void* P, int64_t ldp,
+                int64_t* piv0, int64_t* piv1, double* lvals, int32_t* info, char* uplo,
+                void* work, size_t work_bytes, void* stream);
+
+/* ---- building blocks (the steps of Algorithm 2.1, usable on their own) ---- */
+
+/* Y = A X  (Algorithm 2.1 step 2, and every pass of the subspace iteration):
+ * A m x n, X n x c, Y m x c, all double (RQLP_F64) or all float (RQLP_F32).
+ * Uses `work` for split-K partial sums; query the size with rqlp_gemm_workspace. */
+int rqlp_sketch(const void* A, int64_t lda, int64_t m, int64_t n, const void* X, int64_t ldx,
+                int64_t c, void* Y, int64_t ldy, int precision, void* work, size_t work_bytes,
+                void* stream);
+
+/* B = V^T A  (Algorithm 2.1 step 4): V m x c, A m x n, B c x n. */
+int rqlp_project(const void* A, int64_t lda, int64_t m, int64_t n, const void* V, int64_t ldv,
+                 int64_t c, void* B, int64_t ldb, int precision, void* work, size_t work_bytes,
+                 void* stream);
+
+/* Bytes of work rqlp_sketch / rqlp_project need for these shapes (host out). */
+int rqlp_gemm_workspace(int64_t m, int64_t n, int64_t c, int precision, size_t* bytes);
+
+/* [V, ~] = qr(Y)  (Algorithm 2.1 step 3): V (m x c) gets an orthonormal basis
+ * of range(Y) by CholeskyQR2 (shifted retry on breakdown); Y is m x c,
+ * double.  R (c x c upper, ldr >= c, may be NULL) receives the triangular
+ * factor with Y = V R, diag(R) > 0.  V may alias Y. */
+int rqlp_orthonormalize(const double* Y, int64_t ldy, int64_t m, int64_t c, double* V,
+                        int64_t ldv, double* R, int64_t ldr, int32_t* info, void* work,
+                        size_t work_bytes, void* stream);
+int rqlp_orthonormalize_workspace(int64_t m, int64_t c, size_t* bytes);
+
+/* Column-pivoted Householder QR of the rows x cols double matrix M
+ * (Algorithm 2.1 steps 5-6; the CPQR of Section 1): M Pi = Qm R with the
+ * Businger-Golub pivot rule (largest residual column norm, residual norms
+ * recomputed each step), diag(R) >= 0.  Outputs (any may be NULL):
+ *   piv   min(rows, cols) int64 pivots (original column indices);
+ *   R     rows x min(rows, cols) (ldr >= rows): the pivoted columns of R
+ *         (upper triangular block R11);
+ *   Rt    cols x rows (ldrt >= cols): row c holds column c of R in the
+ *         ORIGINAL column order (R Pi^T transposed);
+ *   Qm    rows x min(rows, cols) (ldq >= rows), explicit orthonormal factor.
+ * Pivots whose residual norms are within a relative 2^-36 may be taken in
+ * either order; the numerical-rank stop (residual <= max(rows, cols) eps
+ * ||M||_F) zeroes the trailing rows of R and sets RQLP_INFO_RANK_DEFICIENT. */
+int rqlp_cpqr(const double* M, int64_t ldm, int64_t rows, int64_t cols, int64_t* piv,
+              double* R, int64_t ldr, double* Rt, int64_t ldrt, double* Qm, int64_t ldq,
+              int32_t* info, void* work, size_t work_bytes, void* stream);
+int rqlp_cpqr_workspace(int64_t rows, int64_t cols, size_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RQLP_H */

@@ -38,6 +38,7 @@ class QRResult:
     R: np.ndarray          # kmax x cols, upper trapezoidal, diag >= 0
     perm: np.ndarray       # cols: M[:, perm] = Q R  (perm[:kmax] are the pivots)
     rank: int              # kmax unless the numerical-rank stop fired
+    trace: Optional[np.ndarray] = None   # per step: (largest, chosen, second largest) residual norm
 
 
 def _reflector(x: np.ndarray):
@@ -56,7 +57,7 @@ def _apply(v: np.ndarray, M: np.ndarray) -> None:
 
 
 def _householder_qr(M: np.ndarray, piv: Optional[Sequence[int]], pivoting: bool,
-                    tol: Optional[float], want_q: bool) -> QRResult:
+                    tol: Optional[float], want_q: bool, want_trace: bool = False) -> QRResult:
     R = np.array(M, dtype=np.float64, copy=True, order="F")
     rows, cols = R.shape
     kmax = min(rows, cols)
@@ -65,7 +66,13 @@ def _householder_qr(M: np.ndarray, piv: Optional[Sequence[int]], pivoting: bool,
         tol = max(rows, cols) * EPS * float(np.sqrt(np.sum(R * R)))
     refl = []
     rank = kmax
+    trace = []
     for j in range(kmax):
+        if want_trace:
+            nrm = np.sqrt(np.sum(R[j:, j:] * R[j:, j:], axis=0))
+            srt = np.sort(nrm)[::-1]
+            chosen = nrm[int(np.flatnonzero(perm[j:] == int(piv[j]))[0])] if piv is not None else srt[0]
+            trace.append((srt[0], chosen, srt[1] if len(srt) > 1 else 0.0))
         if piv is not None:
             p = j + int(np.flatnonzero(perm[j:] == int(piv[j]))[0])
         elif pivoting:
@@ -102,16 +109,19 @@ def _householder_qr(M: np.ndarray, piv: Optional[Sequence[int]], pivoting: bool,
         for j, v in reversed(refl):
             _apply(v, E[j:, :])
         Q = E * sgn[None, :]
-    return QRResult(Q=Q, R=np.triu(R), perm=perm, rank=rank)
+    return QRResult(Q=Q, R=np.triu(R), perm=perm, rank=rank,
+                    trace=np.array(trace) if want_trace else None)
 
 
 def cpqr(M: np.ndarray, piv: Optional[Sequence[int]] = None, tol: Optional[float] = None,
-         want_q: bool = True) -> QRResult:
+         want_q: bool = True, want_trace: bool = False) -> QRResult:
     """Column-pivoted QR M[:, perm] = Q R (Businger-Golub, exact norm recompute).
 
     ``piv`` (optional) freezes the first min(rows, cols) pivots (original
-    column indices); the rank stop is then disabled."""
-    return _householder_qr(M, piv, True, tol, want_q)
+    column indices); the rank stop is then disabled.  ``want_trace`` records,
+    for every step, the largest residual column norm, the norm of the column
+    taken and the second largest norm (used to judge pivot ties)."""
+    return _householder_qr(M, piv, True, tol, want_q, want_trace)
 
 
 def householder_qr(M: np.ndarray, want_q: bool = True) -> QRResult:

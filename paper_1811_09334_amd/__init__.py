@@ -1,2 +1,203 @@
-"""MI355X-native randomized QLP (RQLP / ERQLP / block RQLP)."""
+"""MI355X-native randomized QLP (RQLP / ERQLP / block RQLP).
+
+``A ~= Q T P^T`` with Q (m x l), P (n x l) column-orthonormal and T (l x l)
+triangular whose diagonal are the L-values (Wu & Xiang, Algorithms 2.1, 2.2,
+4.1).  Every step runs in the gfx950 kernels of ``librqlp.so``; this module
+only allocates device memory with torch, picks the current stream and
+forwards pointers through the C ABI (``_lib``).  When the library is missing,
+calls raise: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
 from . import inputs  # noqa: F401
+from ._lib import RQLPError, check, load  # noqa: F401
+from . import _lib
+
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "fp16": 3, "bf16x3": 4}
+INFO_FLAGS = {"cholqr_shifted": 0x1, "rank_deficient": 0x2, "nonfinite": 0x4, "barrier_timeout": 0x8,
+              "chol_failed": 0x10}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _prec(precision) -> int:
+    if isinstance(precision, int):
+        return precision
+    return PRECISIONS[precision]
+
+
+def _elem_dtype(prec: int):
+    torch = _torch()
+    return torch.float64 if prec == 0 else torch.float32
+
+
+def empty_colmajor(rows: int, cols: int, dtype, device):
+    """Uninitialised column-major (rows x cols) tensor: stride (1, rows)."""
+    torch = _torch()
+    return torch.empty((cols, rows), dtype=dtype, device=device).t()
+
+
+def colmajor(t):
+    """``t`` itself when it is already column-major (stride(0) == 1), else a column-major copy."""
+    if t.dim() != 2:
+        raise ValueError("expected a matrix")
+    rows, cols = t.shape
+    if t.stride(0) == 1 and (cols <= 1 or t.stride(1) >= max(rows, 1)):
+        return t
+    return t.t().contiguous().t()
+
+
+def ld(t) -> int:
+    rows, cols = t.shape
+    return max(int(t.stride(1)) if cols > 1 else rows, 1)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device=None) -> int:
+    torch = _torch()
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+@dataclass
+class Factorization:
+    Q: "object"        # m x l (column-major)
+    T: "object"        # l x l, float64
+    P: "object"        # n x l
+    piv0: "object"     # l int64
+    piv1: "object"     # l int64
+    lvals: "object"    # l float64
+    info: "object"     # 1 int32 (device)
+    uplo: str
+
+    def info_flags(self) -> dict:
+        v = int(self.info.item())
+        return {k: bool(v & b) for k, b in INFO_FLAGS.items()}
+
+
+def workspace_size(m, n, k, p, q=0, d=0, b=0, precision="f64") -> int:
+    return _lib.rqlp_workspace_size(m, n, k, p, q, d, b, _prec(precision))
+
+
+def factor(A, k: int, p: int, q: int = 0, d: int = 0, b: int = 0, precision="f64", seed: int = 0,
+           Omega=None, work=None) -> Factorization:
+    """Randomized QLP of the device matrix ``A`` (m x n) through ``rqlp_factor``.
+
+    ``A`` (and ``Omega`` if given, n x (k+p)) must be float64 for 'f64' and
+    float32 otherwise; column-major layouts are used as they are, other
+    layouts are copied once to column-major."""
+    torch = _torch()
+    load()
+    prec = _prec(precision)
+    dt = _elem_dtype(prec)
+    if A.dtype != dt:
+        raise TypeError(f"A must be {dt} for precision {precision}")
+    A = colmajor(A)
+    m, n = A.shape
+    l = k + p
+    dev = A.device
+    if Omega is not None:
+        if Omega.dtype != dt or tuple(Omega.shape) != (n, l):
+            raise ValueError("Omega must be n x (k+p) with the element type of A")
+        Omega = colmajor(Omega)
+    Q = empty_colmajor(m, l, dt, dev)
+    T = empty_colmajor(l, l, torch.float64, dev)
+    P = empty_colmajor(n, l, dt, dev)
+    piv0 = torch.empty(l, dtype=torch.int64, device=dev)
+    piv1 = torch.empty(l, dtype=torch.int64, device=dev)
+    lv = torch.empty(l, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    nbytes = workspace_size(m, n, k, p, q, d, b, prec)
+    if work is None or work.numel() < nbytes:
+        work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    uplo = ctypes.c_char(b"?")
+    st = _lib.rqlp_factor(A.data_ptr(), ld(A), m, n, k, p, q, d, b, prec, seed,
+                          _ptr(Omega), ld(Omega) if Omega is not None else max(n, 1),
+                          Q.data_ptr(), ld(Q), T.data_ptr(), ld(T), P.data_ptr(), ld(P),
+                          piv0.data_ptr(), piv1.data_ptr(), lv.data_ptr(), info.data_ptr(),
+                          ctypes.byref(uplo), work.data_ptr(), work.numel(), _stream(dev))
+    check("rqlp_factor", st)
+    return Factorization(Q=Q, T=T, P=P, piv0=piv0, piv1=piv1, lvals=lv, info=info, uplo=uplo.value.decode())
+
+
+def generate_omega(n: int, l: int, seed: int, precision="f64", device="cuda"):
+    """The library's Philox4x32-10 / Box-Muller test matrix (n x l, column-major)."""
+    prec = _prec(precision)
+    out = empty_colmajor(n, l, _elem_dtype(prec), device)
+    check("rqlp_generate_omega", _lib.rqlp_generate_omega(n, l, seed, prec, out.data_ptr(), ld(out),
+                                                          _stream(out.device)))
+    return out
+
+
+def sketch(A, X, precision=None):
+    """Y = A X through ``rqlp_sketch``."""
+    torch = _torch()
+    prec = _prec(precision if precision is not None else ("f64" if A.dtype == torch.float64 else "f32"))
+    A, X = colmajor(A), colmajor(X)
+    m, n = A.shape
+    c = X.shape[1]
+    Y = empty_colmajor(m, c, A.dtype, A.device)
+    nb = _lib.rqlp_gemm_workspace(m, n, c, prec)
+    work = torch.empty(nb, dtype=torch.uint8, device=A.device)
+    check("rqlp_sketch", _lib.rqlp_sketch(A.data_ptr(), ld(A), m, n, X.data_ptr(), ld(X), c, Y.data_ptr(), ld(Y),
+                                          prec, work.data_ptr(), nb, _stream(A.device)))
+    return Y
+
+
+def project(A, V, precision=None):
+    """B = V^T A through ``rqlp_project``."""
+    torch = _torch()
+    prec = _prec(precision if precision is not None else ("f64" if A.dtype == torch.float64 else "f32"))
+    A, V = colmajor(A), colmajor(V)
+    m, n = A.shape
+    c = V.shape[1]
+    B = empty_colmajor(c, n, A.dtype, A.device)
+    nb = _lib.rqlp_gemm_workspace(m, n, c, prec)
+    work = torch.empty(nb, dtype=torch.uint8, device=A.device)
+    check("rqlp_project", _lib.rqlp_project(A.data_ptr(), ld(A), m, n, V.data_ptr(), ld(V), c, B.data_ptr(),
+                                            ld(B), prec, work.data_ptr(), nb, _stream(A.device)))
+    return B
+
+
+def orthonormalize(Y, want_r: bool = False):
+    """[V, R] = qr(Y) by CholeskyQR2 through ``rqlp_orthonormalize`` (FP64)."""
+    torch = _torch()
+    Y = colmajor(Y)
+    m, c = Y.shape
+    V = empty_colmajor(m, c, torch.float64, Y.device)
+    R = empty_colmajor(c, c, torch.float64, Y.device) if want_r else None
+    info = torch.zeros(1, dtype=torch.int32, device=Y.device)
+    nb = _lib.rqlp_orthonormalize_workspace(m, c)
+    work = torch.empty(nb, dtype=torch.uint8, device=Y.device)
+    check("rqlp_orthonormalize", _lib.rqlp_orthonormalize(Y.data_ptr(), ld(Y), m, c, V.data_ptr(), ld(V),
+                                                          _ptr(R), ld(R) if R is not None else 1, info.data_ptr(),
+                                                          work.data_ptr(), nb, _stream(Y.device)))
+    return (V, R, info) if want_r else (V, info)
+
+
+def cpqr(M):
+    """Column-pivoted QR through ``rqlp_cpqr``: returns (piv, R11, Rt, Q, info)."""
+    torch = _torch()
+    M = colmajor(M)
+    rows, cols = M.shape
+    kmax = min(rows, cols)
+    piv = torch.empty(kmax, dtype=torch.int64, device=M.device)
+    R = empty_colmajor(rows, kmax, torch.float64, M.device)
+    Rt = empty_colmajor(cols, rows, torch.float64, M.device)
+    Q = empty_colmajor(rows, kmax, torch.float64, M.device)
+    info = torch.zeros(1, dtype=torch.int32, device=M.device)
+    nb = _lib.rqlp_cpqr_workspace(rows, cols)
+    work = torch.empty(nb, dtype=torch.uint8, device=M.device)
+    check("rqlp_cpqr", _lib.rqlp_cpqr(M.data_ptr(), ld(M), rows, cols, piv.data_ptr(), R.data_ptr(), ld(R),
+                                      Rt.data_ptr(), ld(Rt), Q.data_ptr(), ld(Q), info.data_ptr(),
+                                      work.data_ptr(), nb, _stream(M.device)))
+    return piv, R, Rt, Q, info

@@ -1,0 +1,125 @@
+// Internal helpers shared by the gfx950 kernels of the randomized QLP library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/rqlp.h"
+
+#define RQLP_WAVE 64
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+namespace rqlp {
+
+// ---------------------------------------------------------------------------
+// host-side error plumbing
+// ---------------------------------------------------------------------------
+#define RQLP_HIP_TRY(expr)                                   \
+    do {                                                     \
+        hipError_t _e = (expr);                              \
+        if (_e != hipSuccess) return RQLP_E_HIP;             \
+    } while (0)
+
+#define RQLP_TRY(expr)                                       \
+    do {                                                     \
+        int _s = (expr);                                     \
+        if (_s != 0) return _s;                              \
+    } while (0)
+
+static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Linear carve-up of the caller's workspace (256-byte aligned pieces).
+struct Arena {
+    char* base;
+    size_t used;
+    size_t cap;
+    Arena(void* b, size_t c) : base((char*)b), used(0), cap(c) {}
+    template <typename T>
+    T* take(size_t count) {
+        size_t bytes = align256(count * sizeof(T));
+        T* p = base ? (T*)(base + used) : nullptr;
+        used += bytes;
+        return p;
+    }
+    bool ok() const { return used <= cap; }
+};
+
+// device properties cached per device (immutable after first query)
+struct DeviceInfo {
+    int device = -1;
+    int num_cus = 0;
+    size_t max_lds = 0;
+};
+const DeviceInfo& device_info();
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, RQLP_WAVE);
+    return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, RQLP_WAVE);
+    return v;
+}
+
+// Order-preserving 64-bit key for a non-negative double: larger value ->
+// larger key.  The low `ibits` bits carry (mask - index) so that among equal
+// truncated values the smallest index wins an unsigned max.
+__device__ __forceinline__ unsigned long long pivot_key(double v, unsigned idx, int ibits) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);   // v >= 0
+    unsigned long long mask = (1ull << ibits) - 1ull;
+    return (b & ~mask) | (mask - (unsigned long long)idx);
+}
+__device__ __forceinline__ unsigned key_index(unsigned long long key, int ibits) {
+    unsigned long long mask = (1ull << ibits) - 1ull;
+    return (unsigned)(mask - (key & mask));
+}
+__device__ __forceinline__ double key_value(unsigned long long key, int ibits) {
+    unsigned long long mask = (1ull << ibits) - 1ull;
+    return __longlong_as_double((long long)(key & ~mask));
+}
+
+// Grid-wide barrier for cooperatively launched kernels (all workgroups
+// co-resident).  bar[0] counts arrivals, bar[1] is the generation.  Every
+// wait is bounded: after `spin_limit` polls the barrier gives up, raises
+// RQLP_INFO_BARRIER_TIMEOUT in *info and returns false; callers then leave
+// the kernel, so no wave can wait forever.
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned& gen,
+                                             int32_t* info, unsigned long long spin_limit) {
+    __shared__ int s_ok;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        unsigned g = gen;
+        unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned long long spins = 0;
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (++spins > spin_limit) {
+                    ok = 0;
+                    if (info) atomicOr(info, RQLP_INFO_BARRIER_TIMEOUT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        gen = g + 1u;
+        s_ok = ok;
+    }
+    __syncthreads();
+    __threadfence();
+    return s_ok != 0;
+}
+
+}  // namespace rqlp

@@ -1,0 +1,452 @@
+// Column-pivoted Householder QR of the reduced matrix (Algorithm 2.1 step 5,
+// Algorithm 2.2 step 5; CPQR as defined in Section 1) and of the small l x l
+// factor of the second stage (Algorithm 2.1 step 6).
+//
+// Design: the matrix is distributed by columns over G co-resident workgroups
+// (cooperative launch), each holding its columns in LDS for the whole
+// factorisation, so the matrix never returns to HBM until the end.  Every
+// pivot step needs one grid-wide agreement on the winning column:
+//   1. each workgroup finds its best active column (largest residual norm,
+//      ties -> smallest index) and publishes it: a 64-bit key (norm^2 with the
+//      low mantissa bits replaced by the complemented column index) goes into
+//      a device-wide atomic max, and the column itself into a double-buffered
+//      exchange slot;
+//   2. one grid barrier;
+//   3. every workgroup reads the winning key and column, builds the same
+//      Householder reflector redundantly (bitwise identical, fixed reduction
+//      order), applies it to its own active columns and recomputes their
+//      residual norms exactly from LDS.
+// The reflector keeps R(j, j) = ||x|| >= 0 (Parlett's form of the
+// Householder vector; Golub & Van Loan, Alg. 5.1.1).  Columns whose norms
+// agree to 2^-(52 - index bits) may be taken in either order.
+// Numerical-rank stop: when the largest residual norm is <= max(rows, cols)
+// * eps * ||M||_F, the remaining steps take the smallest-index active columns,
+// apply no reflection, and the trailing rows of R are zero.
+// With G = 1 the exchange goes through LDS only.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rqlp {
+
+constexpr int CP_T = 256;
+constexpr unsigned long long CP_SPIN_LIMIT = 1ull << 20;   // ~1 s of polling
+
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
+    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+    lo = __shfl_xor(lo, m, RQLP_WAVE);
+    hi = __shfl_xor(hi, m, RQLP_WAVE);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+template <bool SINGLE>
+__global__ __launch_bounds__(CP_T) void cpqr_kernel(
+    const double* __restrict__ M, int64_t ldm, int rows, int cols, int cpw, int kmax, int ibits,
+    unsigned long long* keys, double* candcol, double* partial, unsigned* bar, int64_t* piv,
+    double* Vh, int64_t ldv, double* beta_out, double* Rpiv, int64_t ldr, double* Rt, int64_t ldrt,
+    int32_t* info, unsigned long long spin_limit) {
+    extern __shared__ double lds[];
+    const int ldl = rows | 1;
+    double* colv = lds;                                  // cpw x ldl
+    double* nrm2 = colv + (size_t)cpw * ldl;             // cpw
+    double* v = nrm2 + cpw;                              // rows
+    int* act = (int*)(v + rows);                         // cpw: -1 active, else pivot step
+
+    __shared__ double s_red[CP_T / 64];
+    __shared__ unsigned long long s_kred[2][CP_T / 64];
+    __shared__ unsigned long long s_key[2];
+    __shared__ double s_beta, s_mu, s_tol2;
+    __shared__ int s_stop, s_rank;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int G = gridDim.x, g = blockIdx.x;
+    const int c0 = g * cpw;
+    const int ncol = (cols - c0) < cpw ? ((cols - c0) > 0 ? cols - c0 : 0) : cpw;
+    unsigned gen = 0;
+
+    for (int idx = tid; idx < ncol * rows; idx += CP_T) {
+        const int c = idx / rows, i = idx % rows;
+        colv[c * ldl + i] = M[i + (int64_t)(c0 + c) * ldm];
+    }
+    for (int c = tid; c < ncol; c += CP_T) act[c] = -1;
+    __syncthreads();
+
+    // exact column norms (4 threads per column) and ||M||_F^2
+    for (int c = tid >> 2; c < ncol; c += CP_T / 4) {
+        const int qd = tid & 3;
+        double s = 0.0;
+        for (int i = qd; i < rows; i += 4) s += colv[c * ldl + i] * colv[c * ldl + i];
+        s += __shfl_xor(s, 1, RQLP_WAVE);
+        s += __shfl_xor(s, 2, RQLP_WAVE);
+        if (qd == 0) nrm2[c] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double f = 0.0;
+        for (int c = 0; c < ncol; ++c) f += nrm2[c];
+        if (!SINGLE) partial[g] = f;
+        s_tol2 = f;
+    }
+    if (!SINGLE) {
+        if (!grid_barrier(bar, G, gen, info, spin_limit)) return;
+        if (tid == 0) {
+            double f = 0.0;
+            for (int h = 0; h < G; ++h) f += partial[h];
+            s_tol2 = f;
+        }
+    }
+    if (tid == 0) {
+        const double tol = (double)(rows > cols ? rows : cols) * 2.220446049250313e-16;
+        s_tol2 = tol * tol * s_tol2;
+        s_stop = 0;
+        s_rank = kmax;
+    }
+    __syncthreads();
+
+    for (int j = 0; j < kmax; ++j) {
+        const int stopped = s_stop;
+        // ---- 1. local candidates: by norm (k0) and by smallest index (k1) ----
+        unsigned long long k0 = 0, k1 = 0;
+        for (int c = tid; c < ncol; c += CP_T) {
+            if (act[c] < 0) {
+                const unsigned long long a = pivot_key(stopped ? 0.0 : nrm2[c], (unsigned)(c0 + c), ibits);
+                const unsigned long long b = pivot_key(0.0, (unsigned)(c0 + c), ibits);
+                k0 = a > k0 ? a : k0;
+                k1 = b > k1 ? b : k1;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long a = shfl_xor_u64(k0, off), b = shfl_xor_u64(k1, off);
+            k0 = a > k0 ? a : k0;
+            k1 = b > k1 ? b : k1;
+        }
+        if (lane == 0) {
+            s_kred[0][wave] = k0;
+            s_kred[1][wave] = k1;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long a = 0, b = 0;
+            for (int w = 0; w < CP_T / 64; ++w) {
+                a = s_kred[0][w] > a ? s_kred[0][w] : a;
+                b = s_kred[1][w] > b ? s_kred[1][w] : b;
+            }
+            s_key[0] = a;
+            s_key[1] = b;
+        }
+        __syncthreads();
+        unsigned long long best0 = s_key[0], best1 = s_key[1];
+        if (!SINGLE) {
+            if (best0 != 0 && !stopped) {
+                const int bc = (int)key_index(best0, ibits) - c0;
+                double* slot = candcol + ((size_t)(j & 1) * G + g) * rows;
+                for (int i = j + tid; i < rows; i += CP_T) slot[i] = colv[bc * ldl + i];
+            }
+            if (tid == 0 && best0 != 0) {
+                atomicMax(&keys[2 * j], best0);
+                atomicMax(&keys[2 * j + 1], best1);
+            }
+            if (!grid_barrier(bar, G, gen, info, spin_limit)) return;
+            best0 = __hip_atomic_load(&keys[2 * j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            best1 = __hip_atomic_load(&keys[2 * j + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // ---- 2. decide the pivot ----
+        int now_stopped = stopped;
+        if (!stopped && !(key_value(best0, ibits) > s_tol2)) {
+            const double kv = key_value(best0, ibits);
+            if (kv == kv) now_stopped = 1;   // NaN norms never trigger the stop
+        }
+        const unsigned long long best = now_stopped ? best1 : best0;
+        const int gidx = (int)key_index(best, ibits);
+        const int owner = gidx / cpw;
+        // ---- 3. reflector ----
+        if (!now_stopped) {
+            if (SINGLE) {
+                for (int i = j + tid; i < rows; i += CP_T) v[i] = colv[(gidx - c0) * ldl + i];
+            } else {
+                const double* slot = candcol + ((size_t)(j & 1) * G + owner) * rows;
+                for (int i = j + tid; i < rows; i += CP_T) v[i] = slot[i];
+            }
+            __syncthreads();
+            double s = 0.0;
+            for (int i = j + 1 + tid; i < rows; i += CP_T) s += v[i] * v[i];
+            s = wave_sum(s);
+            if (lane == 0) s_red[wave] = s;
+            __syncthreads();
+            if (tid == 0) {
+                double sigma = 0.0;
+                for (int w = 0; w < CP_T / 64; ++w) sigma += s_red[w];
+                const double x0 = v[j];
+                const double mu = sqrt(x0 * x0 + sigma);
+                double v0, b;
+                if (sigma == 0.0) {
+                    v0 = 1.0;
+                    b = (x0 >= 0.0) ? 0.0 : 2.0;
+                } else {
+                    v0 = (x0 <= 0.0) ? (x0 - mu) : (-sigma / (x0 + mu));
+                    b = 2.0 * v0 * v0 / (sigma + v0 * v0);
+                }
+                s_beta = b;
+                s_mu = mu;
+                s_red[0] = v0;
+            }
+            __syncthreads();
+            const double v0 = s_red[0];
+            for (int i = j + 1 + tid; i < rows; i += CP_T) v[i] = (s_beta == 0.0) ? 0.0 : v[i] / v0;
+            if (tid == 0) v[j] = 1.0;
+        } else {
+            if (tid == 0) {
+                s_beta = 0.0;
+                s_mu = 0.0;
+                if (!stopped) {
+                    s_stop = 1;
+                    s_rank = j;
+                }
+            }
+        }
+        __syncthreads();
+        const double b = s_beta;
+        // ---- 4. bookkeeping ----
+        if (g == 0) {
+            if (tid == 0) {
+                if (piv) piv[j] = gidx;
+                if (beta_out) beta_out[j] = b;
+            }
+            if (Vh) {
+                for (int i = tid; i < rows; i += CP_T)
+                    Vh[i + (int64_t)j * ldv] = (i < j || now_stopped) ? ((i == j) ? 1.0 : 0.0) : v[i];
+            }
+        }
+        if (owner == g) {
+            const int lc = gidx - c0;
+            if (tid == 0) act[lc] = j;
+            if (!now_stopped) {
+                for (int i = j + tid; i < rows; i += CP_T) colv[lc * ldl + i] = (i == j) ? s_mu : 0.0;
+            }
+        }
+        __syncthreads();
+        // ---- 5. apply H = I - b v v^T to the active local columns, exact norms ----
+        if (!now_stopped) {
+            for (int c = tid >> 2; c < ncol; c += CP_T / 4) {
+                if (act[c] >= 0) continue;
+                const int qd = tid & 3;
+                double* col = colv + c * ldl;
+                double dot = 0.0;
+                for (int i = j + qd; i < rows; i += 4) dot += v[i] * col[i];
+                dot += __shfl_xor(dot, 1, RQLP_WAVE);
+                dot += __shfl_xor(dot, 2, RQLP_WAVE);
+                const double w = b * dot;
+                double s = 0.0;
+                for (int i = j + qd; i < rows; i += 4) {
+                    const double x = col[i] - w * v[i];
+                    col[i] = x;
+                    if (i > j) s += x * x;
+                }
+                s += __shfl_xor(s, 1, RQLP_WAVE);
+                s += __shfl_xor(s, 2, RQLP_WAVE);
+                if (qd == 0) nrm2[c] = s;
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- write back: R^T in original column order, pivoted columns of R ----
+    const int rank = s_rank;
+    if (rank < kmax && g == 0 && tid == 0 && info) atomicOr(info, RQLP_INFO_RANK_DEFICIENT);
+    if (Rt) {
+        for (int idx = tid; idx < ncol * rows; idx += CP_T) {
+            const int c = idx % ncol, i = idx / ncol;
+            Rt[(c0 + c) + (int64_t)i * ldrt] = (i >= rank) ? 0.0 : colv[c * ldl + i];
+        }
+    }
+    if (Rpiv) {
+        for (int c = 0; c < ncol; ++c) {
+            const int js = act[c];
+            if (js < 0) continue;
+            for (int i = tid; i < rows; i += CP_T)
+                Rpiv[i + (int64_t)js * ldr] = (i >= rank || i > js) ? 0.0 : colv[c * ldl + i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+static int index_bits(int64_t cols) {
+    int b = 1;
+    while ((1ll << b) <= cols) ++b;
+    return b;
+}
+
+static size_t cpqr_lds(int64_t rows, int cpw) {
+    const int ldl = (int)(rows | 1);
+    return sizeof(double) * ((size_t)cpw * ldl + cpw + rows) + sizeof(int) * (size_t)cpw;
+}
+
+int cpqr_plan(int64_t rows, int64_t cols, CpqrPlan* plan) {
+    const DeviceInfo& di = device_info();
+    const size_t budget = di.max_lds > 0 ? di.max_lds : 65536;
+    const int cus = di.num_cus > 0 ? di.num_cus : 1;
+    // single workgroup when everything fits
+    if (cpqr_lds(rows, (int)cols) <= budget && cols <= 512) {
+        plan->G = 1;
+        plan->cpw = (int)cols;
+        plan->lds = cpqr_lds(rows, (int)cols);
+        plan->single = true;
+        return 0;
+    }
+    int cpw = (int)ceil_div(cols, cus);
+    if (cpw < 1) cpw = 1;
+    while (cpqr_lds(rows, cpw) > budget && cpw > 1) --cpw;
+    if (cpqr_lds(rows, cpw) > budget) return RQLP_E_UNSUPPORTED;
+    const int64_t G = ceil_div(cols, cpw);
+    if (G > cus) return RQLP_E_UNSUPPORTED;   // would not be co-resident (one workgroup per CU)
+    plan->G = (int)G;
+    plan->cpw = cpw;
+    plan->lds = cpqr_lds(rows, cpw);
+    plan->single = (G == 1);
+    return 0;
+}
+
+size_t cpqr_scratch_bytes(int64_t rows, int64_t cols) {
+    Arena ar(nullptr, 0);
+    CpqrScratch sc;
+    cpqr_carve(ar, rows, cols, &sc);
+    return ar.used;
+}
+
+void cpqr_carve(Arena& ar, int64_t rows, int64_t cols, CpqrScratch* sc) {
+    const int cus = device_info().num_cus > 0 ? device_info().num_cus : 256;
+    const int64_t kmax = rows < cols ? rows : cols;
+    sc->keys = ar.take<unsigned long long>(2 * kmax);
+    sc->candcol = ar.take<double>((size_t)2 * cus * rows);
+    sc->partial = ar.take<double>(cus);
+    sc->bar = ar.take<unsigned>(2);
+}
+
+int cpqr(const double* M, int64_t ldm, int64_t rows, int64_t cols, const CpqrScratch& sc, int64_t* piv,
+         double* Vh, int64_t ldv, double* beta, double* Rpiv, int64_t ldr, double* Rt, int64_t ldrt,
+         int32_t* info, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return 0;
+    CpqrPlan plan;
+    RQLP_TRY(cpqr_plan(rows, cols, &plan));
+    const int64_t kmax = rows < cols ? rows : cols;
+    int ibits = index_bits(cols);
+    int rows_i = (int)rows, cols_i = (int)cols, cpw = plan.cpw, kmax_i = (int)kmax;
+    unsigned long long spin = CP_SPIN_LIMIT;
+    static bool attr_set = false;
+    if (!attr_set) {
+        const int mx = (int)(device_info().max_lds > 0 ? device_info().max_lds : 65536);
+        RQLP_HIP_TRY(hipFuncSetAttribute((const void*)cpqr_kernel<true>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, mx));
+        RQLP_HIP_TRY(hipFuncSetAttribute((const void*)cpqr_kernel<false>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, mx));
+        attr_set = true;
+    }
+    if (plan.single) {
+        hipLaunchKernelGGL(cpqr_kernel<true>, dim3(1), dim3(CP_T), plan.lds, s, M, ldm, rows_i, cols_i, cpw,
+                           kmax_i, ibits, sc.keys, sc.candcol, sc.partial, sc.bar, piv, Vh, ldv, beta, Rpiv,
+                           ldr, Rt, ldrt, info, spin);
+        return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
+    }
+    RQLP_TRY(fill_zero_bytes(sc.keys, sizeof(unsigned long long) * 2 * kmax, s));
+    RQLP_TRY(fill_zero_bytes(sc.bar, 2 * sizeof(unsigned), s));
+    int nb = 0;
+    RQLP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)cpqr_kernel<false>, CP_T,
+                                                             plan.lds));
+    if ((int64_t)nb * device_info().num_cus < plan.G) return RQLP_E_UNSUPPORTED;
+    const double* Mp = M;
+    int64_t ldm_ = ldm, ldv_ = ldv, ldr_ = ldr, ldrt_ = ldrt;
+    unsigned long long* keys = sc.keys;
+    double* cand = sc.candcol;
+    double* part = sc.partial;
+    unsigned* bar = sc.bar;
+    void* args[] = {(void*)&Mp,   (void*)&ldm_,  (void*)&rows_i, (void*)&cols_i, (void*)&cpw,
+                    (void*)&kmax_i, (void*)&ibits, (void*)&keys, (void*)&cand,  (void*)&part,
+                    (void*)&bar,  (void*)&piv,   (void*)&Vh,    (void*)&ldv_,  (void*)&beta,
+                    (void*)&Rpiv, (void*)&ldr_,  (void*)&Rt,    (void*)&ldrt_, (void*)&info,
+                    (void*)&spin};
+    RQLP_HIP_TRY(hipLaunchCooperativeKernel((const void*)cpqr_kernel<false>, dim3(plan.G), dim3(CP_T), args,
+                                            (unsigned)plan.lds, s));
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Y = H_0 H_1 ... H_{k-1} X, one wave per column, the column held in registers
+// (RPL rows per lane), the next reflector prefetched while the current one is
+// applied.
+template <int RPL>
+__global__ __launch_bounds__(256) void apply_householder_kernel(int rows, int k, const double* __restrict__ Vh,
+                                                                int64_t ldv, const double* __restrict__ beta,
+                                                                const double* __restrict__ X, int64_t ldx,
+                                                                const int64_t* __restrict__ unit, int ncols,
+                                                                double* __restrict__ Y, int64_t ldy) {
+    const int lane = threadIdx.x & 63;
+    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (col >= ncols) return;
+    double x[RPL];
+    const int64_t u = unit ? unit[col] : (int64_t)col;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        x[r] = (i < rows) ? (X ? X[i + (int64_t)col * ldx] : (i == u ? 1.0 : 0.0)) : 0.0;
+    }
+    double vn[RPL];
+    if (k > 0) {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = lane + 64 * r;
+            vn[r] = (i < rows) ? Vh[i + (int64_t)(k - 1) * ldv] : 0.0;
+        }
+    }
+    for (int j = k - 1; j >= 0; --j) {
+        double vc[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) vc[r] = vn[r];
+        const double bj = beta[j];
+        if (j > 0) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = lane + 64 * r;
+                vn[r] = (i < rows) ? Vh[i + (int64_t)(j - 1) * ldv] : 0.0;
+            }
+        }
+        double dot = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = lane + 64 * r;
+            dot += (i >= j) ? vc[r] * x[r] : 0.0;
+        }
+        dot = wave_sum(dot);
+        const double w = bj * dot;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = lane + 64 * r;
+            if (i >= j) x[r] -= w * vc[r];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        if (i < rows) Y[i + (int64_t)col * ldy] = x[r];
+    }
+}
+
+int apply_householder(int64_t rows, int64_t k, const double* Vh, int64_t ldv, const double* beta,
+                      const double* X, int64_t ldx, const int64_t* unit, int64_t ncols, double* Y,
+                      int64_t ldy, hipStream_t s) {
+    if (rows <= 0 || ncols <= 0) return 0;
+    dim3 grid((unsigned)ceil_div(ncols, 4));
+    const int rpl = (int)ceil_div(rows, 64);
+#define RQLP_AH(R)                                                                                       \
+    hipLaunchKernelGGL(apply_householder_kernel<R>, grid, dim3(256), 0, s, (int)rows, (int)k, Vh, ldv, beta, \
+                       X, ldx, unit, (int)ncols, Y, ldy)
+    if (rpl <= 1) RQLP_AH(1);
+    else if (rpl <= 2) RQLP_AH(2);
+    else if (rpl <= 4) RQLP_AH(4);
+    else if (rpl <= 5) RQLP_AH(5);
+    else if (rpl <= 8) RQLP_AH(8);
+    else if (rpl <= 17) RQLP_AH(17);
+    else return RQLP_E_UNSUPPORTED;
+#undef RQLP_AH
+    return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
+}
+
+}  // namespace rqlp

@@ -1,0 +1,75 @@
+// Host-side launchers of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include "common.hpp"
+
+namespace rqlp {
+
+// --- gemm.hip ---------------------------------------------------------------
+// C = alpha * op(A) * B + beta * C, op(A) = A (ta = false, A is M x K) or
+// A^T (ta = true, A is K x M); B is K x N; C is M x N, or N x M when
+// trans_out (C = (op(A) B)^T).  ws must hold gemm_workspace_elems(M, N, K)
+// elements unless the product goes straight to C.
+size_t gemm_workspace_elems(int64_t M, int64_t N, int64_t K);
+template <typename T>
+int gemm(bool ta, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64_t ldb,
+         T* C, int64_t ldc, bool trans_out, T alpha, T beta, T* ws, size_t ws_elems, hipStream_t s);
+
+// --- chol.hip ---------------------------------------------------------------
+// Cholesky G = L L^T of the c x c Gram matrix (lower triangle read) and the
+// inverse of L, in one workgroup.  On breakdown the factorisation restarts
+// from G + shift * trace(G) * I (RQLP_INFO_CHOLQR_SHIFTED).  Outputs (any may
+// be NULL): R = L^T (upper), Rinv = L^{-T} (upper); strictly lower parts are
+// written as zero.  W1, W2: c x c scratch (ld = c).
+size_t chol_inv_lds_bytes(int64_t c);
+int chol_inv(int64_t c, const double* G, int64_t ldg, double* R, int64_t ldr, double* Rinv,
+             int64_t ldri, double shift_scale, double* W1, double* W2, int32_t* info, hipStream_t s);
+
+// --- cpqr.hip ---------------------------------------------------------------
+struct CpqrScratch {
+    unsigned long long* keys;   // kmax
+    double* candcol;            // 2 * G * rows
+    double* partial;            // G
+    unsigned* bar;              // 2
+};
+struct CpqrPlan {
+    int G;          // workgroups
+    int cpw;        // columns per workgroup
+    size_t lds;     // dynamic LDS bytes
+    bool single;    // one workgroup: no grid-wide exchange
+};
+int cpqr_plan(int64_t rows, int64_t cols, CpqrPlan* plan);
+size_t cpqr_scratch_bytes(int64_t rows, int64_t cols);
+void cpqr_carve(Arena& ar, int64_t rows, int64_t cols, CpqrScratch* sc);
+// M: rows x cols.  Outputs (any may be NULL except as noted): piv (kmax,
+// int64), Vh (rows x kmax Householder vectors, v_j(j) = 1), beta (kmax),
+// Rpiv (rows x kmax, pivoted columns of R), Rt (cols x rows: R^T in
+// original column order).
+int cpqr(const double* M, int64_t ldm, int64_t rows, int64_t cols, const CpqrScratch& sc, int64_t* piv,
+         double* Vh, int64_t ldv, double* beta, double* Rpiv, int64_t ldr, double* Rt, int64_t ldrt,
+         int32_t* info, hipStream_t s);
+
+// Y = H_0 H_1 ... H_{k-1} X  (rows x ncols, in place on Y), where X is either
+// given (X != NULL, copied into Y) or the unit columns e_{unit[c]} (unit !=
+// NULL) or the leading identity columns (both NULL).
+int apply_householder(int64_t rows, int64_t k, const double* Vh, int64_t ldv, const double* beta,
+                      const double* X, int64_t ldx, const int64_t* unit, int64_t ncols, double* Y,
+                      int64_t ldy, hipStream_t s);
+
+// --- misc.hip ---------------------------------------------------------------
+int fill_zero_bytes(void* p, size_t bytes, hipStream_t s);
+int copy_matrix(int64_t rows, int64_t cols, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                hipStream_t s);
+// Y (cols x rows) = X^T, optionally keeping only the lower/upper triangle of Y.
+// tri: 0 = full, 'L' = keep lower of Y, 'U' = keep upper of Y (rest zero).
+int transpose_matrix(int64_t rows, int64_t cols, const double* X, int64_t ldx, double* Y, int64_t ldy,
+                     int tri, hipStream_t s);
+int set_identity(int64_t n, double* Y, int64_t ldy, hipStream_t s);
+// lvals = diag(T), flags NaN/Inf in T into *info
+int finish_lvals(int64_t l, const double* T, int64_t ldt, double* lvals, int32_t* info, hipStream_t s);
+// dst[i] = src[i], or dst[i] = i when src is NULL
+int copy_i64(int64_t n, const int64_t* src, int64_t* dst, hipStream_t s);
+int generate_omega(int64_t n, int64_t l, uint64_t seed, int precision, void* Omega, int64_t ldo,
+                   hipStream_t s);
+
+}  // namespace rqlp

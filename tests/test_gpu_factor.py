@@ -1,0 +1,102 @@
+"""GPU parity of the whole FP64 pipeline (rqlp_factor through the C ABI)
+against the FP64 CPU oracle on the same seeded A and Omega.
+
+Bar (FP64 path): L-values j <= k within 1e-10 relative, the reconstruction
+Q T P^T within 1e-10 of the oracle's relative to ||A||_F, pivots identical
+wherever the oracle's top-two residual norms differ by more than 1e-8
+(otherwise the oracle is re-run on the GPU's pivots and compared there)."""
+import numpy as np
+import pytest
+
+from oracle.rqlp import rqlp as oracle_rqlp
+from paper_1811_09334_amd import inputs
+
+from _helpers import first_difference, pivots_valid, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+LVAL_TOL = 1e-10
+REC_TOL = 1e-10
+
+
+def _compare(gpu, A, Om, k, p, q, d, lval_tol=LVAL_TOL):
+    f = gpu.factor(to_dev(A), k, p, q=q, d=d, Omega=to_dev(Om))
+    Q, T, P = to_np(f.Q), to_np(f.T), to_np(f.P)
+    piv0, piv1, lv, info = to_np(f.piv0), to_np(f.piv1), to_np(f.lvals), int(to_np(f.info)[0])
+    l = k + p
+    ref = oracle_rqlp(A, Om, k, p, q=q, d=d)
+    if first_difference(piv0, ref.piv0) >= 0 or (d == 0 and first_difference(piv1, ref.piv1) >= 0):
+        ok0, bad0 = pivots_valid(ref.B, piv0)
+        assert ok0, f"first-CPQR pivot {bad0} was not maximal within 1e-8"
+        ref = oracle_rqlp(A, Om, k, p, q=q, d=d, piv0=piv0, piv1=piv1 if d == 0 else None)
+    assert info == 0, f"info flags {info:#x}"
+    assert f.uplo == ref.uplo
+    assert np.array_equal(np.diag(T), lv)
+    rel = np.abs(lv[:k] - ref.lvals[:k]) / ref.lvals[:k]
+    assert rel.max() < lval_tol, f"L-value rel err {rel.max():.3e} at j={rel.argmax()}"
+    nA = np.linalg.norm(A)
+    rec = np.linalg.norm(Q @ T @ P.T - ref.Q @ ref.T @ ref.P.T) / nA
+    assert rec < REC_TOL, f"reconstruction differs by {rec:.3e}"
+    err_g = np.linalg.norm(A - Q @ T @ P.T) / nA
+    err_o = np.linalg.norm(A - ref.Q @ ref.T @ ref.P.T) / nA
+    assert abs(err_g - err_o) < REC_TOL
+    assert np.abs(Q.T @ Q - np.eye(l)).max() < 1e-12
+    assert np.abs(P.T @ P - np.eye(l)).max() < 1e-12
+    tri = np.triu(T, 1) if f.uplo == "L" else np.tril(T, -1)
+    assert np.all(tri == 0.0)
+    assert np.all(lv >= 0)
+    return f, ref, rel.max(), rec
+
+
+@pytest.mark.parametrize("d", [0, 1, 2, 3])
+@pytest.mark.parametrize("q", [0, 1])
+def test_rqlp_1000x500_k20_p5(gpu, q, d):
+    """The plain-RQLP FP64 workload (m=1000, n=500, s_j = j^-2, k=20, p=5)."""
+    w = inputs.WORKLOADS["rqlp_f64_1000x500"]
+    A, Om = inputs.make_matrix(w), inputs.make_omega(w)
+    _compare(gpu, A, Om, w.k, w.p, q, d)
+
+
+@pytest.mark.parametrize("m,n,k,p,q,d", [
+    (777, 333, 30, 7, 1, 0),      # ragged tiles everywhere, l = 37
+    (777, 333, 30, 7, 2, 2),
+    (300, 60, 50, 10, 0, 0),      # l = n
+    (400, 400, 100, 20, 1, 4),    # square
+    (40, 20, 2, 2, 0, 0),         # smallest k and p
+    (2500, 1200, 130, 10, 1, 0),  # second-stage CPQR on 140 x 140 in one workgroup
+    (3000, 1500, 150, 10, 1, 0),  # second-stage CPQR spread over workgroups (l = 160)
+])
+def test_rqlp_shapes(gpu, m, n, k, p, q, d):
+    s = inputs.spectrum_poly(n, 1.0)
+    A = inputs.svd_matrix(m, n, s, m + n)
+    Om = inputs.gaussian(n, k + p, k)
+    _compare(gpu, A, Om, k, p, q, d)
+
+
+def test_erqlp_two_level_spectrum_scaled(gpu):
+    """The ERQLP FP64 workload's spectrum (log-linear 1 -> 1e-4, then 1e-6) at
+    4000 x 2000, k = 100, p = 10, q = 1, d = 2."""
+    m, n, k, p = 4000, 2000, 100, 10
+    A = inputs.svd_matrix(m, n, inputs.spectrum_two_level(n, head=k), 7)
+    Om = inputs.gaussian(n, k + p, 8)
+    _, _, rel, rec = _compare(gpu, A, Om, k, p, 1, 2)
+    print(f"two-level 4000x2000: L-value rel err {rel:.2e}, reconstruction diff {rec:.2e}")
+
+
+def test_library_omega_is_used_when_none_given(gpu):
+    from oracle.philox import omega_gaussian
+    w = inputs.WORKLOADS["rqlp_f64_1000x500"]
+    A = inputs.make_matrix(w)
+    f = gpu.factor(to_dev(A), w.k, w.p, seed=1234)
+    ref = oracle_rqlp(A, omega_gaussian(w.n, w.l, 1234), w.k, w.p)
+    lv = to_np(f.lvals)
+    assert np.max(np.abs(lv[: w.k] - ref.lvals[: w.k]) / ref.lvals[: w.k]) < LVAL_TOL
+
+
+def test_repeat_calls_are_bitwise_identical(gpu):
+    w = inputs.WORKLOADS["rqlp_f64_1000x500"]
+    A, Om = to_dev(inputs.make_matrix(w)), to_dev(inputs.make_omega(w))
+    f1 = gpu.factor(A, w.k, w.p, q=1, d=2, Omega=Om)
+    f2 = gpu.factor(A, w.k, w.p, q=1, d=2, Omega=Om)
+    for a, b in [(f1.Q, f2.Q), (f1.T, f2.T), (f1.P, f2.P), (f1.piv0, f2.piv0)]:
+        assert np.array_equal(to_np(a), to_np(b))

@@ -1,0 +1,113 @@
+"""GPU parity of the building blocks (through the C ABI) against the FP64
+oracle or plain NumPy products: the Gaussian generator, the skinny MFMA
+products, CholeskyQR2 and the column-pivoted QR."""
+import numpy as np
+import pytest
+
+from oracle.philox import omega_gaussian
+from oracle.qr import cpqr as oracle_cpqr
+from paper_1811_09334_amd import inputs
+
+from _helpers import first_difference, pivots_valid, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def test_omega_generator_matches_reference(gpu):
+    for n, l, seed in [(500, 25, 2000), (1031, 47, 2**40 + 7), (7, 3, 0)]:
+        g = to_np(gpu.generate_omega(n, l, seed, "f64"))
+        ref = omega_gaussian(n, l, seed)
+        assert g.shape == (n, l)
+        assert np.max(np.abs(g - ref)) < 1e-13 * max(1.0, np.abs(ref).max())
+    g32 = to_np(gpu.generate_omega(300, 20, 5, "bf16"))
+    ref = inputs.round_to_bf16(omega_gaussian(300, 20, 5))
+    # same bfloat16 value except where the double sits on a rounding boundary
+    assert np.mean(g32 == ref) > 0.999
+
+
+@pytest.mark.parametrize("m,n,c", [(1000, 500, 25), (777, 333, 47), (4096, 2048, 210), (64, 16, 16),
+                                   (130, 70, 3), (5000, 300, 272), (2000, 4000, 120)])
+def test_sketch_and_projection_f64(gpu, m, n, c):
+    rng = np.random.default_rng(m + n + c)
+    A = rng.standard_normal((m, n))
+    X = rng.standard_normal((n, c))
+    V = rng.standard_normal((m, c))
+    Y = to_np(gpu.sketch(to_dev(A), to_dev(X)))
+    ref = A @ X
+    assert np.max(np.abs(Y - ref)) < 1e-13 * np.sqrt(n) * np.abs(ref).max() + 1e-13
+    B = to_np(gpu.project(to_dev(A), to_dev(V)))
+    ref = V.T @ A
+    assert B.shape == (c, n)
+    assert np.max(np.abs(B - ref)) < 1e-13 * np.sqrt(m) * np.abs(ref).max() + 1e-13
+
+
+@pytest.mark.parametrize("m,n,c", [(1000, 500, 25), (777, 333, 47), (3000, 1000, 136)])
+def test_sketch_and_projection_f32(gpu, m, n, c):
+    import torch
+    rng = np.random.default_rng(7 * m + c)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    X = rng.standard_normal((n, c)).astype(np.float32)
+    Y = to_np(gpu.sketch(to_dev(A), to_dev(X))).astype(np.float64)
+    ref = A.astype(np.float64) @ X.astype(np.float64)
+    assert np.max(np.abs(Y - ref)) < 2e-6 * np.sqrt(n) * np.abs(ref).max()
+    B = to_np(gpu.project(to_dev(A), to_dev(Y.astype(np.float32)))).astype(np.float64)
+    refB = Y.astype(np.float32).astype(np.float64).T @ A.astype(np.float64)
+    assert np.max(np.abs(B - refB)) < 2e-6 * np.sqrt(m) * np.abs(refB).max()
+    assert torch.cuda.is_available()
+
+
+@pytest.mark.parametrize("m,c,cond", [(2000, 25, 1e2), (5000, 210, 1e6), (333, 333, 1e3), (4096, 272, 1e4),
+                                      (100, 7, 1.0)])
+def test_cholqr2_orthonormalizes(gpu, m, c, cond):
+    rng = np.random.default_rng(c)
+    U = inputs.haar_columns(rng, m, c)
+    Vr = inputs.haar_columns(rng, c, c)
+    Y = (U * np.logspace(0, -np.log10(cond), c)) @ Vr.T
+    V, R, info = gpu.orthonormalize(to_dev(Y), want_r=True)
+    V, R = to_np(V), to_np(R)
+    assert int(to_np(info)[0]) == 0
+    assert np.abs(V.T @ V - np.eye(c)).max() < 1e-13 * max(10, c)
+    assert np.allclose(np.tril(R, -1), 0.0) and np.all(np.diag(R) > 0)
+    assert np.linalg.norm(Y - V @ R) < 1e-14 * cond * np.linalg.norm(Y) * c
+    # unique QR with positive diagonal: compare with the oracle's Householder QR
+    q, r = np.linalg.qr(Y)
+    s = np.sign(np.diag(r))
+    assert np.allclose(V[:, :min(c, 10)], (q * s)[:, :min(c, 10)], atol=1e-9 * cond)
+
+
+@pytest.mark.parametrize("rows,cols,seed", [(25, 500, 0), (210, 2000, 1), (47, 333, 2), (64, 64, 3),
+                                            (136, 136, 4), (200, 200, 5), (272, 4000, 6), (30, 12, 7)])
+def test_cpqr_matches_oracle(gpu, rows, cols, seed):
+    rng = np.random.default_rng(seed)
+    M = rng.standard_normal((rows, cols)) * np.exp(rng.uniform(-6, 0, cols))[None, :]
+    piv, R, Rt, Q, info = gpu.cpqr(to_dev(M))
+    piv, R, Rt, Q = to_np(piv), to_np(R), to_np(Rt), to_np(Q)
+    kmax = min(rows, cols)
+    ok, bad = pivots_valid(M, piv)
+    assert ok, f"pivot {bad} was not a maximal column"
+    ref = oracle_cpqr(M)
+    if first_difference(piv, ref.perm[:kmax]) >= 0:
+        ref = oracle_cpqr(M, piv=piv)      # a near-tie was broken the other way: compare on its pivots
+    scale = np.abs(ref.R).max()
+    assert np.max(np.abs(R[:kmax] - ref.R[:, :kmax])) < 1e-12 * scale
+    assert np.all(R[kmax:] == 0.0)
+    # Rt holds R in the original column order (transposed)
+    Rorig = np.zeros((kmax, cols))
+    Rorig[:, ref.perm] = ref.R
+    assert np.max(np.abs(Rt[:, :kmax].T - Rorig)) < 1e-12 * scale
+    assert np.max(np.abs(Q - ref.Q)) < 1e-10
+    assert int(to_np(info)[0]) == 0
+
+
+def test_cpqr_rank_deficient_stop(gpu):
+    rng = np.random.default_rng(11)
+    M = rng.standard_normal((40, 6)) @ rng.standard_normal((6, 300))
+    piv, R, Rt, Q, info = gpu.cpqr(to_dev(M))
+    piv, R = to_np(piv), to_np(R)
+    ref = oracle_cpqr(M)
+    assert ref.rank == 6
+    assert int(to_np(info)[0]) & 0x2
+    assert np.array_equal(piv[:6], ref.perm[:6])
+    assert np.allclose(R[6:, :], 0.0)
+    # after the stop the remaining pivots are the smallest unused indices
+    assert np.array_equal(piv[6:], ref.perm[6:40])

@@ -1,0 +1,85 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/rqlp.h declares, and rejects invalid arguments
+with LAPACK-style negative indices before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1811_09334_amd as rq
+from paper_1811_09334_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rqlp.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rqlp_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("librqlp.so is not built (run __graft_entry__.build())")
+    return rq.load()
+
+
+def test_every_declared_symbol_is_exported_and_bound(lib):
+    names = _declared()
+    assert "rqlp_factor" in names and "rqlp_cpqr" in names
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, f"{name} has no Python binding"
+    assert set(_lib.SIGNATURES) == set(names)
+
+
+def test_version_and_status_strings(lib):
+    assert _lib.rqlp_version().startswith("rqlp-gfx950")
+    assert _lib.rqlp_status_string(0) == "success"
+    assert "workspace" in _lib.rqlp_status_string(-1000)
+    assert "invalid argument" in _lib.rqlp_status_string(-4)
+
+
+def _factor_status(**kw):
+    a = dict(A=1, lda=100, m=100, n=50, k=5, p=3, q=0, d=0, b=0, precision=0, seed=0, Omega=None, ldo=50,
+             Q=1, ldq=100, T=1, ldt=8, P=1, ldp=50, piv0=None, piv1=None, lvals=None, info=None, uplo=None,
+             work=1, work_bytes=0, stream=None)
+    a.update(kw)
+    return _lib.rqlp_factor(*a.values())
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(A=None), -1), (dict(lda=99), -2), (dict(m=0), -3), (dict(n=101), -4), (dict(n=0), -4),
+    (dict(k=1), -5), (dict(p=1), -6), (dict(k=48, p=3), -6), (dict(q=-1), -7), (dict(d=-1), -8),
+    (dict(b=-1), -9), (dict(b=4, d=2), -9), (dict(precision=7), -10), (dict(Omega=1, ldo=49), -13),
+    (dict(Q=None), -14), (dict(ldq=99), -15), (dict(T=None), -16), (dict(ldt=7), -17), (dict(P=None), -18),
+    (dict(ldp=49), -19), (dict(work=None), -25),
+])
+def test_factor_rejects_invalid_arguments(lib, kw, code):
+    assert _factor_status(**kw) == code
+
+
+def test_workspace_too_small_is_reported(lib):
+    assert _factor_status(work_bytes=16) == -1000
+
+
+def test_workspace_size_query(lib):
+    b1 = rq.workspace_size(1000, 500, 20, 5)
+    b2 = rq.workspace_size(20000, 10000, 200, 10, 1, 2)
+    assert 0 < b1 < b2
+    # dominated by the m x l panels, the reduced matrix and the split-K partial sums
+    assert b2 >= 8 * (2 * 20000 * 210 + 3 * 10000 * 210)
+    with pytest.raises(rq.RQLPError):
+        rq.workspace_size(10, 20, 2, 2)
+
+
+def test_building_block_argument_checks(lib):
+    assert _lib.rqlp_sketch(None, 10, 10, 5, 1, 5, 3, 1, 10, 0, None, 0, None) == -1
+    assert _lib.rqlp_sketch(1, 9, 10, 5, 1, 5, 3, 1, 10, 0, None, 0, None) == -2
+    assert _lib.rqlp_project(1, 10, 10, 5, 1, 10, 3, 1, 2, 0, None, 0, None) == -9
+    assert _lib.rqlp_cpqr(1, 3, 4, 6, None, None, 0, None, 0, None, 0, None, None, 0, None) == -2
+    assert _lib.rqlp_orthonormalize(1, 10, 10, 11, 1, 10, None, 0, None, None, 0, None) == -4
+    assert _lib.rqlp_generate_omega(10, 3, 0, 9, 1, 10, None) == -4

@@ -106,3 +106,18 @@ def test_cpqr_frozen_pivots_reproduce_free_run():
     h = cpqr(M, piv=piv)
     assert np.array_equal(h.perm[:15], piv)
     _check_factor(M, h)
+
+
+def test_cpqr_trace_records_step_norms():
+    rng = np.random.default_rng(8)
+    M = rng.standard_normal((6, 20))
+    f = cpqr(M, want_trace=True)
+    assert f.trace.shape == (6, 3)
+    # free run: the chosen norm is the largest; the first largest is the largest column norm of M
+    assert np.allclose(f.trace[:, 0], f.trace[:, 1])
+    assert np.isclose(f.trace[0, 0], np.linalg.norm(M, axis=0).max())
+    assert np.all(f.trace[:, 2] <= f.trace[:, 0])
+    # a frozen run records the norm of the imposed pivot
+    piv = f.perm[:6][::-1]
+    g = cpqr(M, piv=piv, want_trace=True)
+    assert np.isclose(g.trace[0, 1], np.linalg.norm(M[:, piv[0]]))
