@@ -17,20 +17,16 @@ double shift_scale(int64_t rows, int64_t c) { return 11.0 * ((double)rows * c + 
 // Scratch for orthonormalising a rows x c panel.
 struct OrthoScratch {
     double* G;      // c x c Gram
-    double* Rinv;   // c x c
-    double* R1;     // c x c
-    double* R2;     // c x c
-    double* W1;     // c x c chol scratch
-    double* W2;     // c x c
+    double* L1;     // c x c Cholesky factor of pass 1
+    double* L2;     // c x c Cholesky factor of pass 2
+    double* Li;     // c x c inverse of the current factor
 };
 
 void carve_ortho(Arena& ar, int64_t c, OrthoScratch* o) {
     o->G = ar.take<double>(c * c);
-    o->Rinv = ar.take<double>(c * c);
-    o->R1 = ar.take<double>(c * c);
-    o->R2 = ar.take<double>(c * c);
-    o->W1 = ar.take<double>(c * c);
-    o->W2 = ar.take<double>(c * c);
+    o->L1 = ar.take<double>(c * c);
+    o->L2 = ar.take<double>(c * c);
+    o->Li = ar.take<double>(c * c);
 }
 
 struct Ctx {
@@ -42,27 +38,27 @@ struct Ctx {
 };
 
 // CholeskyQR2 of the rows x c panel held in buf0 (leading dimension ld):
-// two passes of G = X^T X, G = R^T R, X <- X R^{-1}.  Returns the buffer
-// holding the orthonormal result (buf0 or buf1).  Rout (c x c, optional)
-// receives R2 R1 so that X_in = V Rout.
-int cholqr2(Ctx& cx, int64_t rows, int64_t c, double* buf0, double* buf1, int64_t ld, double* Rout,
+// two passes of G = X^T X, G = L L^T, X <- X L^{-T}.  Returns the buffer
+// holding the orthonormal result (buf0 or buf1; buf0 is overwritten).  RT
+// (c x c, optional) receives R^T = L1 L2 (lower triangular), where
+// X_in = V R is the QR factorisation with diag(R) > 0.
+int cholqr2(Ctx& cx, int64_t rows, int64_t c, double* buf0, double* buf1, int64_t ld, double* RT,
             double** out) {
     double* cur = buf0;
     double* nxt = buf1;
     for (int pass = 0; pass < 2; ++pass) {
-        RQLP_TRY(gemm<double>(true, c, c, rows, cur, ld, cur, ld, cx.o.G, c, false, 1.0, 0.0, cx.gws,
+        RQLP_TRY(gemm<double>(true, false, c, c, rows, cur, ld, cur, ld, cx.o.G, c, false, 1.0, 0.0, cx.gws,
                               cx.gws_elems, cx.s));
-        double* Rp = Rout ? (pass == 0 ? cx.o.R1 : cx.o.R2) : nullptr;
-        RQLP_TRY(chol_inv(c, cx.o.G, c, Rp, c, cx.o.Rinv, c, shift_scale(rows, c), cx.o.W1, cx.o.W2, cx.info,
-                          cx.s));
-        RQLP_TRY(gemm<double>(false, rows, c, c, cur, ld, cx.o.Rinv, c, nxt, ld, false, 1.0, 0.0, cx.gws,
+        double* Lp = pass == 0 ? cx.o.L1 : cx.o.L2;
+        RQLP_TRY(chol_inv(c, cx.o.G, c, Lp, cx.o.Li, c, shift_scale(rows, c), cx.info, cx.s));
+        RQLP_TRY(gemm<double>(false, true, rows, c, c, cur, ld, cx.o.Li, c, nxt, ld, false, 1.0, 0.0, cx.gws,
                               cx.gws_elems, cx.s));
         double* t = cur;
         cur = nxt;
         nxt = t;
     }
-    if (Rout)
-        RQLP_TRY(gemm<double>(false, c, c, c, cx.o.R2, c, cx.o.R1, c, Rout, c, false, 1.0, 0.0, cx.gws,
+    if (RT)
+        RQLP_TRY(gemm<double>(false, false, c, c, c, cx.o.L1, c, cx.o.L2, c, RT, c, false, 1.0, 0.0, cx.gws,
                               cx.gws_elems, cx.s));
     *out = cur;
     return 0;
@@ -99,12 +95,13 @@ struct FactorBufs {
     int64_t* piv1;
     double* Lt;
     double* Rtil;
+    double* RtT;
+    double* RiT;
     double* Ml;
     double* Mr;
     double* Mt;
     double* Xi;
     double* Xi2;
-    double* Ri;
     int32_t* info;
 };
 
@@ -127,12 +124,13 @@ void carve_factor(Arena& ar, int64_t m, int64_t n, int64_t l, bool need_omega, F
     f->piv1 = ar.take<int64_t>(l);
     f->Lt = ar.take<double>(l * l);
     f->Rtil = ar.take<double>(l * l);
+    f->RtT = ar.take<double>(l * l);
+    f->RiT = ar.take<double>(l * l);
     f->Ml = ar.take<double>(l * l);
     f->Mr = ar.take<double>(l * l);
     f->Mt = ar.take<double>(l * l);
     f->Xi = ar.take<double>(l * l);
     f->Xi2 = ar.take<double>(l * l);
-    f->Ri = ar.take<double>(l * l);
     f->info = ar.take<int32_t>(1);
 }
 
@@ -238,60 +236,62 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
         Om = f.Om;
         ldom = n;
     }
-    RQLP_TRY(gemm<double>(false, m, l, n, Ad, lda, Om, ldom, f.Y, m, false, 1.0, 0.0, f.gws, f.gws_elems, s));
+    RQLP_TRY(gemm<double>(false, false, m, l, n, Ad, lda, Om, ldom, f.Y, m, false, 1.0, 0.0, f.gws, f.gws_elems, s));
     double* V = nullptr;
     RQLP_TRY(cholqr2(cx, m, l, f.Y, f.Y2, m, nullptr, &V));
     for (int it = 0; it < q; ++it) {
-        RQLP_TRY(gemm<double>(true, n, l, m, Ad, lda, V, m, f.Z, n, false, 1.0, 0.0, f.gws, f.gws_elems, s));
+        RQLP_TRY(gemm<double>(true, false, n, l, m, Ad, lda, V, m, f.Z, n, false, 1.0, 0.0, f.gws, f.gws_elems, s));
         double* W = nullptr;
         RQLP_TRY(cholqr2(cx, n, l, f.Z, f.Z2, n, nullptr, &W));
         double* ydst = (V == f.Y) ? f.Y2 : f.Y;
-        RQLP_TRY(gemm<double>(false, m, l, n, Ad, lda, W, n, ydst, m, false, 1.0, 0.0, f.gws, f.gws_elems, s));
+        RQLP_TRY(gemm<double>(false, false, m, l, n, Ad, lda, W, n, ydst, m, false, 1.0, 0.0, f.gws, f.gws_elems, s));
         double* other = (ydst == f.Y) ? f.Y2 : f.Y;
         RQLP_TRY(cholqr2(cx, m, l, ydst, other, m, nullptr, &V));
     }
     // ---- projection B = V^T A (as (A^T V)^T, stored l x n) ----
-    RQLP_TRY(gemm<double>(true, n, l, m, Ad, lda, V, m, f.B, l, true, 1.0, 0.0, f.gws, f.gws_elems, s));
+    RQLP_TRY(gemm<double>(true, false, n, l, m, Ad, lda, V, m, f.B, l, true, 1.0, 0.0, f.gws, f.gws_elems, s));
     // ---- first CPQR: B Pi0 = Q0 R0; R0^T kept in original column order (n x l) ----
     RQLP_TRY(cpqr(f.B, l, l, n, f.cs, f.piv0, f.Vh0, l, f.beta0, nullptr, l, f.Z, n, inf, s));
-    // ---- second stage: R0^T = Qt Rtil (CholeskyQR2) ----
+    // ---- second stage: R0^T = Qt Rtil (CholeskyQR2), Rtil^T kept ----
     double* Qt = nullptr;
-    RQLP_TRY(cholqr2(cx, n, l, f.Z, f.Z2, n, f.Rtil, &Qt));
+    RQLP_TRY(cholqr2(cx, n, l, f.Z, f.Z2, n, f.RtT, &Qt));
     char tri = 'L';
     if (d == 0) {
         // Rtil Pi1 = Qhat L^T (pivoted, l x l); Q1 = Qt Qhat
+        RQLP_TRY(transpose_matrix(l, l, f.RtT, l, f.Rtil, l, 0, s));
         RQLP_TRY(cpqr(f.Rtil, l, l, l, f.cs, f.piv1, f.Vh1, l, f.beta1, f.Lt, l, nullptr, 1, inf, s));
         RQLP_TRY(apply_householder(l, l, f.Vh1, l, f.beta1, nullptr, 0, nullptr, l, f.Mr, l, s));
-        RQLP_TRY(gemm<double>(false, n, l, l, Qt, n, f.Mr, l, (double*)P, ldp, false, 1.0, 0.0, f.gws,
+        RQLP_TRY(gemm<double>(false, false, n, l, l, Qt, n, f.Mr, l, (double*)P, ldp, false, 1.0, 0.0, f.gws,
                               f.gws_elems, s));
         // Q0 Pi1
         RQLP_TRY(apply_householder(l, l, f.Vh0, l, f.beta0, nullptr, 0, f.piv1, l, f.Ml, l, s));
         RQLP_TRY(transpose_matrix(l, l, f.Lt, l, T, ldt, 'L', s));
     } else {
-        // inner unpivoted QR steps R(i-1)^T = Q(i) R(i); R(1) = Rtil, Q(1) = Qt
-        double* Rprev = f.Rtil;
+        // inner unpivoted QR steps R(i-1)^T = Q(i) R(i); R(1)^T = Rtil^T, Q(1) = Qt.
+        // Only transposed R factors are formed: the next step's input is R(i)^T.
+        double* RprevT = f.RtT;
         bool have_left = false, have_right = false;
         for (int i = 2; i <= d; ++i) {
-            RQLP_TRY(transpose_matrix(l, l, Rprev, l, f.Xi, l, 0, s));
+            RQLP_TRY(copy_matrix(l, l, RprevT, l, f.Xi, l, s));
             double* Qi = nullptr;
-            double* Rnew = (Rprev == f.Ri) ? f.Rtil : f.Ri;
-            RQLP_TRY(cholqr2(cx, l, l, f.Xi, f.Xi2, l, Rnew, &Qi));
+            double* RnewT = (RprevT == f.RiT) ? f.RtT : f.RiT;
+            RQLP_TRY(cholqr2(cx, l, l, f.Xi, f.Xi2, l, RnewT, &Qi));
             double*& Macc = (i % 2 == 0) ? f.Ml : f.Mr;
             bool& have = (i % 2 == 0) ? have_left : have_right;
             if (!have) {
                 RQLP_TRY(copy_matrix(l, l, Qi, l, Macc, l, s));
                 have = true;
             } else {
-                RQLP_TRY(gemm<double>(false, l, l, l, Macc, l, Qi, l, f.Mt, l, false, 1.0, 0.0, f.gws,
+                RQLP_TRY(gemm<double>(false, false, l, l, l, Macc, l, Qi, l, f.Mt, l, false, 1.0, 0.0, f.gws,
                                       f.gws_elems, s));
                 double* t = Macc;
                 Macc = f.Mt;
                 f.Mt = t;
             }
-            Rprev = Rnew;
+            RprevT = RnewT;
         }
         if (have_right)
-            RQLP_TRY(gemm<double>(false, n, l, l, Qt, n, f.Mr, l, (double*)P, ldp, false, 1.0, 0.0, f.gws,
+            RQLP_TRY(gemm<double>(false, false, n, l, l, Qt, n, f.Mr, l, (double*)P, ldp, false, 1.0, 0.0, f.gws,
                                   f.gws_elems, s));
         else
             RQLP_TRY(copy_matrix(n, l, Qt, n, (double*)P, ldp, s));
@@ -302,15 +302,14 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
         f.Ml = f.Xi;
         f.Xi = t;
         if (d % 2 == 1) {
-            RQLP_TRY(transpose_matrix(l, l, Rprev, l, T, ldt, 'L', s));
+            RQLP_TRY(copy_matrix(l, l, RprevT, l, T, ldt, s));                 // L = R(d)^T
         } else {
-            RQLP_TRY(transpose_matrix(l, l, Rprev, l, f.Mt, l, 'L', s));   // lower of R^T ...
-            RQLP_TRY(transpose_matrix(l, l, f.Mt, l, T, ldt, 'U', s));     // ... back to upper R
+            RQLP_TRY(transpose_matrix(l, l, RprevT, l, T, ldt, 'U', s));       // R(d) itself
             tri = 'U';
         }
     }
     // ---- assembly: Q = V (Q_B) ----
-    RQLP_TRY(gemm<double>(false, m, l, l, V, m, f.Ml, l, (double*)Q, ldq, false, 1.0, 0.0, f.gws, f.gws_elems, s));
+    RQLP_TRY(gemm<double>(false, false, m, l, l, V, m, f.Ml, l, (double*)Q, ldq, false, 1.0, 0.0, f.gws, f.gws_elems, s));
     RQLP_TRY(finish_lvals(l, T, ldt, lvals, inf, s));
     if (piv0) RQLP_TRY(copy_i64(l, f.piv0, piv0, s));
     if (piv1) RQLP_TRY(copy_i64(l, d == 0 ? f.piv1 : nullptr, piv1, s));
@@ -346,13 +345,13 @@ int rqlp_sketch(const void* A, int64_t lda, int64_t m, int64_t n, const void* X,
         size_t e = gemm_workspace_elems(m, c, n);
         double* ws = ar.take<double>(e);
         if (!ar.ok()) return RQLP_E_WORKSPACE;
-        return gemm<double>(false, m, c, n, (const double*)A, lda, (const double*)X, ldx, (double*)Y, ldy, false,
+        return gemm<double>(false, false, m, c, n, (const double*)A, lda, (const double*)X, ldx, (double*)Y, ldy, false,
                             1.0, 0.0, ws, e, s);
     }
     size_t e = gemm_workspace_elems(m, c, n);
     float* ws = ar.take<float>(e);
     if (!ar.ok()) return RQLP_E_WORKSPACE;
-    return gemm<float>(false, m, c, n, (const float*)A, lda, (const float*)X, ldx, (float*)Y, ldy, false, 1.0f,
+    return gemm<float>(false, false, m, c, n, (const float*)A, lda, (const float*)X, ldx, (float*)Y, ldy, false, 1.0f,
                        0.0f, ws, e, s);
 }
 
@@ -372,12 +371,12 @@ int rqlp_project(const void* A, int64_t lda, int64_t m, int64_t n, const void* V
     if (precision == RQLP_F64) {
         double* ws = ar.take<double>(e);
         if (!ar.ok()) return RQLP_E_WORKSPACE;
-        return gemm<double>(true, n, c, m, (const double*)A, lda, (const double*)V, ldv, (double*)B, ldb, true,
+        return gemm<double>(true, false, n, c, m, (const double*)A, lda, (const double*)V, ldv, (double*)B, ldb, true,
                             1.0, 0.0, ws, e, s);
     }
     float* ws = ar.take<float>(e);
     if (!ar.ok()) return RQLP_E_WORKSPACE;
-    return gemm<float>(true, n, c, m, (const float*)A, lda, (const float*)V, ldv, (float*)B, ldb, true, 1.0f, 0.0f,
+    return gemm<float>(true, false, n, c, m, (const float*)A, lda, (const float*)V, ldv, (float*)B, ldb, true, 1.0f, 0.0f,
                        ws, e, s);
 }
 
@@ -388,10 +387,11 @@ int rqlp_orthonormalize_workspace(int64_t m, int64_t c, size_t* bytes) {
     Arena ar(nullptr, 0);
     OrthoScratch o;
     carve_ortho(ar, c, &o);
-    ar.take<double>(gemm_workspace_elems(c, c, m) > gemm_workspace_elems(m, c, c)
-                        ? gemm_workspace_elems(c, c, m)
-                        : gemm_workspace_elems(m, c, c));
-    ar.take<double>(gemm_workspace_elems(c, c, c));
+    size_t e = gemm_workspace_elems(c, c, m);
+    if (gemm_workspace_elems(m, c, c) > e) e = gemm_workspace_elems(m, c, c);
+    if (gemm_workspace_elems(c, c, c) > e) e = gemm_workspace_elems(c, c, c);
+    ar.take<double>(e);
+    ar.take<double>(c * c);
     ar.take<double>(m * c);
     ar.take<double>(m * c);
     ar.take<int32_t>(1);
@@ -413,11 +413,10 @@ int rqlp_orthonormalize(const double* Y, int64_t ldy, int64_t m, int64_t c, doub
     OrthoScratch o;
     carve_ortho(ar, c, &o);
     size_t e = gemm_workspace_elems(c, c, m);
-    size_t e2 = gemm_workspace_elems(m, c, c);
-    if (e2 > e) e = e2;
+    if (gemm_workspace_elems(m, c, c) > e) e = gemm_workspace_elems(m, c, c);
+    if (gemm_workspace_elems(c, c, c) > e) e = gemm_workspace_elems(c, c, c);
     double* gws = ar.take<double>(e);
-    double* Rtmp = ar.take<double>(gemm_workspace_elems(c, c, c));
-    (void)Rtmp;
+    double* RT = ar.take<double>(c * c);
     double* b0 = ar.take<double>(m * c);
     double* b1 = ar.take<double>(m * c);
     int32_t* linfo = ar.take<int32_t>(1);
@@ -426,14 +425,9 @@ int rqlp_orthonormalize(const double* Y, int64_t ldy, int64_t m, int64_t c, doub
     RQLP_TRY(fill_zero_bytes(inf, sizeof(int32_t), s));
     RQLP_TRY(copy_matrix(m, c, Y, ldy, b0, m, s));
     Ctx cx{s, inf, gws, e, o};
-    if (R) {
-        // R product needs the GEMM workspace of a c x c x c product too
-        if (gemm_workspace_elems(c, c, c) > e) return RQLP_E_WORKSPACE;
-    }
     double* out = nullptr;
-    double* Rtmp2 = R ? o.G : nullptr;   // Gram buffer is free once both passes are done
-    RQLP_TRY(cholqr2(cx, m, c, b0, b1, m, Rtmp2, &out));
-    if (R) RQLP_TRY(copy_matrix(c, c, Rtmp2, c, R, ldr, s));
+    RQLP_TRY(cholqr2(cx, m, c, b0, b1, m, R ? RT : nullptr, &out));
+    if (R) RQLP_TRY(transpose_matrix(c, c, RT, c, R, ldr, 'U', s));
     return copy_matrix(m, c, out, m, V, ldv, s);
 }
 

@@ -5,20 +5,34 @@
 // Yamamoto 2020).
 //
 // One workgroup of 512 threads factors the c x c Gram matrix G = L L^T with a
-// right-looking blocked algorithm (32-column blocks) and, fused into the same
+// right-looking blocked algorithm (16-column blocks) and, fused into the same
 // sweep, solves L X = I for X = L^{-1} (right-looking block forward
-// substitution sharing the panel).  The 32 x 32 diagonal blocks are factored
-// by one wave in registers (lane i holds row i, columns broadcast by
-// shuffles).  The current panel L(J0:c, K0:K0+32) and block row X(K0:K0+32,
-// 0:J0) are cached in LDS (up to 256 rows / columns, the rest is read from
-// the L2-resident scratch copies), and the trailing updates run as 4 x 4
-// register tiles.
+// substitution sharing the panel).  Per block step:
+//   (1) the 16 x 16 diagonal block is factored and inverted by one wave in
+//       LDS (unblocked, wave-synchronous: no workgroup barrier per column);
+//   (3) the panel L(J0:c, K) = W(J0:c, K) L_KK^{-T} and the block row
+//       X(K, 0:J0) = L_KK^{-1} X(K, 0:J0), and
+//   (4) the trailing updates W -= L(:,K) L(:,K)^T and X -= L(:,K) X(K,:),
+//       all as 16 x 16 FP64 MFMA tiles distributed over the 8 waves, the
+//       panel and the block row read from LDS (up to 256 rows / columns
+//       cached; beyond that from the L2-resident scratch).
+// Loops are kept compact on purpose: fully unrolled triangular loops here
+// overflow the instruction cache and run several times slower.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace rqlp {
 
-constexpr int CH_NB = 32;
+// Orders LDS traffic between the lanes of one wave: DS instructions of a wave
+// execute in order, so only the compiler must be kept from reordering.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int CH_NB = 16;                 // block size (multiple of 16: one MFMA tile)
+constexpr int CH_NBT = CH_NB / 16;
 constexpr int CH_T = 512;
 constexpr int CH_PMAX = 256;
 constexpr int CH_XMAX = 256;
@@ -27,27 +41,30 @@ constexpr int CH_PS = CH_NB + 1;
 static inline int ch_prows(int64_t c) { return (int)(c < CH_PMAX ? c : CH_PMAX); }
 static inline int ch_xcols(int64_t c) { return (int)(c < CH_XMAX ? c : CH_XMAX); }
 
+// at least one block of panel rows is allocated
+static inline int ch_prows_alloc(int64_t c) { return ch_prows(c) > CH_NB ? ch_prows(c) : CH_NB; }
+
 size_t chol_inv_lds_bytes(int64_t c) {
-    return sizeof(double) * (size_t)(2 * CH_NB * CH_PS + ch_prows(c) * CH_PS + CH_NB * (ch_xcols(c) + 1));
+    return sizeof(double) *
+           (size_t)(2 * CH_NB * CH_PS + ch_prows_alloc(c) * CH_PS + CH_NB * (ch_xcols(c) + 1));
 }
 
 __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const double* __restrict__ G, int64_t ldg,
-                                                        double* __restrict__ R, int64_t ldr,
-                                                        double* __restrict__ Rinv, int64_t ldri,
                                                         double shift_scale, double* __restrict__ W,
                                                         double* __restrict__ X, int64_t ldw, int32_t* info,
                                                         int prows, int xcols) {
     extern __shared__ double lds[];
-    double* D = lds;                           // [32][33]
-    double* Dinv = D + CH_NB * CH_PS;          // [32][33]
-    double* P = Dinv + CH_NB * CH_PS;          // [prows][33]
-    double* XK = P + (size_t)prows * CH_PS;    // [32][xcols + 1]
+    double* D = lds;                           // [NB][NB+1] factored diagonal block
+    double* Dinv = D + CH_NB * CH_PS;          // [NB][NB+1] its inverse
+    double* P = Dinv + CH_NB * CH_PS;          // [prows][33] panel rows J0..
+    double* XK = P + (size_t)(prows > CH_NB ? prows : CH_NB) * CH_PS;   // [NB][xcols + 1] block row of X
     const int xs = xcols + 1;
     __shared__ int s_bad;
     __shared__ double s_red[CH_T / 64];
     __shared__ double s_trace;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NWAVE = CH_T / 64;
 
     // trace(G) for the shift
     {
@@ -58,7 +75,7 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const double* __r
         __syncthreads();
         if (tid == 0) {
             double s = 0.0;
-            for (int w = 0; w < CH_T / 64; ++w) s += s_red[w];
+            for (int w = 0; w < NWAVE; ++w) s += s_red[w];
             s_trace = s;
         }
         __syncthreads();
@@ -66,10 +83,11 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const double* __r
 
     for (int attempt = 0; attempt < 2; ++attempt) {
         const double shift = attempt == 0 ? 0.0 : shift_scale * s_trace;
-        for (int64_t idx = tid; idx < (int64_t)c * c; idx += CH_T) {
-            const int i = (int)(idx % c), j = (int)(idx / c);
-            if (i >= j) W[i + j * ldw] = G[i + j * ldg] + (i == j ? shift : 0.0);
-            X[i + j * ldw] = (i == j) ? 1.0 : 0.0;
+        for (int j = wave; j < c; j += NWAVE) {
+            for (int i = lane; i < c; i += 64) {
+                if (i >= j) W[i + (int64_t)j * ldw] = G[i + (int64_t)j * ldg] + (i == j ? shift : 0.0);
+                X[i + (int64_t)j * ldw] = (i == j) ? 1.0 : 0.0;
+            }
         }
         if (tid == 0) s_bad = 0;
         __syncthreads();
@@ -77,152 +95,178 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const double* __r
         for (int K0 = 0; K0 < c; K0 += CH_NB) {
             const int kb = (c - K0) < CH_NB ? (c - K0) : CH_NB;
             const int J0 = K0 + kb;
-            // (1) diagonal block -> D
+            // ---- (1) diagonal block factor and inverse: one wave, LDS-resident,
+            // wave-synchronous (DS operations of one wave complete in order) ----
             for (int idx = tid; idx < CH_NB * CH_NB; idx += CH_T) {
                 const int i = idx % CH_NB, j = idx / CH_NB;
                 D[i * CH_PS + j] = (i < kb && j < kb && i >= j) ? W[(K0 + i) + (int64_t)(K0 + j) * ldw] : 0.0;
+                Dinv[i * CH_PS + j] = (i == j && i < kb) ? 1.0 : 0.0;
             }
             __syncthreads();
-            // (2) one wave factors D in registers (lane i = row i)
             if (wave == 0) {
-                double d[CH_NB];
-#pragma unroll
-                for (int j = 0; j < CH_NB; ++j) d[j] = (lane < CH_NB) ? D[lane * CH_PS + j] : 0.0;
                 int bad = 0;
+                for (int j = 0; j < kb; ++j) {
+                    const double pj = D[j * CH_PS + j];
+                    const bool ok = (pj > 0.0) && (pj < 1.0e308);
+                    bad |= !ok;
+                    const double sj = ok ? sqrt(pj) : 1.0;
+                    wave_sync();
+                    if (lane == j) D[j * CH_PS + j] = sj;
+                    else if (lane > j && lane < kb) D[lane * CH_PS + j] /= sj;
+                    wave_sync();
+                    // all loads first, then the stores (loads may not pass stores)
+                    double u[CH_NB * CH_NB / 64];
 #pragma unroll
-                for (int j = 0; j < CH_NB; ++j) {
-                    if (j < kb) {
-                        const double pj = __shfl(d[j], j);
-                        const bool ok = (pj > 0.0) && (pj < 1.0e308);
-                        if (!ok) bad = 1;
-                        const double sj = ok ? sqrt(pj) : 1.0;
-                        if (lane == j) d[j] = sj;
-                        else if (lane > j) d[j] = d[j] / sj;
-#pragma unroll
-                        for (int jj = j + 1; jj < CH_NB; ++jj) {
-                            const double cj = __shfl(d[j], jj);
-                            if (lane >= jj) d[jj] -= d[j] * cj;
-                        }
+                    for (int e = 0; e < CH_NB * CH_NB / 64; ++e) {
+                        const int idx = lane + 64 * e;
+                        const int i = idx % CH_NB, jj = idx / CH_NB;
+                        u[e] = D[i * CH_PS + jj] - D[i * CH_PS + j] * D[jj * CH_PS + j];
                     }
-                }
-                if (lane < CH_NB) {
 #pragma unroll
-                    for (int j = 0; j < CH_NB; ++j) D[lane * CH_PS + j] = (j <= lane) ? d[j] : 0.0;
+                    for (int e = 0; e < CH_NB * CH_NB / 64; ++e) {
+                        const int idx = lane + 64 * e;
+                        const int i = idx % CH_NB, jj = idx / CH_NB;
+                        if (jj > j && i >= jj && i < kb) D[i * CH_PS + jj] = u[e];
+                    }
+                    wave_sync();
                 }
-                if (lane == 0 && bad) s_bad = 1;
+                for (int t = 0; t < kb; ++t) {
+                    const double rt = 1.0 / D[t * CH_PS + t];
+                    wave_sync();
+                    if (lane <= t) Dinv[t * CH_PS + lane] *= rt;
+                    wave_sync();
+                    double u[CH_NB * CH_NB / 64];
+#pragma unroll
+                    for (int e = 0; e < CH_NB * CH_NB / 64; ++e) {
+                        const int idx = lane + 64 * e;
+                        const int i = idx % CH_NB, jj = idx / CH_NB;
+                        u[e] = Dinv[i * CH_PS + jj] - D[i * CH_PS + t] * Dinv[t * CH_PS + jj];
+                    }
+#pragma unroll
+                    for (int e = 0; e < CH_NB * CH_NB / 64; ++e) {
+                        const int idx = lane + 64 * e;
+                        const int i = idx % CH_NB, jj = idx / CH_NB;
+                        if (i > t && i < kb && jj <= t) Dinv[i * CH_PS + jj] = u[e];
+                    }
+                    wave_sync();
+                }
+                if (lane == 0) s_bad = bad;
             }
             __syncthreads();
             if (s_bad) break;
-            // (3) Dinv = D^{-1} (lower); thread j < 32 solves column j in place in LDS
-            if (tid < CH_NB) {
-                const int j = tid;
-                for (int i = 0; i < CH_NB; ++i) {
-                    double s = (i == j) ? 1.0 : 0.0;
-                    for (int t = j; t < i; ++t) s -= D[i * CH_PS + t] * Dinv[t * CH_PS + j];
-                    Dinv[i * CH_PS + j] = (i >= j && i < kb) ? s / D[i * CH_PS + i] : 0.0;
-                }
-            }
-            for (int idx = tid; idx < kb * kb; idx += CH_T) {
-                const int i = idx % kb, j = idx / kb;
-                if (i >= j) W[(K0 + i) + (int64_t)(K0 + j) * ldw] = D[i * CH_PS + j];
+            // L_KK into W
+            for (int idx = tid; idx < CH_NB * CH_NB; idx += CH_T) {
+                const int i = idx % CH_NB, j = idx / CH_NB;
+                if (i < kb && j < kb && i >= j) W[(K0 + i) + (int64_t)(K0 + j) * ldw] = D[i * CH_PS + j];
             }
             __syncthreads();
-            // (4) panel rows i >= J0: L(i, K0:J0) = W(i, K0:J0) Dinv^T
-            for (int i = J0 + tid; i < c; i += CH_T) {
-                double w[CH_NB];
+            // MFMA fragment helpers (v_mfma_f64_16x16x4f64): lane l holds
+            // A(l % 16, k) and B(k, l % 16) with k = 4 ks + l / 16; accumulator
+            // element r of lane l is C(l / 16 + 4 r, l % 16).
+            const int fr = lane & 15, fk = lane >> 4;
+            // L(i, K0 + k) for i >= J0: from the LDS panel (zero-padded past c
+            // and kb) when all rows are cached, else from the scratch copy
+            const bool all_cached = (c - J0) <= prows - 16;
+            auto panel = [&](int i, int k) -> double {
+                double v = 0.0;
+                if (all_cached || (i < c && k < kb && i - J0 < prows)) {
+                    v = P[(i - J0) * CH_PS + k];
+                } else if (i < c && k < kb) {
+                    v = W[i + (int64_t)(K0 + k) * ldw];
+                }
+                return v;
+            };
+            // ---- (3a) panel L(J0:c, K) = W(J0:c, K) Dinv^T ----
+            {
+                const int nti = (c - J0 + 15) >> 4;
+                for (int tile = wave; tile < nti * CH_NBT; tile += NWAVE) {
+                    const int i0 = J0 + 16 * (tile / CH_NBT), s0 = 16 * (tile % CH_NBT);
+                    double4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int t = 0; t < CH_NB; ++t) w[t] = (t < kb) ? W[i + (int64_t)(K0 + t) * ldw] : 0.0;
-                for (int s = 0; s < kb; ++s) {
-                    double y = 0.0;
+                    for (int ks = 0; ks < CH_NB / 4; ++ks) {
+                        const int i = i0 + fr, k = 4 * ks + fk;
+                        const double a = (i < c && k < kb) ? W[i + (int64_t)(K0 + k) * ldw] : 0.0;
+                        const double bb = Dinv[(s0 + fr) * CH_PS + k];
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+                    }
+                    // all loads of W(i, K) by this wave are done before it writes L(i, K)
 #pragma unroll
-                    for (int t = 0; t < CH_NB; ++t) y += (t <= s) ? w[t] * Dinv[s * CH_PS + t] : 0.0;
-                    W[i + (int64_t)(K0 + s) * ldw] = y;
-                    if (i - J0 < prows) P[(i - J0) * CH_PS + s] = y;
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = i0 + fk + 4 * r, sx = s0 + fr;
+                        if (i < c && sx < kb) W[i + (int64_t)(K0 + sx) * ldw] = acc[r];
+                        if (i - J0 < prows) P[(i - J0) * CH_PS + sx] = (i < c && sx < kb) ? acc[r] : 0.0;
+                    }
                 }
             }
-            // (5) block row of the inverse: X(K0:J0, 0:J0) = Dinv X(K0:J0, 0:J0)
-            for (int j = tid; j < J0; j += CH_T) {
-                double xc[CH_NB];
+            // ---- (3b) block row of the inverse: X(K, 0:J0) = Dinv X(K, 0:J0) ----
+            {
+                const int ntj = (J0 + 15) >> 4;
+                for (int tile = wave; tile < ntj * CH_NBT; tile += NWAVE) {
+                    const int s0 = 16 * (tile % CH_NBT), j0 = 16 * (tile / CH_NBT);
+                    double4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int t = 0; t < CH_NB; ++t) xc[t] = (t < kb) ? X[(K0 + t) + (int64_t)j * ldw] : 0.0;
-                for (int s = 0; s < kb; ++s) {
-                    double y = 0.0;
+                    for (int ks = 0; ks < CH_NB / 4; ++ks) {
+                        const int k = 4 * ks + fk, j = j0 + fr;
+                        const double a = Dinv[(s0 + fr) * CH_PS + k];
+                        const double bb = (j < J0 && k < kb) ? X[(K0 + k) + (int64_t)j * ldw] : 0.0;
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+                    }
 #pragma unroll
-                    for (int t = 0; t < CH_NB; ++t) y += (t <= s) ? Dinv[s * CH_PS + t] * xc[t] : 0.0;
-                    X[(K0 + s) + (int64_t)j * ldw] = y;
-                    if (j < xcols) XK[s * xs + j] = y;
+                    for (int r = 0; r < 4; ++r) {
+                        const int sx = s0 + fk + 4 * r, j = j0 + fr;
+                        if (sx < kb && j < J0) X[(K0 + sx) + (int64_t)j * ldw] = acc[r];
+                        if (j < xcols) XK[sx * xs + j] = (sx < kb && j < J0) ? acc[r] : 0.0;
+                    }
                 }
             }
             __syncthreads();
             if (J0 >= c) break;
-            // (6a) trailing update W(i, j) -= L(i, K) L(j, K)^T, J0 <= j <= i < c
+            // ---- (4a) trailing update W(i, j) -= L(i, K) L(j, K)^T, J0 <= j <= i < c ----
             {
-                const int nt = (c - J0 + 3) / 4;
-                const int64_t T = (int64_t)nt * (nt + 1) / 2;
-                for (int64_t idx = tid; idx < T; idx += CH_T) {
-                    int ti = (int)((sqrt(8.0 * (double)idx + 1.0) - 1.0) * 0.5);
-                    while ((int64_t)ti * (ti + 1) / 2 > idx) --ti;
-                    while ((int64_t)(ti + 1) * (ti + 2) / 2 <= idx) ++ti;
-                    const int tj = (int)(idx - (int64_t)ti * (ti + 1) / 2);
-                    const int i0 = J0 + 4 * ti, j0 = J0 + 4 * tj;
-                    double acc[4][4] = {};
-                    for (int s = 0; s < kb; ++s) {
-                        double a[4], b[4];
+                const int nt = (c - J0 + 15) >> 4;
+                const int T = nt * (nt + 1) / 2;
+                for (int idx = wave; idx < T; idx += NWAVE) {
+                    int ti = (int)((sqrtf(8.0f * (float)idx + 1.0f) - 1.0f) * 0.5f);
+                    while (ti * (ti + 1) / 2 > idx) --ti;
+                    while ((ti + 1) * (ti + 2) / 2 <= idx) ++ti;
+                    const int tj = idx - ti * (ti + 1) / 2;
+                    const int i0 = J0 + 16 * ti, j0 = J0 + 16 * tj;
+                    double4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int i = i0 + r, j = j0 + r;
-                            a[r] = (i < c) ? ((i - J0 < prows) ? P[(i - J0) * CH_PS + s]
-                                                               : W[i + (int64_t)(K0 + s) * ldw])
-                                           : 0.0;
-                            b[r] = (j < c) ? ((j - J0 < prows) ? P[(j - J0) * CH_PS + s]
-                                                               : W[j + (int64_t)(K0 + s) * ldw])
-                                           : 0.0;
-                        }
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) acc[r][q] += a[r] * b[q];
+                    for (int ks = 0; ks < CH_NB / 4; ++ks) {
+                        const int k = 4 * ks + fk;
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(panel(i0 + fr, k), panel(j0 + fr, k), acc,
+                                                                   0, 0, 0);
                     }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int i = i0 + r, j = j0 + q;
-                            if (i < c && j < c && i >= j) W[i + (int64_t)j * ldw] -= acc[r][q];
-                        }
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = i0 + fk + 4 * r, j = j0 + fr;
+                        if (i < c && j < c && i >= j) W[i + (int64_t)j * ldw] -= acc[r];
+                    }
                 }
             }
-            // (6b) inverse update X(i, j) -= L(i, K) X(K, j), i >= J0, j < J0
+            // ---- (4b) inverse update X(i, j) -= L(i, K) X(K, j), i >= J0, j < J0 ----
             {
-                const int nti = (c - J0 + 3) / 4, ntj = (J0 + 3) / 4;
-                const int64_t T = (int64_t)nti * ntj;
-                for (int64_t idx = tid; idx < T; idx += CH_T) {
-                    const int ti = (int)(idx / ntj), tj = (int)(idx % ntj);
-                    const int i0 = J0 + 4 * ti, j0 = 4 * tj;
-                    double acc[4][4] = {};
-                    for (int s = 0; s < kb; ++s) {
-                        double a[4], b[4];
+                const int nti = (c - J0 + 15) >> 4, ntj = (J0 + 15) >> 4;
+                for (int idx = wave; idx < nti * ntj; idx += NWAVE) {
+                    const int ti = idx / ntj, tj = idx - (idx / ntj) * ntj;
+                    const int i0 = J0 + 16 * ti, j0 = 16 * tj;
+                    double4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int i = i0 + r, j = j0 + r;
-                            a[r] = (i < c) ? ((i - J0 < prows) ? P[(i - J0) * CH_PS + s]
-                                                               : W[i + (int64_t)(K0 + s) * ldw])
-                                           : 0.0;
-                            b[r] = (j < J0) ? ((j < xcols) ? XK[s * xs + j] : X[(K0 + s) + (int64_t)j * ldw])
-                                            : 0.0;
+                    for (int ks = 0; ks < CH_NB / 4; ++ks) {
+                        const int k = 4 * ks + fk, j = j0 + fr;
+                        double bb = 0.0;
+                        if (j < J0 && k < kb) {
+                            if (j < xcols) bb = XK[k * xs + j];
+                            else bb = X[(K0 + k) + (int64_t)j * ldw];
                         }
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-#pragma unroll
-                            for (int q = 0; q < 4; ++q) acc[r][q] += a[r] * b[q];
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(panel(i0 + fr, k), bb, acc, 0, 0, 0);
                     }
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int i = i0 + r, j = j0 + q;
-                            if (i < c && j < J0) X[i + (int64_t)j * ldw] -= acc[r][q];
-                        }
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = i0 + fk + 4 * r, j = j0 + fr;
+                        if (i < c && j < J0) X[i + (int64_t)j * ldw] -= acc[r];
+                    }
                 }
             }
             __syncthreads();
@@ -230,19 +274,16 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const double* __r
         if (!s_bad) break;
         if (tid == 0 && info) atomicOr(info, attempt == 0 ? RQLP_INFO_CHOLQR_SHIFTED : RQLP_INFO_CHOL_FAILED);
         __syncthreads();
-        if (attempt == 1) break;
     }
     __syncthreads();
-    // outputs: R = L^T, Rinv = X^T (upper triangular, zero below)
-    for (int64_t idx = tid; idx < (int64_t)c * c; idx += CH_T) {
-        const int i = (int)(idx % c), j = (int)(idx / c);   // output element (i, j)
-        if (R) R[i + j * ldr] = (i <= j) ? W[j + (int64_t)i * ldw] : 0.0;
-        if (Rinv) Rinv[i + j * ldri] = (i <= j) ? X[j + (int64_t)i * ldw] : 0.0;
-    }
+    // outputs are the working buffers themselves: W holds L (lower), X holds
+    // L^{-1} (lower; its strictly upper part is zero); zero W's upper part.
+    for (int j = wave; j < c; j += NWAVE)
+        for (int i = lane; i < j; i += 64) W[i + (int64_t)j * ldw] = 0.0;
 }
 
-int chol_inv(int64_t c, const double* G, int64_t ldg, double* R, int64_t ldr, double* Rinv, int64_t ldri,
-             double shift_scale, double* W1, double* W2, int32_t* info, hipStream_t s) {
+int chol_inv(int64_t c, const double* G, int64_t ldg, double* L, double* Linv, int64_t ld, double shift_scale,
+             int32_t* info, hipStream_t s) {
     if (c <= 0) return 0;
     const size_t lds = chol_inv_lds_bytes(c);
     static bool attr_set = false;
@@ -252,8 +293,8 @@ int chol_inv(int64_t c, const double* G, int64_t ldg, double* R, int64_t ldr, do
                                          (int)chol_inv_lds_bytes(1 << 20)));
         attr_set = true;
     }
-    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(CH_T), lds, s, (int)c, G, ldg, R, ldr, Rinv, ldri,
-                       shift_scale, W1, W2, c, info, ch_prows(c), ch_xcols(c));
+    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(CH_T), lds, s, (int)c, G, ldg, shift_scale, L, Linv, ld,
+                       info, ch_prows(c), ch_xcols(c));
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 

@@ -93,13 +93,16 @@ __device__ __forceinline__ double key_value(unsigned long long key, int ibits) {
 __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, unsigned& gen,
                                              int32_t* info, unsigned long long spin_limit) {
     __shared__ int s_ok;
-    __threadfence();
+    // the workgroup barrier orders this workgroup's global stores before thread
+    // 0's device-scope release below; thread 0's acquire plus the second
+    // workgroup barrier order every thread's later loads after the other
+    // workgroups' releases.
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
         unsigned g = gen;
-        unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (arrived == nblocks - 1) {
             __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -111,14 +114,14 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, un
                     if (info) atomicOr(info, RQLP_INFO_BARRIER_TIMEOUT);
                     break;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(1);
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         gen = g + 1u;
         s_ok = ok;
     }
     __syncthreads();
-    __threadfence();
     return s_ok != 0;
 }
 

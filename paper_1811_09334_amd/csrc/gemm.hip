@@ -2,7 +2,7 @@
 //   Y = A * X          (sketch, Algorithm 2.1 step 2; subspace iteration)
 //   Z = A^T * V        (subspace iteration; B^T = A^T V, Algorithm 2.1 step 4)
 //   G = X^T * X        (Gram matrix of CholeskyQR)
-//   Y = X * Rinv       (CholeskyQR update, assembly Q = V Q_B)
+//   Y = X * L^{-T}     (CholeskyQR update, B transposed), Q = V Q_B (assembly)
 // in FP64 or FP32 on the gfx950 matrix cores (v_mfma_f64_16x16x4f64 /
 // v_mfma_f32_16x16x4f32), FP accumulation in the input precision.
 //
@@ -50,7 +50,7 @@ struct Mfma<float> {
 constexpr int GEMM_BK = 32;
 constexpr int GEMM_THREADS = 256;
 
-template <typename T, bool TA, int MB, int NB>
+template <typename T, bool TA, bool TB, int MB, int NB>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
     int64_t M, int64_t N, int64_t K, const T* __restrict__ A, int64_t lda,
     const T* __restrict__ B, int64_t ldb, T* __restrict__ C, int64_t ldc, int64_t split_stride,
@@ -106,11 +106,23 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
                 ra[r] = (i < M && k < kend) ? A[k + i * lda] : T(0);
             }
         }
+        if (!TB) {
+            // op(B) = B (K x N): k = tid % 32, j = tid / 32 + 8 r
 #pragma unroll
-        for (int r = 0; r < B_PER_T; ++r) {
-            int64_t k = kt + (tid & 31);
-            int64_t j = n0 + (tid >> 5) + 8 * r;
-            rb[r] = (j < N && k < kend) ? B[k + j * ldb] : T(0);
+            for (int r = 0; r < B_PER_T; ++r) {
+                int64_t k = kt + (tid & 31);
+                int64_t j = n0 + (tid >> 5) + 8 * r;
+                rb[r] = (j < N && k < kend) ? B[k + j * ldb] : T(0);
+            }
+        } else {
+            // op(B) = B^T, B stored N x K: consecutive threads run along j
+#pragma unroll
+            for (int r = 0; r < B_PER_T; ++r) {
+                const int e = tid + GEMM_THREADS * r;
+                int64_t j = n0 + e % BN;
+                int64_t k = kt + e / BN;
+                rb[r] = (j < N && k < kend) ? B[j + k * ldb] : T(0);
+            }
         }
     };
     auto store_tile = [&]() {
@@ -124,8 +136,16 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
 #pragma unroll
             for (int r = 0; r < A_PER_T; ++r) As[((tid >> 5) + 8 * r) * SA + (tid & 31)] = ra[r];
         }
+        if (!TB) {
 #pragma unroll
-        for (int r = 0; r < B_PER_T; ++r) Bs[((tid >> 5) + 8 * r) * SB + (tid & 31)] = rb[r];
+            for (int r = 0; r < B_PER_T; ++r) Bs[((tid >> 5) + 8 * r) * SB + (tid & 31)] = rb[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < B_PER_T; ++r) {
+                const int e = tid + GEMM_THREADS * r;
+                Bs[(e % BN) * SB + e / BN] = rb[r];
+            }
+        }
     };
 
     if (kbeg < kend) load_tile(kbeg);
@@ -239,20 +259,20 @@ GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K) {
     return p;
 }
 
-template <typename T, bool TA, int NB>
+template <typename T, bool TA, bool TB, int NB>
 void launch_nb(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda,
                const T* B, int64_t ldb, T* C, int64_t ldc, int64_t split_stride, hipStream_t s) {
     dim3 grid((unsigned)p.tm, (unsigned)p.tn, (unsigned)p.S);
-    hipLaunchKernelGGL((gemm_skinny_kernel<T, TA, 1, NB>), grid, dim3(GEMM_THREADS), 0, s, M, N, K, A,
+    hipLaunchKernelGGL((gemm_skinny_kernel<T, TA, TB, 1, NB>), grid, dim3(GEMM_THREADS), 0, s, M, N, K, A,
                        lda, B, ldb, C, ldc, split_stride, p.kchunk);
 }
 
-template <typename T, bool TA>
+template <typename T, bool TA, bool TB>
 void launch_dispatch(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda,
                      const T* B, int64_t ldb, T* C, int64_t ldc, int64_t split_stride, hipStream_t s) {
     switch (p.nb) {
 #define RQLP_NB_CASE(X) \
-    case X: launch_nb<T, TA, X>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, s); break;
+    case X: launch_nb<T, TA, TB, X>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, s); break;
         RQLP_NB_CASE(1) RQLP_NB_CASE(2) RQLP_NB_CASE(3) RQLP_NB_CASE(4)
         RQLP_NB_CASE(5) RQLP_NB_CASE(6) RQLP_NB_CASE(7) RQLP_NB_CASE(8)
         RQLP_NB_CASE(9) RQLP_NB_CASE(10) RQLP_NB_CASE(11) RQLP_NB_CASE(12)
@@ -269,19 +289,28 @@ size_t gemm_workspace_elems(int64_t M, int64_t N, int64_t K) {
 }
 
 template <typename T>
-int gemm(bool ta, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64_t ldb,
+static void launch_any(bool ta, bool tb, const GemmPlan& p, int64_t M, int64_t N, int64_t K, const T* A,
+                       int64_t lda, const T* B, int64_t ldb, T* C, int64_t ldc, int64_t split_stride,
+                       hipStream_t s) {
+    if (ta && tb) return;   // not needed by the method
+    if (ta) launch_dispatch<T, true, false>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, s);
+    else if (tb) launch_dispatch<T, false, true>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, s);
+    else launch_dispatch<T, false, false>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, s);
+}
+
+template <typename T>
+int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64_t ldb,
          T* C, int64_t ldc, bool trans_out, T alpha, T beta, T* ws, size_t ws_elems, hipStream_t s) {
+    if (ta && tb) return RQLP_E_UNSUPPORTED;
     if (M <= 0 || N <= 0) return 0;
     GemmPlan p = plan_gemm(M, N, K);
     const bool direct = (p.S == 1 && !trans_out && alpha == T(1) && beta == T(0));
     if (direct) {
-        if (ta) launch_dispatch<T, true>(p, M, N, K, A, lda, B, ldb, C, ldc, 0, s);
-        else launch_dispatch<T, false>(p, M, N, K, A, lda, B, ldb, C, ldc, 0, s);
+        launch_any<T>(ta, tb, p, M, N, K, A, lda, B, ldb, C, ldc, 0, s);
         return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
     }
     if ((size_t)(p.S * M * N) > ws_elems || ws == nullptr) return RQLP_E_WORKSPACE;
-    if (ta) launch_dispatch<T, true>(p, M, N, K, A, lda, B, ldb, ws, M, M * N, s);
-    else launch_dispatch<T, false>(p, M, N, K, A, lda, B, ldb, ws, M, M * N, s);
+    launch_any<T>(ta, tb, p, M, N, K, A, lda, B, ldb, ws, M, M * N, s);
     dim3 grid((unsigned)ceil_div(M, 32), (unsigned)ceil_div(N, 32));
     if (trans_out)
         hipLaunchKernelGGL((splitk_reduce_kernel<T, true>), grid, dim3(256), 0, s, M, N, ws, M, M * N,
@@ -292,9 +321,9 @@ int gemm(bool ta, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, cons
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 
-template int gemm<double>(bool, int64_t, int64_t, int64_t, const double*, int64_t, const double*, int64_t,
+template int gemm<double>(bool, bool, int64_t, int64_t, int64_t, const double*, int64_t, const double*, int64_t,
                           double*, int64_t, bool, double, double, double*, size_t, hipStream_t);
-template int gemm<float>(bool, int64_t, int64_t, int64_t, const float*, int64_t, const float*, int64_t,
+template int gemm<float>(bool, bool, int64_t, int64_t, int64_t, const float*, int64_t, const float*, int64_t,
                          float*, int64_t, bool, float, float, float*, size_t, hipStream_t);
 
 }  // namespace rqlp

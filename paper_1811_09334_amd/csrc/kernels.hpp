@@ -6,24 +6,25 @@
 namespace rqlp {
 
 // --- gemm.hip ---------------------------------------------------------------
-// C = alpha * op(A) * B + beta * C, op(A) = A (ta = false, A is M x K) or
-// A^T (ta = true, A is K x M); B is K x N; C is M x N, or N x M when
-// trans_out (C = (op(A) B)^T).  ws must hold gemm_workspace_elems(M, N, K)
+// C = alpha * op(A) * op(B) + beta * C, op(A) = A (ta = false, A is M x K)
+// or A^T (ta = true, A is K x M); op(B) = B (tb = false, B is K x N) or B^T
+// (tb = true, B is N x K; not combined with ta); C is M x N, or N x M when
+// trans_out (C = (op(A) op(B))^T).  ws must hold gemm_workspace_elems(M, N, K)
 // elements unless the product goes straight to C.
 size_t gemm_workspace_elems(int64_t M, int64_t N, int64_t K);
 template <typename T>
-int gemm(bool ta, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64_t ldb,
+int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64_t ldb,
          T* C, int64_t ldc, bool trans_out, T alpha, T beta, T* ws, size_t ws_elems, hipStream_t s);
 
 // --- chol.hip ---------------------------------------------------------------
 // Cholesky G = L L^T of the c x c Gram matrix (lower triangle read) and the
 // inverse of L, in one workgroup.  On breakdown the factorisation restarts
-// from G + shift * trace(G) * I (RQLP_INFO_CHOLQR_SHIFTED).  Outputs (any may
-// be NULL): R = L^T (upper), Rinv = L^{-T} (upper); strictly lower parts are
-// written as zero.  W1, W2: c x c scratch (ld = c).
+// from G + shift_scale * trace(G) * I (RQLP_INFO_CHOLQR_SHIFTED).  Outputs:
+// L and Linv (c x c lower triangular, leading dimension ld, zero above the
+// diagonal); both are also the kernel's working storage.
 size_t chol_inv_lds_bytes(int64_t c);
-int chol_inv(int64_t c, const double* G, int64_t ldg, double* R, int64_t ldr, double* Rinv,
-             int64_t ldri, double shift_scale, double* W1, double* W2, int32_t* info, hipStream_t s);
+int chol_inv(int64_t c, const double* G, int64_t ldg, double* L, double* Linv, int64_t ld, double shift_scale,
+             int32_t* info, hipStream_t s);
 
 // --- cpqr.hip ---------------------------------------------------------------
 struct CpqrScratch {
