@@ -9,10 +9,13 @@
 //   1. each workgroup finds its best active column (largest residual norm,
 //      ties -> smallest index) and publishes it: a 64-bit key (norm^2 with the
 //      low mantissa bits replaced by the complemented column index) goes into
-//      a device-wide atomic max, and the column itself into a double-buffered
-//      exchange slot;
-//   2. one grid barrier;
-//   3. every workgroup reads the winning key and column, builds the same
+//      an atomic max of its group of 16 workgroups (forwarded to a top slot by
+//      the group's last arriver), and the column itself into a
+//      double-buffered exchange slot;
+//   2. one two-level grid barrier (relaxed device-scope atomics only, see
+//      below), whose last arriver reads the winning key and publishes the
+//      decision inside the barrier's generation word;
+//   3. every workgroup reads the winning column, builds the same
 //      Householder reflector redundantly (bitwise identical, fixed reduction
 //      order), applies it to its own active columns and recomputes their
 //      residual norms exactly from LDS.
@@ -36,6 +39,114 @@ __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v,
     lo = __shfl_xor(lo, m, RQLP_WAVE);
     hi = __shfl_xor(hi, m, RQLP_WAVE);
     return ((unsigned long long)hi << 32) | lo;
+}
+
+// Cross-workgroup traffic of the CPQR uses only relaxed device-scope atomic
+// loads and stores (coherent at the memory side, they bypass the per-XCD L2
+// caches) plus completion waits for ordering: a workgroup's data stores are
+// waited for (s_waitcnt) before the barrier arrival is issued, and readers
+// issue their loads after they observed the barrier release.  This avoids
+// device-scope release/acquire fences, which write back and invalidate the
+// whole L2 once per workgroup and step.
+__device__ __forceinline__ void st_coherent(double* p, double v) {
+    __hip_atomic_store((unsigned long long*)p, (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coherent(const double* p) {
+    return __longlong_as_double(
+        (long long)__hip_atomic_load((unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+// every wave waits for its outstanding memory operations, then workgroup barrier
+__device__ __forceinline__ void drain_and_sync() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// Two-level grid barrier: workgroups arrive on the counter of their group of
+// 16 (each counter on its own 128-byte line), the last of a group forwards
+// the group's pivot keys to the top slot and arrives on the top counter, and
+// the very last arriver evaluates `decide()` and publishes its 32-bit result
+// together with the new generation in one 64-bit word, which the others poll.
+// Every wait is bounded by spin_limit polls (RQLP_INFO_BARRIER_TIMEOUT,
+// returns false).
+constexpr int CP_GROUP = 16;
+__host__ __device__ constexpr int cp_bar_words(int G) { return 32 * ((G + CP_GROUP - 1) / CP_GROUP + 2); }
+// Key slots of one step: (groups + 1) slots of 16 u64 (one 128-byte line
+// each); slot[0] is the max-by-norm key, slot[1] the max-by-index key.
+__host__ __device__ constexpr int cp_key_words(int G) { return 16 * ((G + CP_GROUP - 1) / CP_GROUP + 1); }
+
+template <typename F>
+__device__ __forceinline__ bool grid_sync_decide(unsigned* bar, int G, unsigned& gen, unsigned& payload,
+                                                 int32_t* info, unsigned long long spin_limit,
+                                                 unsigned long long* kslots, unsigned long long lk0,
+                                                 unsigned long long lk1, F decide) {
+    __shared__ int s_ok;
+    __shared__ unsigned s_pay;
+    drain_and_sync();
+    if (threadIdx.x == 0) {
+        const int ng = (G + CP_GROUP - 1) / CP_GROUP;
+        const int grp = (int)blockIdx.x / CP_GROUP;
+        const int gsz = (G - grp * CP_GROUP) < CP_GROUP ? (G - grp * CP_GROUP) : CP_GROUP;
+        unsigned* cnt = bar + 32 * grp;
+        unsigned* top = bar + 32 * ng;
+        unsigned long long* gw = (unsigned long long*)(bar + 32 * (ng + 1));
+        const unsigned g = gen;
+        int ok = 1;
+        unsigned pay = 0;
+        bool last = false;
+        if (kslots && lk0 != 0) {
+            atomicMax(kslots + 16 * grp, lk0);
+            atomicMax(kslots + 16 * grp + 1, lk1);
+            __builtin_amdgcn_s_waitcnt(0);
+        }
+        if (__hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)gsz - 1u) {
+            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (kslots) {
+                // forward this group's maxima to the top slot
+                const unsigned long long g0 =
+                    __hip_atomic_load(kslots + 16 * grp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long g1 =
+                    __hip_atomic_load(kslots + 16 * grp + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (g0 != 0) {
+                    atomicMax(kslots + 16 * ng, g0);
+                    atomicMax(kslots + 16 * ng + 1, g1);
+                }
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            if (__hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)ng - 1u) {
+                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                last = true;
+            }
+        }
+        if (last) {
+            pay = decide();
+            __builtin_amdgcn_s_waitcnt(0);
+            __hip_atomic_store(gw, ((unsigned long long)(g + 1u) << 32) | pay, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned long long spins = 0;
+            while (true) {
+                const unsigned long long w = __hip_atomic_load(gw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((unsigned)(w >> 32) != g) {
+                    pay = (unsigned)w;
+                    break;
+                }
+                if (++spins > spin_limit) {
+                    ok = 0;
+                    if (info) atomicOr(info, RQLP_INFO_BARRIER_TIMEOUT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        gen = g + 1u;
+        s_ok = ok;
+        s_pay = pay;
+    }
+    __syncthreads();
+    payload = s_pay;
+    return s_ok != 0;
 }
 
 template <bool SINGLE>
@@ -83,14 +194,16 @@ __global__ __launch_bounds__(CP_T) void cpqr_kernel(
     if (tid == 0) {
         double f = 0.0;
         for (int c = 0; c < ncol; ++c) f += nrm2[c];
-        if (!SINGLE) partial[g] = f;
+        if (!SINGLE) st_coherent(partial + g, f);
         s_tol2 = f;
     }
     if (!SINGLE) {
-        if (!grid_barrier(bar, G, gen, info, spin_limit)) return;
+        unsigned pay;
+        if (!grid_sync_decide(bar, G, gen, pay, info, spin_limit, nullptr, 0ull, 0ull, []() { return 0u; }))
+            return;
         if (tid == 0) {
             double f = 0.0;
-            for (int h = 0; h < G; ++h) f += partial[h];
+            for (int h = 0; h < G; ++h) f += ld_coherent(partial + h);
             s_tol2 = f;
         }
     }
@@ -100,6 +213,9 @@ __global__ __launch_bounds__(CP_T) void cpqr_kernel(
         s_stop = 0;
         s_rank = kmax;
     }
+    // threads per column in the update: a power of two up to 16
+    int tpc = 1;
+    while (tpc < 16 && tpc * 2 * cpw <= CP_T) tpc *= 2;
     __syncthreads();
 
     for (int j = 0; j < kmax; ++j) {
@@ -134,64 +250,76 @@ __global__ __launch_bounds__(CP_T) void cpqr_kernel(
             s_key[1] = b;
         }
         __syncthreads();
-        unsigned long long best0 = s_key[0], best1 = s_key[1];
-        if (!SINGLE) {
-            if (best0 != 0 && !stopped) {
-                const int bc = (int)key_index(best0, ibits) - c0;
-                double* slot = candcol + ((size_t)(j & 1) * G + g) * rows;
-                for (int i = j + tid; i < rows; i += CP_T) slot[i] = colv[bc * ldl + i];
-            }
-            if (tid == 0 && best0 != 0) {
-                atomicMax(&keys[2 * j], best0);
-                atomicMax(&keys[2 * j + 1], best1);
-            }
-            if (!grid_barrier(bar, G, gen, info, spin_limit)) return;
-            best0 = __hip_atomic_load(&keys[2 * j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            best1 = __hip_atomic_load(&keys[2 * j + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        // ---- 2. decide the pivot ----
-        int now_stopped = stopped;
-        if (!stopped && !(key_value(best0, ibits) > s_tol2)) {
-            const double kv = key_value(best0, ibits);
-            if (kv == kv) now_stopped = 1;   // NaN norms never trigger the stop
-        }
-        const unsigned long long best = now_stopped ? best1 : best0;
-        const int gidx = (int)key_index(best, ibits);
-        const int owner = gidx / cpw;
-        // ---- 3. reflector ----
-        if (!now_stopped) {
+        // ---- 2. agree on the pivot (the last arriver decides) ----
+        unsigned pay = 0;
+        {
+            const unsigned long long lk0 = s_key[0], lk1 = s_key[1];
+            const double tol2 = s_tol2;
+            auto decide = [&](unsigned long long k0g, unsigned long long k1g) -> unsigned {
+                unsigned stopnow = 0;
+                if (!stopped) {
+                    const double kv = key_value(k0g, ibits);
+                    if (!(kv > tol2) && kv == kv) stopnow = 1;   // NaN norms never trigger the stop
+                }
+                const unsigned win = (stopped || stopnow) ? key_index(k1g, ibits) : key_index(k0g, ibits);
+                return win | (stopnow << 31);
+            };
             if (SINGLE) {
-                for (int i = j + tid; i < rows; i += CP_T) v[i] = colv[(gidx - c0) * ldl + i];
+                if (tid == 0) s_red[0] = __longlong_as_double((long long)decide(lk0, lk1));
+                __syncthreads();
+                pay = (unsigned)__double_as_longlong(s_red[0]);
+                __syncthreads();
             } else {
-                const double* slot = candcol + ((size_t)(j & 1) * G + owner) * rows;
-                for (int i = j + tid; i < rows; i += CP_T) v[i] = slot[i];
+                if (lk0 != 0 && !stopped) {
+                    const int bc = (int)key_index(lk0, ibits) - c0;
+                    double* slot = candcol + ((size_t)(j & 1) * G + g) * rows;
+                    for (int i = j + tid; i < rows; i += CP_T) st_coherent(slot + i, colv[bc * ldl + i]);
+                }
+                unsigned long long* ks = keys + (size_t)j * cp_key_words(G);
+                unsigned long long* top = ks + 16 * ((G + CP_GROUP - 1) / CP_GROUP);
+                if (!grid_sync_decide(bar, G, gen, pay, info, spin_limit, ks, lk0, lk1, [&]() {
+                        return decide(__hip_atomic_load(top, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                                      __hip_atomic_load(top + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    }))
+                    return;
             }
-            __syncthreads();
-            double s = 0.0;
-            for (int i = j + 1 + tid; i < rows; i += CP_T) s += v[i] * v[i];
-            s = wave_sum(s);
-            if (lane == 0) s_red[wave] = s;
+        }
+        const int now_stopped = stopped | (int)(pay >> 31);
+        const int gidx = (int)(pay & 0x7FFFFFFFu);
+        const int owner = gidx / cpw;
+        // ---- 3. reflector (Parlett's form, R(j, j) = ||x|| >= 0) ----
+        if (!now_stopped) {
+            const double* src = SINGLE ? (colv + (gidx - c0) * ldl)
+                                       : (candcol + ((size_t)(j & 1) * G + owner) * rows);
+            double sg = 0.0;
+            for (int i = j + tid; i < rows; i += CP_T) {
+                const double x = SINGLE ? src[i] : ld_coherent(src + i);
+                v[i] = x;
+                if (i > j) sg += x * x;
+            }
+            sg = wave_sum(sg);
+            if (lane == 0) s_red[wave] = sg;
             __syncthreads();
             if (tid == 0) {
                 double sigma = 0.0;
                 for (int w = 0; w < CP_T / 64; ++w) sigma += s_red[w];
                 const double x0 = v[j];
                 const double mu = sqrt(x0 * x0 + sigma);
-                double v0, b;
+                double v0, bb;
                 if (sigma == 0.0) {
                     v0 = 1.0;
-                    b = (x0 >= 0.0) ? 0.0 : 2.0;
+                    bb = (x0 >= 0.0) ? 0.0 : 2.0;
                 } else {
                     v0 = (x0 <= 0.0) ? (x0 - mu) : (-sigma / (x0 + mu));
-                    b = 2.0 * v0 * v0 / (sigma + v0 * v0);
+                    bb = 2.0 * v0 * v0 / (sigma + v0 * v0);
                 }
-                s_beta = b;
+                s_beta = bb;
                 s_mu = mu;
-                s_red[0] = v0;
+                s_red[0] = (sigma == 0.0) ? 0.0 : 1.0 / v0;
             }
             __syncthreads();
-            const double v0 = s_red[0];
-            for (int i = j + 1 + tid; i < rows; i += CP_T) v[i] = (s_beta == 0.0) ? 0.0 : v[i] / v0;
+            const double rv0 = s_red[0];
+            for (int i = j + 1 + tid; i < rows; i += CP_T) v[i] *= rv0;
             if (tid == 0) v[j] = 1.0;
         } else {
             if (tid == 0) {
@@ -226,24 +354,38 @@ __global__ __launch_bounds__(CP_T) void cpqr_kernel(
         __syncthreads();
         // ---- 5. apply H = I - b v v^T to the active local columns, exact norms ----
         if (!now_stopped) {
-            for (int c = tid >> 2; c < ncol; c += CP_T / 4) {
-                if (act[c] >= 0) continue;
-                const int qd = tid & 3;
+            const int qd = tid & (tpc - 1);
+            for (int c = tid / tpc; c < ncol; c += CP_T / tpc) {
+                if (act[c] >= 0) continue;   // whole group of tpc lanes skips together
                 double* col = colv + c * ldl;
-                double dot = 0.0;
-                for (int i = j + qd; i < rows; i += 4) dot += v[i] * col[i];
-                dot += __shfl_xor(dot, 1, RQLP_WAVE);
-                dot += __shfl_xor(dot, 2, RQLP_WAVE);
+                double d0 = 0.0, d1 = 0.0;
+                int i = j + qd;
+                for (; i + tpc < rows; i += 2 * tpc) {
+                    d0 += v[i] * col[i];
+                    d1 += v[i + tpc] * col[i + tpc];
+                }
+                if (i < rows) d0 += v[i] * col[i];
+                double dot = d0 + d1;
+                for (int off = tpc >> 1; off > 0; off >>= 1) dot += __shfl_xor(dot, off, RQLP_WAVE);
                 const double w = b * dot;
-                double s = 0.0;
-                for (int i = j + qd; i < rows; i += 4) {
+                double s0 = 0.0, s1 = 0.0;
+                i = j + qd;
+                for (; i + tpc < rows; i += 2 * tpc) {
+                    const double x = col[i] - w * v[i];
+                    const double y = col[i + tpc] - w * v[i + tpc];
+                    col[i] = x;
+                    col[i + tpc] = y;
+                    s0 += (i > j) ? x * x : 0.0;
+                    s1 += y * y;
+                }
+                if (i < rows) {
                     const double x = col[i] - w * v[i];
                     col[i] = x;
-                    if (i > j) s += x * x;
+                    s0 += (i > j) ? x * x : 0.0;
                 }
-                s += __shfl_xor(s, 1, RQLP_WAVE);
-                s += __shfl_xor(s, 2, RQLP_WAVE);
-                if (qd == 0) nrm2[c] = s;
+                double sn = s0 + s1;
+                for (int off = tpc >> 1; off > 0; off >>= 1) sn += __shfl_xor(sn, off, RQLP_WAVE);
+                if (qd == 0) nrm2[c] = sn;
             }
         }
         __syncthreads();
@@ -315,10 +457,10 @@ size_t cpqr_scratch_bytes(int64_t rows, int64_t cols) {
 void cpqr_carve(Arena& ar, int64_t rows, int64_t cols, CpqrScratch* sc) {
     const int cus = device_info().num_cus > 0 ? device_info().num_cus : 256;
     const int64_t kmax = rows < cols ? rows : cols;
-    sc->keys = ar.take<unsigned long long>(2 * kmax);
+    sc->keys = ar.take<unsigned long long>((size_t)kmax * cp_key_words(cus));
     sc->candcol = ar.take<double>((size_t)2 * cus * rows);
     sc->partial = ar.take<double>(cus);
-    sc->bar = ar.take<unsigned>(2);
+    sc->bar = ar.take<unsigned>(cp_bar_words(cus));
 }
 
 int cpqr(const double* M, int64_t ldm, int64_t rows, int64_t cols, const CpqrScratch& sc, int64_t* piv,
@@ -346,8 +488,8 @@ int cpqr(const double* M, int64_t ldm, int64_t rows, int64_t cols, const CpqrScr
                            ldr, Rt, ldrt, info, spin);
         return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
     }
-    RQLP_TRY(fill_zero_bytes(sc.keys, sizeof(unsigned long long) * 2 * kmax, s));
-    RQLP_TRY(fill_zero_bytes(sc.bar, 2 * sizeof(unsigned), s));
+    RQLP_TRY(fill_zero_bytes(sc.keys, sizeof(unsigned long long) * (size_t)kmax * cp_key_words(plan.G), s));
+    RQLP_TRY(fill_zero_bytes(sc.bar, sizeof(unsigned) * cp_bar_words(plan.G), s));
     int nb = 0;
     RQLP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)cpqr_kernel<false>, CP_T,
                                                              plan.lds));
