@@ -6,13 +6,17 @@
 // in FP64 or FP32 on the gfx950 matrix cores (v_mfma_f64_16x16x4f64 /
 // v_mfma_f32_16x16x4f32), FP accumulation in the input precision.
 //
-// Tiling: a workgroup of 4 waves owns a (64*MB) x (16*NB) block of C; the
-// four waves are stacked along M, each computing (16*MB) x (16*NB) with
-// MB*NB 16x16 accumulators.  N (= the sketch width l, at most a few hundred)
-// is covered by one or two column tiles, so A streams through HBM once per
-// column tile.  K is split across blockIdx.z when the M x N tile grid alone
-// cannot fill the 256 CUs; partial sums then go to a workspace and a second
-// kernel adds them in a fixed order (bitwise reproducible results).
+// Tiling: a workgroup of 4 waves owns a 64 x (16*NB) block of C (NB <= 7);
+// the four waves are stacked along M, each computing 16 x (16*NB) with NB
+// 16x16 accumulators.  K advances in stages of 16 through two LDS buffers
+// (the next stage is fetched into registers and stored while the current one
+// feeds the MFMAs; one barrier per stage), which keeps a workgroup at ~53 KB
+// of LDS so that three are resident per CU and hide each other's latencies
+// (measured: 1 resident workgroup with 224-column tiles ran at ~33 TFLOP/s,
+// 3 resident with 112-column tiles at ~50 TFLOP/s on the 20000 x 10000 x 210
+// products).  K is split across blockIdx.z to give ~6 workgroups per CU;
+// partial sums go to a workspace and a second kernel adds them in a fixed
+// order (bitwise reproducible results).
 //
 // LDS layouts (chosen for conflict-free fragment reads on 64 banks):
 //   A, op(A) = A   : [k][i], row stride BM + 16   (global loads run along i)
@@ -47,26 +51,30 @@ struct Mfma<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-constexpr int GEMM_BK = 32;
+constexpr int GEMM_BK = 16;        // K depth of one LDS stage (two stages resident)
+constexpr int GEMM_MAX_NB = 7;     // at most 7 blocks of 16 columns per tile: 3 workgroups per CU
 constexpr int GEMM_THREADS = 256;
 
-template <typename T, bool TA, bool TB, int MB, int NB>
+template <typename T, bool TA, bool TB, int MB, int NB, int BK>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
     int64_t M, int64_t N, int64_t K, const T* __restrict__ A, int64_t lda,
     const T* __restrict__ B, int64_t ldb, T* __restrict__ C, int64_t ldc, int64_t split_stride,
     int64_t kchunk) {
-    constexpr int BK = GEMM_BK;
     constexpr int BM = 64 * MB;
     constexpr int BN = 16 * NB;
     constexpr int SA = TA ? (BK + 2) : (BM + 16);
     constexpr int A_ELEMS = TA ? BM * SA : BK * SA;
     constexpr int SB = BK + 2;
-    constexpr int A_PER_T = BM * BK / GEMM_THREADS;     // 8 * MB
-    constexpr int B_PER_T = BN * BK / GEMM_THREADS;     // 2 * NB
+    constexpr int B_ELEMS = BN * SB;
+    constexpr int A_PER_T = BM * BK / GEMM_THREADS;
+    constexpr int B_PER_T = BN * BK / GEMM_THREADS;
+    constexpr int KSTEP = GEMM_THREADS / BK;             // rows covered per pass of a k-contiguous load
+    static_assert(GEMM_THREADS % BK == 0 && BK % 4 == 0, "BK must divide the workgroup size");
     typedef typename Mfma<T>::acc_t acc_t;
 
-    __shared__ T As[A_ELEMS];
-    __shared__ T Bs[BN * SB];
+    // two LDS buffers: the tile for step t+1 is stored while step t computes
+    __shared__ T As[2][A_ELEMS];
+    __shared__ T Bs[2][B_ELEMS];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -88,30 +96,30 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
     // ---- global -> registers for the tile starting at kt ----
     auto load_tile = [&](int64_t kt) {
         if (!TA) {
-            // i = tid % 64 + 64 r, k = tid / 64 + 4 c
+            // op(A) = A: i = tid % 64 + 64 r, k = tid / 64 + 4 c (runs along i)
 #pragma unroll
             for (int r = 0; r < MB; ++r)
 #pragma unroll
                 for (int c = 0; c < BK / 4; ++c) {
-                    int64_t i = m0 + (tid & 63) + 64 * r;
-                    int64_t k = kt + (tid >> 6) + 4 * c;
+                    const int64_t i = m0 + (tid & 63) + 64 * r;
+                    const int64_t k = kt + (tid >> 6) + 4 * c;
                     ra[r * (BK / 4) + c] = (i < M && k < kend) ? A[i + k * lda] : T(0);
                 }
         } else {
-            // k = tid % 32, i = tid / 32 + 8 r
+            // op(A) = A^T: k = tid % BK, i = tid / BK + KSTEP r (runs along k)
 #pragma unroll
             for (int r = 0; r < A_PER_T; ++r) {
-                int64_t k = kt + (tid & 31);
-                int64_t i = m0 + (tid >> 5) + 8 * r;
+                const int64_t k = kt + (tid % BK);
+                const int64_t i = m0 + (tid / BK) + KSTEP * r;
                 ra[r] = (i < M && k < kend) ? A[k + i * lda] : T(0);
             }
         }
         if (!TB) {
-            // op(B) = B (K x N): k = tid % 32, j = tid / 32 + 8 r
+            // op(B) = B (K x N): k = tid % BK, j = tid / BK + KSTEP r
 #pragma unroll
             for (int r = 0; r < B_PER_T; ++r) {
-                int64_t k = kt + (tid & 31);
-                int64_t j = n0 + (tid >> 5) + 8 * r;
+                const int64_t k = kt + (tid % BK);
+                const int64_t j = n0 + (tid / BK) + KSTEP * r;
                 rb[r] = (j < N && k < kend) ? B[k + j * ldb] : T(0);
             }
         } else {
@@ -119,41 +127,48 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
 #pragma unroll
             for (int r = 0; r < B_PER_T; ++r) {
                 const int e = tid + GEMM_THREADS * r;
-                int64_t j = n0 + e % BN;
-                int64_t k = kt + e / BN;
+                const int64_t j = n0 + e % BN;
+                const int64_t k = kt + e / BN;
                 rb[r] = (j < N && k < kend) ? B[j + k * ldb] : T(0);
             }
         }
     };
-    auto store_tile = [&]() {
+    auto store_tile = [&](int buf) {
+        T* as = As[buf];
+        T* bs = Bs[buf];
         if (!TA) {
 #pragma unroll
             for (int r = 0; r < MB; ++r)
 #pragma unroll
                 for (int c = 0; c < BK / 4; ++c)
-                    As[((tid >> 6) + 4 * c) * SA + (tid & 63) + 64 * r] = ra[r * (BK / 4) + c];
+                    as[((tid >> 6) + 4 * c) * SA + (tid & 63) + 64 * r] = ra[r * (BK / 4) + c];
         } else {
 #pragma unroll
-            for (int r = 0; r < A_PER_T; ++r) As[((tid >> 5) + 8 * r) * SA + (tid & 31)] = ra[r];
+            for (int r = 0; r < A_PER_T; ++r) as[((tid / BK) + KSTEP * r) * SA + (tid % BK)] = ra[r];
         }
         if (!TB) {
 #pragma unroll
-            for (int r = 0; r < B_PER_T; ++r) Bs[((tid >> 5) + 8 * r) * SB + (tid & 31)] = rb[r];
+            for (int r = 0; r < B_PER_T; ++r) bs[((tid / BK) + KSTEP * r) * SB + (tid % BK)] = rb[r];
         } else {
 #pragma unroll
             for (int r = 0; r < B_PER_T; ++r) {
                 const int e = tid + GEMM_THREADS * r;
-                Bs[(e % BN) * SB + e / BN] = rb[r];
+                bs[(e % BN) * SB + e / BN] = rb[r];
             }
         }
     };
 
-    if (kbeg < kend) load_tile(kbeg);
+    if (kbeg < kend) {
+        load_tile(kbeg);
+        store_tile(0);
+    }
+    __syncthreads();
+    int buf = 0;
     for (int64_t kt = kbeg; kt < kend; kt += BK) {
-        __syncthreads();
-        store_tile();
-        __syncthreads();
-        if (kt + BK < kend) load_tile(kt + BK);
+        const bool more = kt + BK < kend;
+        if (more) load_tile(kt + BK);
+        const T* as = As[buf];
+        const T* bs = Bs[buf];
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
@@ -161,15 +176,18 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
 #pragma unroll
             for (int a = 0; a < MB; ++a) {
                 const int i = wave * 16 * MB + a * 16 + (lane & 15);
-                af[a] = TA ? As[i * SA + kk] : As[kk * SA + i];
+                af[a] = TA ? as[i * SA + kk] : as[kk * SA + i];
             }
 #pragma unroll
-            for (int b = 0; b < NB; ++b) bf[b] = Bs[(b * 16 + (lane & 15)) * SB + kk];
+            for (int b = 0; b < NB; ++b) bf[b] = bs[(b * 16 + (lane & 15)) * SB + kk];
 #pragma unroll
             for (int a = 0; a < MB; ++a)
 #pragma unroll
                 for (int b = 0; b < NB; ++b) acc[a][b] = Mfma<T>::op(af[a], bf[b], acc[a][b]);
         }
+        if (more) store_tile(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
     }
 
     // ---- write C (or this split's partial) ----
@@ -188,13 +206,33 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
         }
 }
 
-// C (M x N, or its transpose when trans_out) = alpha * sum_s W_s + beta * C,
+// C (M x N) = alpha * sum_s W_s + beta * C, one output element per thread,
 // summed in the fixed order s = 0, 1, ...
-template <typename T, bool TRANS_OUT>
+template <typename T>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(int64_t M, int64_t N, const T* __restrict__ W,
-                                                            int64_t ldw, int64_t split_stride, int S,
-                                                            T alpha, T beta, T* __restrict__ C,
-                                                            int64_t ldc) {
+                                                            int64_t ldw, int64_t split_stride, int S, T alpha,
+                                                            T beta, T* __restrict__ C, int64_t ldc) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= M * N) return;
+    const int64_t i = idx % M, j = idx / M;
+    const T* w = W + i + j * ldw;
+    T v0 = T(0), v1 = T(0);
+    int s = 0;
+    for (; s + 1 < S; s += 2) {
+        v0 += w[s * split_stride];
+        v1 += w[(s + 1) * split_stride];
+    }
+    if (s < S) v0 += w[s * split_stride];
+    T v = alpha * (v0 + v1);
+    if (beta != T(0)) v += beta * C[i + j * ldc];
+    C[i + j * ldc] = v;
+}
+
+// C (N x M) = (alpha * sum_s W_s + beta * C^T)^T through 32 x 32 LDS tiles.
+template <typename T>
+__global__ __launch_bounds__(256) void splitk_reduce_t_kernel(int64_t M, int64_t N, const T* __restrict__ W,
+                                                              int64_t ldw, int64_t split_stride, int S, T alpha,
+                                                              T beta, T* __restrict__ C, int64_t ldc) {
     __shared__ T tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
     const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
@@ -204,16 +242,10 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(int64_t M, int64_t N
         if (i < M && j < N) {
             for (int s = 0; s < S; ++s) v += W[s * split_stride + i + j * ldw];
             v *= alpha;
-            if (!TRANS_OUT) {
-                if (beta != T(0)) v += beta * C[i + j * ldc];
-                C[i + j * ldc] = v;
-            }
         }
-        if (TRANS_OUT) tile[jj][tx] = v;
+        tile[jj][tx] = v;
     }
-    if (!TRANS_OUT) return;
     __syncthreads();
-    // C is N x M: element (j, i) at C[j + i * ldc]
     for (int ii = ty; ii < 32; ii += 8) {
         const int64_t j = j0 + tx, i = i0 + ii;
         if (i < M && j < N) {
@@ -238,14 +270,18 @@ struct GemmPlan {
 GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K) {
     GemmPlan p;
     int64_t nblk = ceil_div(N, 16);
-    int64_t ntiles = ceil_div(nblk, 16);
+    int64_t ntiles = ceil_div(nblk, GEMM_MAX_NB);
     p.nb = (int)ceil_div(nblk, ntiles);
     p.tm = ceil_div(M, 64);
     p.tn = ceil_div(N, 16 * p.nb);
     const int cus = device_info().num_cus > 0 ? device_info().num_cus : 256;
-    int64_t want = 2 * cus;
+    int64_t want = 6 * cus;              // two rounds of three resident workgroups per CU
     int64_t S = ceil_div(want, p.tm * p.tn);
-    int64_t smax = ceil_div(K, 4 * GEMM_BK);
+    // K chunks of at least 256, and partial sums (S M N) of at most a quarter
+    // of the operands' volume K (M + N)
+    int64_t smax = ceil_div(K, 256);
+    const int64_t straffic = (K * (M + N)) / (4 * M * N);
+    if (smax > straffic) smax = straffic > 1 ? straffic : 1;
     if (S > smax) S = smax;
     if (S < 1) S = 1;
     if (K <= 0) {
@@ -263,7 +299,7 @@ template <typename T, bool TA, bool TB, int NB>
 void launch_nb(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda,
                const T* B, int64_t ldb, T* C, int64_t ldc, int64_t split_stride, hipStream_t s) {
     dim3 grid((unsigned)p.tm, (unsigned)p.tn, (unsigned)p.S);
-    hipLaunchKernelGGL((gemm_skinny_kernel<T, TA, TB, 1, NB>), grid, dim3(GEMM_THREADS), 0, s, M, N, K, A,
+    hipLaunchKernelGGL((gemm_skinny_kernel<T, TA, TB, 1, NB, GEMM_BK>), grid, dim3(GEMM_THREADS), 0, s, M, N, K, A,
                        lda, B, ldb, C, ldc, split_stride, p.kchunk);
 }
 
@@ -274,9 +310,7 @@ void launch_dispatch(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const T
 #define RQLP_NB_CASE(X) \
     case X: launch_nb<T, TA, TB, X>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, s); break;
         RQLP_NB_CASE(1) RQLP_NB_CASE(2) RQLP_NB_CASE(3) RQLP_NB_CASE(4)
-        RQLP_NB_CASE(5) RQLP_NB_CASE(6) RQLP_NB_CASE(7) RQLP_NB_CASE(8)
-        RQLP_NB_CASE(9) RQLP_NB_CASE(10) RQLP_NB_CASE(11) RQLP_NB_CASE(12)
-        RQLP_NB_CASE(13) RQLP_NB_CASE(14) RQLP_NB_CASE(15) RQLP_NB_CASE(16)
+        RQLP_NB_CASE(5) RQLP_NB_CASE(6) RQLP_NB_CASE(7)
 #undef RQLP_NB_CASE
         default: break;
     }
@@ -311,13 +345,14 @@ int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A, int64_t 
     }
     if ((size_t)(p.S * M * N) > ws_elems || ws == nullptr) return RQLP_E_WORKSPACE;
     launch_any<T>(ta, tb, p, M, N, K, A, lda, B, ldb, ws, M, M * N, s);
-    dim3 grid((unsigned)ceil_div(M, 32), (unsigned)ceil_div(N, 32));
-    if (trans_out)
-        hipLaunchKernelGGL((splitk_reduce_kernel<T, true>), grid, dim3(256), 0, s, M, N, ws, M, M * N,
-                           (int)p.S, alpha, beta, C, ldc);
-    else
-        hipLaunchKernelGGL((splitk_reduce_kernel<T, false>), grid, dim3(256), 0, s, M, N, ws, M, M * N,
-                           (int)p.S, alpha, beta, C, ldc);
+    if (trans_out) {
+        dim3 grid((unsigned)ceil_div(M, 32), (unsigned)ceil_div(N, 32));
+        hipLaunchKernelGGL((splitk_reduce_t_kernel<T>), grid, dim3(256), 0, s, M, N, ws, M, M * N, (int)p.S,
+                           alpha, beta, C, ldc);
+    } else {
+        hipLaunchKernelGGL((splitk_reduce_kernel<T>), dim3((unsigned)ceil_div(M * N, 256)), dim3(256), 0, s, M, N,
+                           ws, M, M * N, (int)p.S, alpha, beta, C, ldc);
+    }
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 

@@ -108,21 +108,22 @@ int set_identity(int64_t n, double* Y, int64_t ldy, hipStream_t s) {
 }
 
 __global__ void finish_lvals_kernel(int64_t l, const double* T, int64_t ldt, double* lvals, int32_t* info) {
+    // one wave per column: lvals = diag(T), any NaN / Inf in T flagged
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= l) return;
     int bad = 0;
-    for (int64_t j = threadIdx.x; j < l; j += blockDim.x) {
-        const double d = T[j + j * ldt];
-        if (lvals) lvals[j] = d;
-        for (int64_t i = 0; i < l; ++i) {
-            const double x = T[i + j * ldt];
-            if (!(x == x) || x > 1.7e308 || x < -1.7e308) bad = 1;
-        }
+    for (int64_t i = lane; i < l; i += 64) {
+        const double x = T[i + j * ldt];
+        if (!(x == x) || x > 1.7e308 || x < -1.7e308) bad = 1;
     }
-    if (bad && info) atomicOr(info, RQLP_INFO_NONFINITE);
+    if (lane == 0 && lvals) lvals[j] = T[j + j * ldt];
+    if (__any(bad) && lane == 0 && info) atomicOr(info, RQLP_INFO_NONFINITE);
 }
 
 int finish_lvals(int64_t l, const double* T, int64_t ldt, double* lvals, int32_t* info, hipStream_t s) {
     if (l <= 0) return 0;
-    hipLaunchKernelGGL(finish_lvals_kernel, dim3(1), dim3(256), 0, s, l, T, ldt, lvals, info);
+    hipLaunchKernelGGL(finish_lvals_kernel, dim3((unsigned)ceil_div(l, 4)), dim3(256), 0, s, l, T, ldt, lvals, info);
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 
