@@ -42,6 +42,11 @@ def parse_args():
     ap.add_argument("--workload", default="erqlp_f64_20000x10000")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--gaussian-input", action="store_true",
+                    help="A = N(0,1) instead of the prescribed spectrum (hardware-counter runs only: "
+                         "skips the QR-based generation)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one elementwise copy of 1 GiB (reference for the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -74,10 +79,23 @@ def main():
     w = inputs.WORKLOADS[args.workload]
     l = w.l
     t0 = time.time()
-    A = inputs.make_matrix_torch(w, dev)           # column-major (m, n) in HBM
+    if args.gaussian_input:
+        g = torch.Generator(device=dev)
+        g.manual_seed(w.seed_a)
+        dt = torch.float64 if w.storage == "f64" else torch.float32
+        A = torch.randn(w.n, w.m, generator=g, dtype=dt, device=dev).t()
+    else:
+        A = inputs.make_matrix_torch(w, dev)       # column-major (m, n) in HBM
     torch.cuda.synchronize()
     gen_s = time.time() - t0
     print(f"# generated A {w.m}x{w.n} in {gen_s:.1f} s", file=sys.stderr, flush=True)
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)     # 1 GiB read, 1 GiB written
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     work = torch.empty(rq.workspace_size(w.m, w.n, w.k, w.p, w.q, w.d, w.b, w.precision),
                        dtype=torch.uint8, device=dev)
@@ -171,7 +189,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "m": w.m, "n": w.n, "k": w.k, "p": w.p, "q": w.q, "d": w.d,
-                   "precision": w.precision, "spectrum": "10^(-4(j-1)/199), j<=200; 1e-6 beyond"},
+                   "precision": w.precision,
+                   "input": "gaussian" if args.gaussian_input else "prescribed spectrum"},
         "factorizations_per_s": round(1e3 / ms, 3),
         "flops_per_step": F,
         "info": info,
