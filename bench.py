@@ -1,15 +1,21 @@
 """Benchmark of the randomized QLP hot path on one MI355X.
 
-Default workload: ERQLP in FP64, A = U diag(s) V^T (20000 x 10000,
-s_j = 10^(-4(j-1)/199) for j <= 200, 1e-6 beyond), k = 200, p = 10,
-q = 1 subspace iteration, d = 2 inner QR steps, Omega generated inside the
-call.  One step = one full rqlp_factor call (test matrix, sketch, subspace
-iteration, orthonormalisations, projection, both factorisations, assembly)
-with A already resident in HBM.
+Default workload: mixed-precision ERQLP on A = U_256 diag(1/j) V_256^T +
+1e-3 N(0,1) (32768 x 16384, stored FP32), k = 256, p = 16, q = 2 subspace
+iterations, d = 2 inner QR steps, Omega generated inside the call and
+rounded to bfloat16.  The 2q + 2 passes over A run as bfloat16 MFMA products
+with FP32 accumulation, the panels are orthonormalised by FP32 CholeskyQR2
+(FP64 Cholesky), and the CPQR, second factorisation and L stay in FP64.  One
+step = one full rqlp_factor call with A already resident in HBM (the
+FP32 -> bfloat16 encoding of A happens inside the call and is timed).
 
-Prints ONE JSON line (rank 0) with the throughput, a roofline figure for
-the dominant kernel (the FP64 MFMA skinny product, timed with HIP events on
-the library's stream) and the FP64 CPU oracle timed on the host cores.
+Prints ONE JSON line with the throughput (TFLOP/s under the fixed flop
+model), the same call in FP64 on the same matrix and the speedup, the
+L-value error against the FP64 CPU oracle (free pivots and the oracle re-run
+on the GPU's pivots), a roofline figure for the dominant kernel (the 16-bit
+projection product, timed with HIP events on the library's stream) and the
+oracle's own throughput on the host cores.  ``--workload
+erqlp_f64_20000x10000`` runs the FP64 ERQLP workload instead.
 """
 import argparse
 import hashlib
@@ -26,6 +32,12 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "fp16": 2500.0}   # dense TFLOP/s, MI355X
 HBM_PEAK_GBS = 8000.0
+METRIC = "RQLP TFLOP/s & factorizations/s, mixed vs FP64, at L-value rel err <=1e-3"
+DEFAULT_WORKLOAD = "erqlp_bf16_32768x16384"
+PMC_PROFILES = {   # dominant kernel -> committed PMC summary (HBM bytes per launch)
+    "f64": ("gemm_f64_tn_20000x10000_pmc.md", "gemm.hip"),
+    "lp": ("gemm_lp_bf16_tn_32768x16384_pmc.md", "gemm_lp.hip"),
+}
 
 
 def flop_model(m, n, l, q):
@@ -39,9 +51,10 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="erqlp_f64_20000x10000")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run on the mixed workload's matrix")
     ap.add_argument("--gaussian-input", action="store_true",
                     help="A = N(0,1) instead of the prescribed spectrum (hardware-counter runs only: "
                          "skips the QR-based generation)")
@@ -50,18 +63,98 @@ def parse_args():
     return ap.parse_args()
 
 
-def traffic_from_profile(src_sha):
+def traffic_from_profile(name, src_file):
     """HBM bytes per launch of the dominant kernel from the committed PMC
     summary, or None when it is absent or was taken on other kernel source."""
-    path = os.path.join(ROOT, "profiles", "gemm_f64_tn_20000x10000_pmc.md")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
+    src = open(os.path.join(ROOT, "paper_1811_09334_amd", "csrc", src_file), "rb").read()
     txt = open(path).read()
     m_sha = re.search(r"source_sha256:\s*([0-9a-f]+)", txt)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m_sha or not m_b or m_sha.group(1) != src_sha:
+    if not m_sha or not m_b or m_sha.group(1) != hashlib.sha256(src).hexdigest():
         return None
     return float(m_b.group(1))
+
+
+def timed(fn, steps, warmup):
+    import torch
+    out = None
+    for _ in range(warmup):
+        out = fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, out
+
+
+def event_time(fn, stream, reps=10):
+    """Average device time of fn() over reps calls, HIP events on ``stream``."""
+    import torch
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def roofline_f64(rq, A, V, w, dev):
+    import torch
+    l = w.l
+    nb = rq._lib.rqlp_gemm_workspace(w.m, w.n, l, 0)
+    gw = torch.empty(nb, dtype=torch.uint8, device=dev)
+    B = rq.empty_colmajor(l, w.n, torch.float64, dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def proj():
+        rq.check("rqlp_project", rq._lib.rqlp_project(A.data_ptr(), rq.ld(A), w.m, w.n, V.data_ptr(), rq.ld(V), l,
+                                                      B.data_ptr(), rq.ld(B), 0, gw.data_ptr(), nb,
+                                                      stream.cuda_stream))
+    t = event_time(proj, stream)
+    flops = 2.0 * w.m * w.n * l
+    achieved = flops / t / 1e12
+    name, src = PMC_PROFILES["f64"]
+    print(f"# projection product: {t*1e3:.3f} ms, {achieved:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK["f64"], 4), "traffic": traffic_from_profile(name, src),
+            "kernel": "gemm_skinny_kernel<double, A^T> + split-K reduce (B = V^T A)", "flops_per_launch": flops,
+            "launch_ms": round(t * 1e3, 4)}
+
+
+def roofline_lp(rq, A, V, w, dev):
+    """The 16-bit projection product B = V^T A on the pre-encoded A: below the
+    BF16 ridge (2 m n l flops over ~2 m n bytes = l flop/B < 312), so HBM
+    bandwidth is the roof; algorithmic bytes = A once in 16 bits (twice for
+    the split form) + V read in FP32 + B written in FP32."""
+    import torch
+    l = w.l
+    E = rq.encode(A, w.precision)
+    torch.cuda.synchronize()
+    B = rq.empty_colmajor(l, w.n, torch.float32, dev)
+    nb = rq._lib.rqlp_gemm_workspace(w.m, w.n, l, rq.PRECISIONS[w.precision])
+    work = torch.empty(nb, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    t = event_time(lambda: rq.project_encoded(E, V, B, work), stream)
+    parts = 2 if w.precision == "bf16x3" else 1
+    nbytes = 2.0 * parts * w.m * w.n + 4.0 * w.m * l + 4.0 * l * w.n
+    flops = 2.0 * w.m * w.n * l
+    gbs = nbytes / t / 1e9
+    name, src = PMC_PROFILES["lp"]
+    traffic = traffic_from_profile(name, src) if w.precision == "bf16" else None
+    print(f"# 16-bit projection product: {t*1e3:.3f} ms, {gbs:.0f} GB/s, {flops/t/1e12:.1f} TFLOP/s",
+          file=sys.stderr, flush=True)
+    del E
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": f"gemm_lp_kernel<{w.precision}, A^T> + V encode + split-K reduce (B = V^T A)",
+            "bytes_per_launch": nbytes, "launch_ms": round(t * 1e3, 4),
+            "mfma_tflops": round(flops / t / 1e12, 2), "mfma_frac": round(flops / t / 1e12 / PEAK["bf16"], 4)}
 
 
 def main():
@@ -77,6 +170,7 @@ def main():
     rq.load()
     dev = torch.device("cuda:0")
     w = inputs.WORKLOADS[args.workload]
+    mixed = w.precision in ("bf16", "fp16", "bf16x3")
     l = w.l
     t0 = time.time()
     if args.gaussian_input:
@@ -87,8 +181,7 @@ def main():
     else:
         A = inputs.make_matrix_torch(w, dev)       # column-major (m, n) in HBM
     torch.cuda.synchronize()
-    gen_s = time.time() - t0
-    print(f"# generated A {w.m}x{w.n} in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    print(f"# generated A {w.m}x{w.n} ({A.dtype}) in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
 
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)     # 1 GiB read, 1 GiB written
@@ -97,68 +190,52 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    seed = w.seed_omega
     work = torch.empty(rq.workspace_size(w.m, w.n, w.k, w.p, w.q, w.d, w.b, w.precision),
                        dtype=torch.uint8, device=dev)
-    seed = w.seed_omega
-
-    def step():
-        return rq.factor(A, w.k, w.p, q=w.q, d=w.d, b=w.b, precision=w.precision, seed=seed, work=work)
-
-    for _ in range(args.warmup):
-        f = step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        f = step()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms, f = timed(lambda: rq.factor(A, w.k, w.p, q=w.q, d=w.d, b=w.b, precision=w.precision, seed=seed,
+                                    work=work), args.steps, args.warmup)
+    del work
     info = int(f.info.item())
     F = flop_model(w.m, w.n, l, w.q)
     tflops = F / (ms * 1e-3) / 1e12
-    print(f"# {ms:.3f} ms/step, {tflops:.2f} TFLOP/s, info={info:#x}", file=sys.stderr, flush=True)
+    print(f"# {w.precision}: {ms:.3f} ms/step, {tflops:.2f} TFLOP/s, info={info:#x}", file=sys.stderr, flush=True)
 
-    # ---- roofline of the dominant kernel: the FP64 MFMA product B^T = A^T V ----
+    # ---- the same call in FP64 on the same matrix (the "mixed vs FP64" ratio) ----
+    fp64 = None
+    if mixed and not args.no_fp64:
+        A64 = rq.empty_colmajor(w.m, w.n, torch.float64, dev)
+        A64.copy_(A)
+        w64 = torch.empty(rq.workspace_size(w.m, w.n, w.k, w.p, w.q, w.d, w.b, "f64"), dtype=torch.uint8,
+                          device=dev)
+        steps64 = max(3, args.steps // 4)
+        ms64, f64r = timed(lambda: rq.factor(A64, w.k, w.p, q=w.q, d=w.d, b=w.b, precision="f64", seed=seed,
+                                             work=w64), steps64, 1)
+        fp64 = {"ms_per_step": round(ms64, 4), "tflops": round(F / (ms64 * 1e-3) / 1e12, 4), "steps": steps64,
+                "info": int(f64r.info.item())}
+        print(f"# f64 on the same matrix: {ms64:.3f} ms/step ({ms64 / ms:.2f}x the {w.precision} time)",
+              file=sys.stderr, flush=True)
+        del A64, w64, f64r
+        torch.cuda.empty_cache()
+
+    # ---- roofline of the dominant kernel: the projection product B = V^T A ----
     roof = None
     if not args.no_roofline:
-        V = rq.empty_colmajor(w.m, l, torch.float64, dev)
+        V = rq.empty_colmajor(w.m, l, f.Q.dtype, dev)
         V.copy_(f.Q)
-        nb = rq._lib.rqlp_gemm_workspace(w.m, w.n, l, 0)
-        gw = torch.empty(nb, dtype=torch.uint8, device=dev)
-        B = rq.empty_colmajor(l, w.n, torch.float64, dev)
-        stream = torch.cuda.current_stream(dev)
-        reps = 10
-
-        def proj():
-            rq.check("rqlp_project", rq._lib.rqlp_project(A.data_ptr(), rq.ld(A), w.m, w.n, V.data_ptr(),
-                                                          rq.ld(V), l, B.data_ptr(), rq.ld(B), 0,
-                                                          gw.data_ptr(), nb, stream.cuda_stream))
-        proj()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            proj()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t_launch = e0.elapsed_time(e1) * 1e-3 / reps
-        flops = 2.0 * w.m * w.n * l
-        achieved = flops / t_launch / 1e12
-        src = open(os.path.join(ROOT, "paper_1811_09334_amd", "csrc", "gemm.hip"), "rb").read()
-        traffic = traffic_from_profile(hashlib.sha256(src).hexdigest())
-        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["f64"], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK["f64"], 4), "traffic": traffic,
-                "kernel": "gemm_skinny_kernel<double, A^T>", "flops_per_launch": flops,
-                "launch_ms": round(t_launch * 1e3, 4)}
-        print(f"# projection product: {t_launch*1e3:.3f} ms, {achieved:.2f} TFLOP/s", file=sys.stderr, flush=True)
+        roof = roofline_lp(rq, A, V, w, dev) if mixed else roofline_f64(rq, A, V, w, dev)
+        del V
 
     # ---- CPU baseline: the FP64 oracle on the host cores, same A and Omega ----
     cpu = None
-    lval_err = None
+    acc = {}
     if not args.no_cpu_baseline:
         from oracle.rqlp import rqlp as oracle_rqlp
-        Om = rq.generate_omega(w.n, l, seed, "f64", dev)
+        Om = rq.generate_omega(w.n, l, seed, w.precision, dev)
         torch.cuda.synchronize()
-        A_h = np.asfortranarray(A.cpu().numpy())
-        Om_h = np.asfortranarray(Om.cpu().numpy())
+        A_h = np.asfortranarray(A.double().cpu().numpy()) if A.dtype != torch.float64 else \
+            np.asfortranarray(A.cpu().numpy())
+        Om_h = np.asfortranarray(Om.double().cpu().numpy())
         try:
             cores = len(os.sched_getaffinity(0))
         except AttributeError:
@@ -168,15 +245,23 @@ def main():
         ref = oracle_rqlp(A_h, Om_h, w.k, w.p, q=w.q, d=w.d)
         t_cpu = time.perf_counter() - t0
         cpu = {"value": round(F / t_cpu / 1e12, 5), "unit": "TFLOP/s", "cores": min(threads, cores),
-               "kind": "oracle", "sample": f"one full factorisation of the same {w.m}x{w.n} matrix "
+               "kind": "oracle", "sample": f"one full factorisation of the same {w.m}x{w.n} matrix in FP64 "
                                            f"({t_cpu:.1f} s)"}
         lv = f.lvals.cpu().numpy()
-        lval_err = float(np.max(np.abs(lv[: w.k] - ref.lvals[: w.k]) / ref.lvals[: w.k]))
-        print(f"# oracle {t_cpu:.1f} s; GPU vs oracle max L-value rel err {lval_err:.2e}", file=sys.stderr,
-              flush=True)
+        piv0 = f.piv0.cpu().numpy()
+        acc["lval_rel_err_free"] = float(np.max(np.abs(lv[: w.k] - ref.lvals[: w.k]) / ref.lvals[: w.k]))
+        d = np.flatnonzero(piv0 != ref.piv0)
+        acc["first_pivot_divergence"] = int(d[0]) if d.size else -1
+        print(f"# oracle {t_cpu:.1f} s; free L-value rel err {acc['lval_rel_err_free']:.2e}, first pivot "
+              f"divergence {acc['first_pivot_divergence']}", file=sys.stderr, flush=True)
+        if mixed:
+            piv1 = f.piv1.cpu().numpy() if w.d == 0 else None
+            fr = oracle_rqlp(A_h, Om_h, w.k, w.p, q=w.q, d=w.d, piv0=piv0, piv1=piv1)
+            acc["lval_rel_err_frozen"] = float(np.max(np.abs(lv[: w.k] - fr.lvals[: w.k]) / fr.lvals[: w.k]))
+            print(f"# frozen-pivot L-value rel err {acc['lval_rel_err_frozen']:.2e}", file=sys.stderr, flush=True)
 
     out = {
-        "metric": "RQLP TFLOP/s & factorizations/s, mixed vs FP64, at L-value rel err <=1e-3",
+        "metric": METRIC,
         "value": round(tflops, 4),
         "unit": "TFLOP/s",
         "n_gpus": 1,
@@ -186,15 +271,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": w.precision,
         "data": "synthetic",
-        "config": {"workload": w.name, "m": w.m, "n": w.n, "k": w.k, "p": w.p, "q": w.q, "d": w.d,
+        "config": {"workload": w.name, "m": w.m, "n": w.n, "k": w.k, "p": w.p, "q": w.q, "d": w.d, "b": w.b,
                    "precision": w.precision,
+                   "arithmetic": ("16-bit MFMA products with FP32 accumulation, FP32 CholeskyQR2, FP64 CPQR / "
+                                  "second factorisation / L") if mixed else "FP64 throughout",
                    "input": "gaussian" if args.gaussian_input else "prescribed spectrum"},
         "factorizations_per_s": round(1e3 / ms, 3),
         "flops_per_step": F,
         "info": info,
-        "lval_rel_err_vs_oracle": lval_err,
+        "fp64_same_matrix": fp64,
+        "speedup_vs_fp64": round(fp64["ms_per_step"] / ms, 3) if fp64 else None,
+        **acc,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -141,19 +141,52 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
 /* ---- building blocks (the steps of Algorithm 2.1, usable on their own) ---- */
 
 /* Y = A X  (Algorithm 2.1 step 2, and every pass of the subspace iteration):
- * A m x n, X n x c, Y m x c, all double (RQLP_F64) or all float (RQLP_F32).
- * Uses `work` for split-K partial sums; query the size with rqlp_gemm_workspace. */
+ * A m x n, X n x c, Y m x c, all double (RQLP_F64) or all float (any other
+ * precision).  The mixed precisions round A and X to their 16-bit type as
+ * rqlp_encode does and accumulate in FP32 (RQLP_MIXED_FP16 scales column j
+ * of A by 2^-e_j and row j of X by 2^(e_j - g), and Y by 2^g).
+ * Uses `work` for split-K partial sums and the 16-bit copies; query the size
+ * with rqlp_gemm_workspace. */
 int rqlp_sketch(const void* A, int64_t lda, int64_t m, int64_t n, const void* X, int64_t ldx,
                 int64_t c, void* Y, int64_t ldy, int precision, void* work, size_t work_bytes,
                 void* stream);
 
-/* B = V^T A  (Algorithm 2.1 step 4): V m x c, A m x n, B c x n. */
+/* B = V^T A  (Algorithm 2.1 step 4): V m x c, A m x n, B c x n; element
+ * types and 16-bit rounding as for rqlp_sketch (FP16: B(:, j) carries the
+ * column scale 2^e_j back). */
 int rqlp_project(const void* A, int64_t lda, int64_t m, int64_t n, const void* V, int64_t ldv,
                  int64_t c, void* B, int64_t ldb, int precision, void* work, size_t work_bytes,
                  void* stream);
 
-/* Bytes of work rqlp_sketch / rqlp_project need for these shapes (host out). */
+/* Bytes of work rqlp_sketch / rqlp_project / rqlp_project_encoded need for
+ * these shapes (host out). */
 int rqlp_gemm_workspace(int64_t m, int64_t n, int64_t c, int precision, size_t* bytes);
+
+/* 16-bit encoding of the FP32 matrix A (m x n) used by the MFMA products of
+ * the mixed precisions (the sketch / projection operands of Algorithm 2.1
+ * steps 2 and 4 in reduced precision).  precision is RQLP_MIXED_BF16,
+ * RQLP_MIXED_FP16 or RQLP_MIXED_BF16X3:
+ *   BF16   : Ahi = bf16(A) (round to nearest even);
+ *   BF16X3 : Ahi = bf16(A), Alo = bf16(A - Ahi);
+ *   FP16   : Ahi = half(A(:, j) 2^-e_j) with e_j chosen per column so that
+ *            max_i |A(i, j)| 2^-e_j lies in [2^14, 2^15) (0 for a zero
+ *            column); colexp (n int32) receives e_j and gexp (1 int32)
+ *            max_j e_j.  colexp / gexp are not used by the other types and
+ *            may be NULL there.
+ * transpose == 0: Ahi / Alo are column-major m x n (ldh >= m); otherwise
+ * they hold A^T, n x m (ldh >= n).  Alo must be NULL unless BF16X3.  Elements
+ * are the raw 16-bit patterns (uint16_t).  The caller owns all buffers. */
+int rqlp_encode(const float* A, int64_t lda, int64_t m, int64_t n, int precision, int transpose,
+                uint16_t* Ahi, uint16_t* Alo, int64_t ldh, int32_t* colexp, int32_t* gexp,
+                void* stream);
+
+/* B = V^T A (Algorithm 2.1 step 4) with A given as rqlp_encode's column-major
+ * encoding (Ahi, Alo, ldh >= m; colexp for RQLP_MIXED_FP16, else NULL); V is
+ * m x c float, rounded to the same 16-bit type inside; B is c x n float,
+ * FP32 accumulation.  Lets a caller encode A once and reuse it. */
+int rqlp_project_encoded(const uint16_t* Ahi, const uint16_t* Alo, int64_t ldh, const int32_t* colexp,
+                         int64_t m, int64_t n, const float* V, int64_t ldv, int64_t c, float* B,
+                         int64_t ldb, int precision, void* work, size_t work_bytes, void* stream);
 
 /* [V, ~] = qr(Y)  (Algorithm 2.1 step 3): V (m x c) gets an orthonormal basis
  * of range(Y) by CholeskyQR2 (shifted retry on breakdown); Y is m x c,

@@ -168,6 +168,55 @@ def project(A, V, precision=None):
     return B
 
 
+@dataclass
+class Encoded:
+    """A encoded for the 16-bit MFMA products (``rqlp_encode``)."""
+    hi: "object"          # uint16 bit patterns, column-major (m x n) or A^T (n x m)
+    lo: "object"          # bf16x3 remainders or None
+    colexp: "object"      # int32 per-column exponents (FP16) or None
+    gexp: "object"        # int32 max exponent (FP16) or None
+    m: int
+    n: int
+    precision: int
+    transpose: bool
+
+
+def encode(A, precision="bf16", transpose: bool = False) -> Encoded:
+    """16-bit encoding of the FP32 device matrix A through ``rqlp_encode``."""
+    torch = _torch()
+    prec = _prec(precision)
+    A = colmajor(A)
+    m, n = A.shape
+    rows, cols = (n, m) if transpose else (m, n)
+    hi = empty_colmajor(rows, cols, torch.int16, A.device)
+    lo = empty_colmajor(rows, cols, torch.int16, A.device) if prec == PRECISIONS["bf16x3"] else None
+    fp16 = prec == PRECISIONS["fp16"]
+    colexp = torch.empty(n, dtype=torch.int32, device=A.device) if fp16 else None
+    gexp = torch.empty(1, dtype=torch.int32, device=A.device) if fp16 else None
+    check("rqlp_encode", _lib.rqlp_encode(A.data_ptr(), ld(A), m, n, prec, int(transpose), hi.data_ptr(),
+                                          _ptr(lo), ld(hi), _ptr(colexp), _ptr(gexp), _stream(A.device)))
+    return Encoded(hi, lo, colexp, gexp, m, n, prec, transpose)
+
+
+def project_encoded(E: Encoded, V, B=None, work=None):
+    """B = V^T A through ``rqlp_project_encoded`` with A pre-encoded (column-major form)."""
+    torch = _torch()
+    if E.transpose:
+        raise ValueError("project_encoded needs the column-major encoding")
+    V = colmajor(V)
+    c = V.shape[1]
+    if B is None:
+        B = empty_colmajor(c, E.n, torch.float32, V.device)
+    nb = _lib.rqlp_gemm_workspace(E.m, E.n, c, E.precision)
+    if work is None or work.numel() < nb:
+        work = torch.empty(nb, dtype=torch.uint8, device=V.device)
+    check("rqlp_project_encoded", _lib.rqlp_project_encoded(E.hi.data_ptr(), _ptr(E.lo), ld(E.hi), _ptr(E.colexp),
+                                                            E.m, E.n, V.data_ptr(), ld(V), c, B.data_ptr(), ld(B),
+                                                            E.precision, work.data_ptr(), work.numel(),
+                                                            _stream(V.device)))
+    return B
+
+
 def orthonormalize(Y, want_r: bool = False):
     """[V, R] = qr(Y) by CholeskyQR2 through ``rqlp_orthonormalize`` (FP64)."""
     torch = _torch()

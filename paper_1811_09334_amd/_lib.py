@@ -30,6 +30,10 @@ SIGNATURES = {
     "rqlp_project": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_int64, c_void_p, c_int64,
                              c_int, c_void_p, c_size_t, c_void_p]),
     "rqlp_gemm_workspace": (c_int, [c_int64, c_int64, c_int64, c_int, POINTER(c_size_t)]),
+    "rqlp_encode": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_int, c_int, c_void_p, c_void_p, c_int64,
+                            c_void_p, c_void_p, c_void_p]),
+    "rqlp_project_encoded": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_void_p, c_int64,
+                                     c_int64, c_void_p, c_int64, c_int, c_void_p, c_size_t, c_void_p]),
     "rqlp_orthonormalize": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                                     c_void_p, c_void_p, c_size_t, c_void_p]),
     "rqlp_orthonormalize_workspace": (c_int, [c_int64, c_int64, POINTER(c_size_t)]),
@@ -109,6 +113,16 @@ def rqlp_gemm_workspace(m, n, c, precision) -> int:
     out = c_size_t(0)
     check("rqlp_gemm_workspace", _call("rqlp_gemm_workspace", m, n, c, precision, ctypes.byref(out)))
     return out.value
+
+
+def rqlp_encode(A, lda, m, n, precision, transpose, Ahi, Alo, ldh, colexp, gexp, stream) -> int:
+    return _call("rqlp_encode", A, lda, m, n, precision, transpose, Ahi, Alo, ldh, colexp, gexp, stream)
+
+
+def rqlp_project_encoded(Ahi, Alo, ldh, colexp, m, n, V, ldv, c, B, ldb, precision, work, work_bytes,
+                         stream) -> int:
+    return _call("rqlp_project_encoded", Ahi, Alo, ldh, colexp, m, n, V, ldv, c, B, ldb, precision, work,
+                 work_bytes, stream)
 
 
 def rqlp_orthonormalize(Y, ldy, m, c, V, ldv, R, ldr, info, work, work_bytes, stream) -> int:

@@ -1,6 +1,10 @@
 // C ABI of the randomized QLP library: argument checks, workspace carve-up
 // and the enqueue order of the hot path (Algorithms 2.1, 2.2, 4.1).
+#include <math.h>
 #include <string.h>
+
+#include <array>
+#include <initializer_list>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -9,10 +13,17 @@ using namespace rqlp;
 
 namespace {
 
-constexpr double kEps = 2.220446049250313e-16;
+constexpr double kEps = 2.220446049250313e-16;    // FP64 machine epsilon
+constexpr double kEps32 = 1.1920928955078125e-7;  // FP32 machine epsilon
 
 // CholeskyQR shift scale of Fukaya et al. (2020): 11 (m c + c (c + 1)) u.
 double shift_scale(int64_t rows, int64_t c) { return 11.0 * ((double)rows * c + (double)c * (c + 1)) * kEps; }
+
+// Shift scale for a Gram matrix accumulated in FP32 (Cholesky itself in FP64):
+// the worst-case bound above exceeds 1 at the panel sizes of the mixed path,
+// so the probabilistic size of the Gram's rounding error, sqrt(m) u tr(G)
+// (Higham & Mary 2019), is covered instead, with the same factor 11.
+double shift_scale32(int64_t rows, int64_t c) { return 11.0 * (sqrt((double)rows) + (double)c + 1.0) * kEps32; }
 
 // Scratch for orthonormalising a rows x c panel.
 struct OrthoScratch {
@@ -50,7 +61,7 @@ int cholqr2(Ctx& cx, int64_t rows, int64_t c, double* buf0, double* buf1, int64_
         RQLP_TRY(gemm<double>(true, false, c, c, rows, cur, ld, cur, ld, cx.o.G, c, false, 1.0, 0.0, cx.gws,
                               cx.gws_elems, cx.s));
         double* Lp = pass == 0 ? cx.o.L1 : cx.o.L2;
-        RQLP_TRY(chol_inv(c, cx.o.G, c, Lp, cx.o.Li, c, shift_scale(rows, c), cx.info, cx.s));
+        RQLP_TRY(chol_inv<double>(c, cx.o.G, c, Lp, cx.o.Li, nullptr, c, shift_scale(rows, c), cx.info, cx.s));
         RQLP_TRY(gemm<double>(false, true, rows, c, c, cur, ld, cx.o.Li, c, nxt, ld, false, 1.0, 0.0, cx.gws,
                               cx.gws_elems, cx.s));
         double* t = cur;
@@ -64,25 +75,57 @@ int cholqr2(Ctx& cx, int64_t rows, int64_t c, double* buf0, double* buf1, int64_
     return 0;
 }
 
-size_t max_gemm_ws(int64_t m, int64_t n, int64_t l) {
-    const int64_t shapes[][3] = {{m, l, n}, {n, l, m}, {l, l, m}, {l, l, n}, {m, l, l},
-                                 {n, l, l}, {l, l, l}, {l, n, m}};
+// FP32 panels for the mixed-precision range finder: the Gram and the update
+// X <- X L^{-T} run on FP32 MFMA, the c x c Cholesky and inverse in FP64.
+struct Ctx32 {
+    hipStream_t s;
+    int32_t* info;
+    float* ws;
+    size_t ws_elems;
+    float* G;       // c x c
+    float* Li;      // c x c
+    double* L;      // c x c (FP64 factor, discarded)
+    double* Lid;    // c x c (FP64 inverse)
+    int32_t* shifted;   // device word: the first pass used the shifted retry
+};
+
+// CholeskyQR2 of an FP32 panel, made shifted CholeskyQR3 (Fukaya et al.
+// 2020) when the first Cholesky breaks down: a third pass runs, but only
+// does work when the device word cx.shifted was set by the first pass (its
+// factor is the identity otherwise, so X is carried over exactly).  The
+// result is always in buf1.
+int cholqr_f32(Ctx32& cx, int64_t rows, int64_t c, float* buf0, float* buf1, int64_t ld, float** out) {
+    float* cur = buf0;
+    float* nxt = buf1;
+    for (int pass = 0; pass < 3; ++pass) {
+        RQLP_TRY(gemm<float>(true, false, c, c, rows, cur, ld, cur, ld, cx.G, c, false, 1.0f, 0.0f, cx.ws,
+                             cx.ws_elems, cx.s));
+        RQLP_TRY(chol_inv<float>(c, cx.G, c, cx.L, cx.Lid, cx.Li, c, shift_scale32(rows, c), cx.info, cx.s,
+                                 pass == 2 ? cx.shifted : nullptr, pass == 0 ? cx.shifted : nullptr));
+        RQLP_TRY(gemm<float>(false, true, rows, c, c, cur, ld, cx.Li, c, nxt, ld, false, 1.0f, 0.0f, cx.ws,
+                             cx.ws_elems, cx.s));
+        float* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    *out = cur;
+    return 0;
+}
+
+size_t max_ws(size_t (*f)(int64_t, int64_t, int64_t), std::initializer_list<std::array<int64_t, 3>> shapes) {
     size_t mx = 0;
     for (auto& sh : shapes) {
-        size_t e = gemm_workspace_elems(sh[0], sh[1], sh[2]);
+        size_t e = f(sh[0], sh[1], sh[2]);
         if (e > mx) mx = e;
     }
     return mx;
 }
 
-// Device buffers of one rqlp_factor call (FP64 path).
-struct FactorBufs {
-    double* Om;
-    double* Y;
-    double* Y2;
-    double* Z;
-    double* Z2;
-    double* B;
+// FP64 buffers of the small stage (CPQR of B, second factorisation, Q_B / P_B).
+struct SmallBufs {
+    double* B;      // l x n
+    double* Z;      // n x l   R0^T
+    double* Z2;     // n x l
     double* gws;
     size_t gws_elems;
     OrthoScratch o;
@@ -105,14 +148,14 @@ struct FactorBufs {
     int32_t* info;
 };
 
-void carve_factor(Arena& ar, int64_t m, int64_t n, int64_t l, bool need_omega, FactorBufs* f) {
-    f->Om = need_omega ? ar.take<double>(n * l) : nullptr;
-    f->Y = ar.take<double>(m * l);
-    f->Y2 = ar.take<double>(m * l);
+// extra FP64 product shapes (M, N, K) of the caller that share gws
+void carve_small(Arena& ar, int64_t n, int64_t l, std::initializer_list<std::array<int64_t, 3>> extra, SmallBufs* f) {
+    f->B = ar.take<double>(l * n);
     f->Z = ar.take<double>(n * l);
     f->Z2 = ar.take<double>(n * l);
-    f->B = ar.take<double>(l * n);
-    f->gws_elems = max_gemm_ws(m, n, l);
+    size_t e = max_ws(gemm_workspace_elems, {{l, l, n}, {n, l, l}, {l, l, l}});
+    size_t e2 = max_ws(gemm_workspace_elems, extra);
+    f->gws_elems = e > e2 ? e : e2;
     f->gws = ar.take<double>(f->gws_elems);
     carve_ortho(ar, l, &f->o);
     cpqr_carve(ar, l, n, &f->cs);
@@ -134,122 +177,14 @@ void carve_factor(Arena& ar, int64_t m, int64_t n, int64_t l, bool need_omega, F
     f->info = ar.take<int32_t>(1);
 }
 
-bool valid_precision(int p) { return p >= RQLP_F64 && p <= RQLP_MIXED_BF16X3; }
-
-int check_factor_args(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int64_t p, int q, int d, int b,
-                      int precision) {
-    if (m < 1) return -3;
-    if (n < 1 || n > m) return -4;
-    if (lda < m) return -2;
-    if (k < 2) return -5;
-    if (p < 2 || k + p > n) return -6;
-    if (q < 0) return -7;
-    if (d < 0) return -8;
-    if (b < 0 || (b > 0 && d != 0)) return -9;
-    if (!valid_precision(precision)) return -10;
-    if (A == nullptr) return -1;
-    return 0;
-}
-
-// Aligns the caller's workspace pointer to 256 bytes.
-Arena arena_for(void* work, size_t bytes) {
-    uintptr_t a = (uintptr_t)work;
-    uintptr_t al = (a + 255) & ~uintptr_t(255);
-    size_t lost = (size_t)(al - a);
-    return Arena(work ? (void*)al : nullptr, bytes > lost ? bytes - lost : 0);
-}
-
-}  // namespace
-
-extern "C" {
-
-const char* rqlp_version(void) { return "rqlp-gfx950 0.1"; }
-
-const char* rqlp_status_string(int status) {
-    if (status == RQLP_OK) return "success";
-    if (status == RQLP_E_WORKSPACE) return "workspace too small";
-    if (status == RQLP_E_HIP) return "HIP runtime or launch error";
-    if (status == RQLP_E_UNSUPPORTED) return "arguments valid but not supported by this build";
-    if (status < 0 && status > -100) return "invalid argument (see the argument index -status)";
-    return "unknown status";
-}
-
-int rqlp_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p, int q, int d, int b, int precision,
-                        size_t* bytes) {
-    int st = check_factor_args((const void*)1, m, m, n, k, p, q, d, b, precision);
-    if (st) return st;
-    if (!bytes) return -9;
-    Arena ar(nullptr, 0);
-    FactorBufs f;
-    carve_factor(ar, m, n, k + p, true, &f);
-    *bytes = ar.used + 256;
-    return 0;
-}
-
-int rqlp_generate_omega(int64_t n, int64_t l, uint64_t seed, int precision, void* Omega, int64_t ldo,
-                        void* stream) {
-    if (n < 0) return -1;
-    if (l < 0) return -2;
-    if (!valid_precision(precision)) return -4;
-    if (Omega == nullptr && n * l > 0) return -5;
-    if (ldo < (n > 1 ? n : 1)) return -6;
-    return generate_omega(n, l, seed, precision, Omega, ldo, (hipStream_t)stream);
-}
-
-int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int64_t p, int q, int d, int b,
-                int precision, uint64_t seed, const void* Omega, int64_t ldo, void* Q, int64_t ldq, double* T,
-                int64_t ldt, void* P, int64_t ldp, int64_t* piv0, int64_t* piv1, double* lvals, int32_t* info,
-                char* uplo, void* work, size_t work_bytes, void* stream) {
-    RQLP_TRY(check_factor_args(A, lda, m, n, k, p, q, d, b, precision));
-    const int64_t l = k + p;
-    if (Omega && ldo < n) return -13;
-    if (!Q) return -14;
-    if (ldq < m) return -15;
-    if (!T) return -16;
-    if (ldt < l) return -17;
-    if (!P) return -18;
-    if (ldp < n) return -19;
-    if (!work) return -25;
-    if (precision != RQLP_F64 || b != 0) return RQLP_E_UNSUPPORTED;
-
-    hipStream_t s = (hipStream_t)stream;
-    Arena ar = arena_for(work, work_bytes);
-    FactorBufs f;
-    carve_factor(ar, m, n, l, Omega == nullptr, &f);
-    if (!ar.ok()) return RQLP_E_WORKSPACE;
-    {
-        CpqrPlan pl;
-        RQLP_TRY(cpqr_plan(l, n, &pl));
-        RQLP_TRY(cpqr_plan(l, l, &pl));
-    }
-    const double* Ad = (const double*)A;
-    int32_t* inf = info ? info : f.info;
-    RQLP_TRY(fill_zero_bytes(inf, sizeof(int32_t), s));
-
-    Ctx cx{s, inf, f.gws, f.gws_elems, f.o};
-
-    // ---- range finder: Omega, Y = A Omega, V = qr(Y) (+ q subspace iterations) ----
-    const double* Om = (const double*)Omega;
-    int64_t ldom = ldo;
-    if (!Om) {
-        RQLP_TRY(generate_omega(n, l, seed, RQLP_F64, f.Om, n, s));
-        Om = f.Om;
-        ldom = n;
-    }
-    RQLP_TRY(gemm<double>(false, false, m, l, n, Ad, lda, Om, ldom, f.Y, m, false, 1.0, 0.0, f.gws, f.gws_elems, s));
-    double* V = nullptr;
-    RQLP_TRY(cholqr2(cx, m, l, f.Y, f.Y2, m, nullptr, &V));
-    for (int it = 0; it < q; ++it) {
-        RQLP_TRY(gemm<double>(true, false, n, l, m, Ad, lda, V, m, f.Z, n, false, 1.0, 0.0, f.gws, f.gws_elems, s));
-        double* W = nullptr;
-        RQLP_TRY(cholqr2(cx, n, l, f.Z, f.Z2, n, nullptr, &W));
-        double* ydst = (V == f.Y) ? f.Y2 : f.Y;
-        RQLP_TRY(gemm<double>(false, false, m, l, n, Ad, lda, W, n, ydst, m, false, 1.0, 0.0, f.gws, f.gws_elems, s));
-        double* other = (ydst == f.Y) ? f.Y2 : f.Y;
-        RQLP_TRY(cholqr2(cx, m, l, ydst, other, m, nullptr, &V));
-    }
-    // ---- projection B = V^T A (as (A^T V)^T, stored l x n) ----
-    RQLP_TRY(gemm<double>(true, false, n, l, m, Ad, lda, V, m, f.B, l, true, 1.0, 0.0, f.gws, f.gws_elems, s));
+// Algorithm 2.1 steps 5-6 (d = 0) or Algorithm 2.2 steps 5-8 (d >= 1) on
+// the l x n matrix f.B: first CPQR B Pi0 = Q0 R0, then the second
+// factorisation of R0^T.  Writes T (l x l, triangle *tri), P_B (n x l, FP64,
+// into Pd) and returns Q_B (l x l, FP64) in *QB; B = Q_B T P_B^T.
+int qlp_of_B(Ctx& cx, SmallBufs& f, int64_t l, int64_t n, int d, double* Pd, int64_t ldpd, double* T, int64_t ldt,
+             char* tri_out, double** QB) {
+    hipStream_t s = cx.s;
+    int32_t* inf = cx.info;
     // ---- first CPQR: B Pi0 = Q0 R0; R0^T kept in original column order (n x l) ----
     RQLP_TRY(cpqr(f.B, l, l, n, f.cs, f.piv0, f.Vh0, l, f.beta0, nullptr, l, f.Z, n, inf, s));
     // ---- second stage: R0^T = Qt Rtil (CholeskyQR2), Rtil^T kept ----
@@ -261,8 +196,8 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
         RQLP_TRY(transpose_matrix(l, l, f.RtT, l, f.Rtil, l, 0, s));
         RQLP_TRY(cpqr(f.Rtil, l, l, l, f.cs, f.piv1, f.Vh1, l, f.beta1, f.Lt, l, nullptr, 1, inf, s));
         RQLP_TRY(apply_householder(l, l, f.Vh1, l, f.beta1, nullptr, 0, nullptr, l, f.Mr, l, s));
-        RQLP_TRY(gemm<double>(false, false, n, l, l, Qt, n, f.Mr, l, (double*)P, ldp, false, 1.0, 0.0, f.gws,
-                              f.gws_elems, s));
+        RQLP_TRY(gemm<double>(false, false, n, l, l, Qt, n, f.Mr, l, Pd, ldpd, false, 1.0, 0.0, f.gws, f.gws_elems,
+                              s));
         // Q0 Pi1
         RQLP_TRY(apply_householder(l, l, f.Vh0, l, f.beta0, nullptr, 0, f.piv1, l, f.Ml, l, s));
         RQLP_TRY(transpose_matrix(l, l, f.Lt, l, T, ldt, 'L', s));
@@ -291,10 +226,10 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
             RprevT = RnewT;
         }
         if (have_right)
-            RQLP_TRY(gemm<double>(false, false, n, l, l, Qt, n, f.Mr, l, (double*)P, ldp, false, 1.0, 0.0, f.gws,
+            RQLP_TRY(gemm<double>(false, false, n, l, l, Qt, n, f.Mr, l, Pd, ldpd, false, 1.0, 0.0, f.gws,
                                   f.gws_elems, s));
         else
-            RQLP_TRY(copy_matrix(n, l, Qt, n, (double*)P, ldp, s));
+            RQLP_TRY(copy_matrix(n, l, Qt, n, Pd, ldpd, s));
         // Q0 * (product of even-index inner factors)
         RQLP_TRY(apply_householder(l, l, f.Vh0, l, f.beta0, have_left ? f.Ml : nullptr, l, nullptr, l, f.Xi, l,
                                    s));
@@ -308,8 +243,289 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
             tri = 'U';
         }
     }
-    // ---- assembly: Q = V (Q_B) ----
-    RQLP_TRY(gemm<double>(false, false, m, l, l, V, m, f.Ml, l, (double*)Q, ldq, false, 1.0, 0.0, f.gws, f.gws_elems, s));
+    *QB = f.Ml;
+    *tri_out = tri;
+    return 0;
+}
+
+// FP64 range finder buffers.
+struct RangeBufs64 {
+    double* Om;
+    double* Y;
+    double* Y2;
+};
+
+void carve_range64(Arena& ar, int64_t m, int64_t n, int64_t l, bool need_omega, RangeBufs64* r) {
+    r->Om = need_omega ? ar.take<double>(n * l) : nullptr;
+    r->Y = ar.take<double>(m * l);
+    r->Y2 = ar.take<double>(m * l);
+}
+
+// Mixed-precision range finder buffers.
+struct RangeBufsLP {
+    unsigned short* Ac;     // m x n, column-major 16-bit copy of A (FP16: A D^{-1})
+    unsigned short* Ar;     // n x m, i.e. A row-major
+    unsigned short* Aclo;   // bf16x3 remainders (else NULL)
+    unsigned short* Arlo;
+    int* colexp;            // n (FP16 only)
+    int* gexp;              // 1
+    float* Om;              // n x l (generated test matrix)
+    unsigned short* X16;    // max(m, n) x l 16-bit panel (Omega, W or V)
+    unsigned short* X16lo;
+    float* Y;               // m x l
+    float* Y2;
+    float* Z;               // n x l
+    float* Z2;
+    float* lpws;
+    size_t lpws_elems;
+    float* fws;
+    size_t fws_elems;
+    float* G;               // l x l
+    float* Li;              // l x l
+    float* QB;              // l x l
+    double* Pd;             // n x l
+    int32_t* shifted;       // 1 word
+};
+
+void carve_range_lp(Arena& ar, int64_t m, int64_t n, int64_t l, int precision, bool need_omega, RangeBufsLP* r) {
+    const bool x3 = precision == RQLP_MIXED_BF16X3;
+    r->Ac = ar.take<unsigned short>(m * n);
+    r->Ar = ar.take<unsigned short>(m * n);
+    r->Aclo = x3 ? ar.take<unsigned short>(m * n) : nullptr;
+    r->Arlo = x3 ? ar.take<unsigned short>(m * n) : nullptr;
+    r->colexp = ar.take<int>(n);
+    r->gexp = ar.take<int>(1);
+    r->Om = need_omega ? ar.take<float>(n * l) : nullptr;
+    const int64_t mx = m > n ? m : n;
+    r->X16 = ar.take<unsigned short>(mx * l);
+    r->X16lo = x3 ? ar.take<unsigned short>(mx * l) : nullptr;
+    r->Y = ar.take<float>(m * l);
+    r->Y2 = ar.take<float>(m * l);
+    r->Z = ar.take<float>(n * l);
+    r->Z2 = ar.take<float>(n * l);
+    r->lpws_elems = max_ws(gemm_lp_workspace_elems, {{m, l, n}, {n, l, m}});
+    r->lpws = ar.take<float>(r->lpws_elems);
+    r->fws_elems = max_ws(gemm_workspace_elems, {{l, l, m}, {l, l, n}, {m, l, l}, {n, l, l}});
+    r->fws = ar.take<float>(r->fws_elems);
+    r->G = ar.take<float>(l * l);
+    r->Li = ar.take<float>(l * l);
+    r->QB = ar.take<float>(l * l);
+    r->Pd = ar.take<double>(n * l);
+    r->shifted = ar.take<int32_t>(1);
+}
+
+bool valid_precision(int p) { return p >= RQLP_F64 && p <= RQLP_MIXED_BF16X3; }
+bool is_mixed(int p) { return p == RQLP_MIXED_BF16 || p == RQLP_MIXED_FP16 || p == RQLP_MIXED_BF16X3; }
+
+int check_factor_args(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int64_t p, int q, int d, int b,
+                      int precision) {
+    if (m < 1) return -3;
+    if (n < 1 || n > m) return -4;
+    if (lda < m) return -2;
+    if (k < 2) return -5;
+    if (p < 2 || k + p > n) return -6;
+    if (q < 0) return -7;
+    if (d < 0) return -8;
+    if (b < 0 || (b > 0 && d != 0)) return -9;
+    if (!valid_precision(precision)) return -10;
+    if (A == nullptr) return -1;
+    return 0;
+}
+
+// Workspace layout of one rqlp_factor call (shared by the size query and
+// the call itself).
+struct FactorLayout {
+    RangeBufs64 r64;
+    RangeBufsLP rlp;
+    SmallBufs sm;
+};
+
+void carve_factor(Arena& ar, int64_t m, int64_t n, int64_t l, int precision, bool need_omega, FactorLayout* L) {
+    if (precision == RQLP_F64) {
+        carve_range64(ar, m, n, l, need_omega, &L->r64);
+        carve_small(ar, n, l, {{m, l, n}, {n, l, m}, {l, l, m}, {m, l, l}, {l, n, m}}, &L->sm);
+    } else {
+        carve_range_lp(ar, m, n, l, precision, need_omega, &L->rlp);
+        carve_small(ar, n, l, {}, &L->sm);
+    }
+}
+
+// Aligns the caller's workspace pointer to 256 bytes.
+Arena arena_for(void* work, size_t bytes) {
+    uintptr_t a = (uintptr_t)work;
+    uintptr_t al = (a + 255) & ~uintptr_t(255);
+    size_t lost = (size_t)(al - a);
+    return Arena(work ? (void*)al : nullptr, bytes > lost ? bytes - lost : 0);
+}
+
+// FP64 range finder (Algorithm 2.1 steps 1-3 with q subspace iterations) and
+// projection B = V^T A (step 4).  Returns V (m x l) in *Vout.
+int range_and_project_f64(Ctx& cx, RangeBufs64& r, SmallBufs& f, const double* A, int64_t lda, int64_t m, int64_t n,
+                          int64_t l, int q, uint64_t seed, const double* Om, int64_t ldom, double** Vout) {
+    hipStream_t s = cx.s;
+    if (!Om) {
+        RQLP_TRY(generate_omega(n, l, seed, RQLP_F64, r.Om, n, s));
+        Om = r.Om;
+        ldom = n;
+    }
+    RQLP_TRY(gemm<double>(false, false, m, l, n, A, lda, Om, ldom, r.Y, m, false, 1.0, 0.0, f.gws, f.gws_elems, s));
+    double* V = nullptr;
+    RQLP_TRY(cholqr2(cx, m, l, r.Y, r.Y2, m, nullptr, &V));
+    for (int it = 0; it < q; ++it) {
+        // Z = A^T V into the small stage's n x l buffers (free until the CPQR)
+        RQLP_TRY(gemm<double>(true, false, n, l, m, A, lda, V, m, f.Z, n, false, 1.0, 0.0, f.gws, f.gws_elems, s));
+        double* W = nullptr;
+        RQLP_TRY(cholqr2(cx, n, l, f.Z, f.Z2, n, nullptr, &W));
+        double* ydst = (V == r.Y) ? r.Y2 : r.Y;
+        RQLP_TRY(gemm<double>(false, false, m, l, n, A, lda, W, n, ydst, m, false, 1.0, 0.0, f.gws, f.gws_elems, s));
+        double* other = (ydst == r.Y) ? r.Y2 : r.Y;
+        RQLP_TRY(cholqr2(cx, m, l, ydst, other, m, nullptr, &V));
+    }
+    // B = V^T A, computed as (A^T V)^T and stored l x n
+    RQLP_TRY(gemm<double>(true, false, n, l, m, A, lda, V, m, f.B, l, true, 1.0, 0.0, f.gws, f.gws_elems, s));
+    *Vout = V;
+    return 0;
+}
+
+// Mixed-precision range finder and projection: the 2q + 2 passes over A run
+// as 16-bit MFMA products (FP32 accumulation), the panels are orthonormalised
+// by FP32 CholeskyQR2, and B = V^T A is widened to FP64 for the small stage.
+// Returns V (m x l, FP32) in *Vout.
+int range_and_project_lp(Ctx32& c32, RangeBufsLP& r, SmallBufs& f, int kind, const float* A, int64_t lda,
+                         int64_t m, int64_t n, int64_t l, int q, uint64_t seed, const float* Om, int64_t ldom,
+                         float** Vout) {
+    hipStream_t s = c32.s;
+    const bool fp16 = kind == RQLP_MIXED_FP16;
+    const int* cexp = fp16 ? r.colexp : nullptr;
+    const int* gexp = fp16 ? r.gexp : nullptr;
+    if (fp16) RQLP_TRY(column_exponents(m, n, A, lda, r.colexp, r.gexp, s));
+    RQLP_TRY(cast_to_lp(kind, m, n, A, lda, r.Ac, r.Aclo, m, false, nullptr, cexp, nullptr, s));
+    RQLP_TRY(cast_to_lp(kind, m, n, A, lda, r.Ar, r.Arlo, n, true, nullptr, cexp, nullptr, s));
+    if (!Om) {
+        RQLP_TRY(generate_omega(n, l, seed, kind, r.Om, n, s));
+        Om = r.Om;
+        ldom = n;
+    }
+    // Y = A Omega  (FP16: (A D^-1)(2^-g D Omega) 2^g)
+    RQLP_TRY(cast_to_lp(kind, n, l, Om, ldom, r.X16, r.X16lo, n, false, cexp, nullptr, gexp, s));
+    RQLP_TRY(gemm_lp<float>(kind, m, l, n, r.Ar, r.Arlo, n, r.X16, r.X16lo, n, r.Y, m, false, nullptr, gexp, r.lpws,
+                            r.lpws_elems, s));
+    float* V = nullptr;
+    RQLP_TRY(cholqr_f32(c32, m, l, r.Y, r.Y2, m, &V));
+    for (int it = 0; it < q; ++it) {
+        // Z = A^T V  (FP16: D (A D^-1)^T V)
+        RQLP_TRY(cast_to_lp(kind, m, l, V, m, r.X16, r.X16lo, m, false, nullptr, nullptr, nullptr, s));
+        RQLP_TRY(gemm_lp<float>(kind, n, l, m, r.Ac, r.Aclo, m, r.X16, r.X16lo, m, r.Z, n, false, cexp, nullptr,
+                                r.lpws, r.lpws_elems, s));
+        float* W = nullptr;
+        RQLP_TRY(cholqr_f32(c32, n, l, r.Z, r.Z2, n, &W));
+        // Y = A W
+        RQLP_TRY(cast_to_lp(kind, n, l, W, n, r.X16, r.X16lo, n, false, cexp, nullptr, gexp, s));
+        float* ydst = (V == r.Y) ? r.Y2 : r.Y;
+        RQLP_TRY(gemm_lp<float>(kind, m, l, n, r.Ar, r.Arlo, n, r.X16, r.X16lo, n, ydst, m, false, nullptr, gexp,
+                                r.lpws, r.lpws_elems, s));
+        float* other = (ydst == r.Y) ? r.Y2 : r.Y;
+        RQLP_TRY(cholqr_f32(c32, m, l, ydst, other, m, &V));
+    }
+    // B = V^T A = (A^T V)^T, FP32 accumulation, stored l x n in FP64
+    RQLP_TRY(cast_to_lp(kind, m, l, V, m, r.X16, r.X16lo, m, false, nullptr, nullptr, nullptr, s));
+    RQLP_TRY(gemm_lp<double>(kind, n, l, m, r.Ac, r.Aclo, m, r.X16, r.X16lo, m, f.B, l, true, cexp, nullptr, r.lpws,
+                             r.lpws_elems, s));
+    *Vout = V;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rqlp_version(void) { return "rqlp-gfx950 0.1"; }
+
+const char* rqlp_status_string(int status) {
+    if (status == RQLP_OK) return "success";
+    if (status == RQLP_E_WORKSPACE) return "workspace too small";
+    if (status == RQLP_E_HIP) return "HIP runtime or launch error";
+    if (status == RQLP_E_UNSUPPORTED) return "arguments valid but not supported by this build";
+    if (status < 0 && status > -100) return "invalid argument (see the argument index -status)";
+    return "unknown status";
+}
+
+int rqlp_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p, int q, int d, int b, int precision,
+                        size_t* bytes) {
+    int st = check_factor_args((const void*)1, m, m, n, k, p, q, d, b, precision);
+    if (st) return st;
+    if (!bytes) return -9;
+    Arena ar(nullptr, 0);
+    FactorLayout L;
+    carve_factor(ar, m, n, k + p, precision, true, &L);
+    *bytes = ar.used + 256;
+    return 0;
+}
+
+int rqlp_generate_omega(int64_t n, int64_t l, uint64_t seed, int precision, void* Omega, int64_t ldo,
+                        void* stream) {
+    if (n < 0) return -1;
+    if (l < 0) return -2;
+    if (!valid_precision(precision)) return -4;
+    if (Omega == nullptr && n * l > 0) return -5;
+    if (ldo < (n > 1 ? n : 1)) return -6;
+    return generate_omega(n, l, seed, precision, Omega, ldo, (hipStream_t)stream);
+}
+
+int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int64_t p, int q, int d, int b,
+                int precision, uint64_t seed, const void* Omega, int64_t ldo, void* Q, int64_t ldq, double* T,
+                int64_t ldt, void* P, int64_t ldp, int64_t* piv0, int64_t* piv1, double* lvals, int32_t* info,
+                char* uplo, void* work, size_t work_bytes, void* stream) {
+    RQLP_TRY(check_factor_args(A, lda, m, n, k, p, q, d, b, precision));
+    const int64_t l = k + p;
+    if (Omega && ldo < n) return -13;
+    if (!Q) return -14;
+    if (ldq < m) return -15;
+    if (!T) return -16;
+    if (ldt < l) return -17;
+    if (!P) return -18;
+    if (ldp < n) return -19;
+    if (!work) return -25;
+    if (b != 0 || precision == RQLP_F32) return RQLP_E_UNSUPPORTED;
+
+    hipStream_t s = (hipStream_t)stream;
+    Arena ar = arena_for(work, work_bytes);
+    FactorLayout Lay;
+    carve_factor(ar, m, n, l, precision, Omega == nullptr, &Lay);
+    if (!ar.ok()) return RQLP_E_WORKSPACE;
+    SmallBufs& f = Lay.sm;
+    {
+        CpqrPlan pl;
+        RQLP_TRY(cpqr_plan(l, n, &pl));
+        RQLP_TRY(cpqr_plan(l, l, &pl));
+    }
+    int32_t* inf = info ? info : f.info;
+    RQLP_TRY(fill_zero_bytes(inf, sizeof(int32_t), s));
+    Ctx cx{s, inf, f.gws, f.gws_elems, f.o};
+    char tri = 'L';
+    double* QB = nullptr;
+
+    if (precision == RQLP_F64) {
+        double* V = nullptr;
+        RQLP_TRY(range_and_project_f64(cx, Lay.r64, f, (const double*)A, lda, m, n, l, q, seed,
+                                       (const double*)Omega, ldo, &V));
+        RQLP_TRY(qlp_of_B(cx, f, l, n, d, (double*)P, ldp, T, ldt, &tri, &QB));
+        // assembly: Q = V Q_B
+        RQLP_TRY(gemm<double>(false, false, m, l, l, V, m, QB, l, (double*)Q, ldq, false, 1.0, 0.0, f.gws,
+                              f.gws_elems, s));
+    } else {
+        RangeBufsLP& r = Lay.rlp;
+        Ctx32 c32{s, inf, r.fws, r.fws_elems, r.G, r.Li, f.o.L1, f.o.Li, r.shifted};
+        float* V = nullptr;
+        RQLP_TRY(range_and_project_lp(c32, r, f, precision, (const float*)A, lda, m, n, l, q, seed,
+                                      (const float*)Omega, ldo, &V));
+        RQLP_TRY(qlp_of_B(cx, f, l, n, d, r.Pd, n, T, ldt, &tri, &QB));
+        // assembly in FP32: P = P_B, Q = V Q_B
+        RQLP_TRY((cast_matrix<double, float>(n, l, r.Pd, n, (float*)P, ldp, s)));
+        RQLP_TRY((cast_matrix<double, float>(l, l, QB, l, r.QB, l, s)));
+        RQLP_TRY(gemm<float>(false, false, m, l, l, V, m, r.QB, l, (float*)Q, ldq, false, 1.0f, 0.0f, r.fws,
+                             r.fws_elems, s));
+    }
     RQLP_TRY(finish_lvals(l, T, ldt, lvals, inf, s));
     if (piv0) RQLP_TRY(copy_i64(l, f.piv0, piv0, s));
     if (piv1) RQLP_TRY(copy_i64(l, d == 0 ? f.piv1 : nullptr, piv1, s));
@@ -318,14 +534,49 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
 }
 
 // ---- building blocks ----
+namespace {
+// scratch of one 16-bit product over A (m x n) with a c-column panel
+struct LpOp {
+    unsigned short* Ah;
+    unsigned short* Al;
+    unsigned short* Xh;
+    unsigned short* Xl;
+    int* colexp;
+    int* gexp;
+    float* ws;
+    size_t ws_elems;
+};
+void carve_lp_op(Arena& ar, int64_t m, int64_t n, int64_t c, int precision, LpOp* o) {
+    const bool x3 = precision == RQLP_MIXED_BF16X3;
+    const int64_t mx = m > n ? m : n;
+    o->Ah = ar.take<unsigned short>(m * n);
+    o->Al = x3 ? ar.take<unsigned short>(m * n) : nullptr;
+    o->Xh = ar.take<unsigned short>(mx * c);
+    o->Xl = x3 ? ar.take<unsigned short>(mx * c) : nullptr;
+    o->colexp = ar.take<int>(n > 0 ? n : 1);
+    o->gexp = ar.take<int>(1);
+    o->ws_elems = max_ws(gemm_lp_workspace_elems, {{m, c, n}, {n, c, m}});
+    o->ws = ar.take<float>(o->ws_elems);
+}
+bool gemm_precision(int p) { return p == RQLP_F64 || p == RQLP_F32 || is_mixed(p); }
+}  // namespace
+
 int rqlp_gemm_workspace(int64_t m, int64_t n, int64_t c, int precision, size_t* bytes) {
     if (m < 0) return -1;
     if (n < 0) return -2;
     if (c < 0) return -3;
-    if (precision != RQLP_F64 && precision != RQLP_F32) return -4;
+    if (!gemm_precision(precision)) return -4;
     if (!bytes) return -5;
-    size_t e1 = gemm_workspace_elems(m, c, n), e2 = gemm_workspace_elems(n, c, m);
-    *bytes = (e1 > e2 ? e1 : e2) * (precision == RQLP_F64 ? 8 : 4) + 256;
+    Arena ar(nullptr, 0);
+    if (is_mixed(precision)) {
+        LpOp o;
+        carve_lp_op(ar, m, n, c, precision, &o);
+    } else {
+        const size_t e = max_ws(gemm_workspace_elems, {{m, c, n}, {n, c, m}});
+        if (precision == RQLP_F64) ar.take<double>(e);
+        else ar.take<float>(e);
+    }
+    *bytes = ar.used + 256;
     return 0;
 }
 
@@ -337,18 +588,32 @@ int rqlp_sketch(const void* A, int64_t lda, int64_t m, int64_t n, const void* X,
     if (ldx < (n > 1 ? n : 1)) return -6;
     if (c < 0) return -7;
     if (ldy < (m > 1 ? m : 1)) return -9;
-    if (precision != RQLP_F64 && precision != RQLP_F32) return -10;
+    if (!gemm_precision(precision)) return -10;
     if (m * n * c > 0 && (!A || !X || !Y)) return !A ? -1 : (!X ? -5 : -8);
+    if (m * c == 0) return 0;
     Arena ar = arena_for(work, work_bytes);
     hipStream_t s = (hipStream_t)stream;
+    if (is_mixed(precision)) {
+        LpOp o;
+        carve_lp_op(ar, m, n, c, precision, &o);
+        if (!ar.ok()) return RQLP_E_WORKSPACE;
+        const bool fp16 = precision == RQLP_MIXED_FP16;
+        const float* Af = (const float*)A;
+        if (fp16) RQLP_TRY(column_exponents(m, n, Af, lda, o.colexp, o.gexp, s));
+        RQLP_TRY(cast_to_lp(precision, m, n, Af, lda, o.Ah, o.Al, n, true, nullptr, fp16 ? o.colexp : nullptr,
+                            nullptr, s));
+        RQLP_TRY(cast_to_lp(precision, n, c, (const float*)X, ldx, o.Xh, o.Xl, n, false, fp16 ? o.colexp : nullptr,
+                            nullptr, fp16 ? o.gexp : nullptr, s));
+        return gemm_lp<float>(precision, m, c, n, o.Ah, o.Al, n, o.Xh, o.Xl, n, (float*)Y, ldy, false, nullptr,
+                              fp16 ? o.gexp : nullptr, o.ws, o.ws_elems, s);
+    }
+    size_t e = gemm_workspace_elems(m, c, n);
     if (precision == RQLP_F64) {
-        size_t e = gemm_workspace_elems(m, c, n);
         double* ws = ar.take<double>(e);
         if (!ar.ok()) return RQLP_E_WORKSPACE;
         return gemm<double>(false, false, m, c, n, (const double*)A, lda, (const double*)X, ldx, (double*)Y, ldy, false,
                             1.0, 0.0, ws, e, s);
     }
-    size_t e = gemm_workspace_elems(m, c, n);
     float* ws = ar.take<float>(e);
     if (!ar.ok()) return RQLP_E_WORKSPACE;
     return gemm<float>(false, false, m, c, n, (const float*)A, lda, (const float*)X, ldx, (float*)Y, ldy, false, 1.0f,
@@ -363,10 +628,25 @@ int rqlp_project(const void* A, int64_t lda, int64_t m, int64_t n, const void* V
     if (ldv < (m > 1 ? m : 1)) return -6;
     if (c < 0) return -7;
     if (ldb < (c > 1 ? c : 1)) return -9;
-    if (precision != RQLP_F64 && precision != RQLP_F32) return -10;
+    if (!gemm_precision(precision)) return -10;
     if (m * n * c > 0 && (!A || !V || !B)) return !A ? -1 : (!V ? -5 : -8);
+    if (n * c == 0) return 0;
     Arena ar = arena_for(work, work_bytes);
     hipStream_t s = (hipStream_t)stream;
+    if (is_mixed(precision)) {
+        LpOp o;
+        carve_lp_op(ar, m, n, c, precision, &o);
+        if (!ar.ok()) return RQLP_E_WORKSPACE;
+        const bool fp16 = precision == RQLP_MIXED_FP16;
+        const float* Af = (const float*)A;
+        if (fp16) RQLP_TRY(column_exponents(m, n, Af, lda, o.colexp, o.gexp, s));
+        RQLP_TRY(cast_to_lp(precision, m, n, Af, lda, o.Ah, o.Al, m, false, nullptr, fp16 ? o.colexp : nullptr,
+                            nullptr, s));
+        RQLP_TRY(cast_to_lp(precision, m, c, (const float*)V, ldv, o.Xh, o.Xl, m, false, nullptr, nullptr, nullptr,
+                            s));
+        return gemm_lp<float>(precision, n, c, m, o.Ah, o.Al, m, o.Xh, o.Xl, m, (float*)B, ldb, true,
+                              fp16 ? o.colexp : nullptr, nullptr, o.ws, o.ws_elems, s);
+    }
     size_t e = gemm_workspace_elems(n, c, m);
     if (precision == RQLP_F64) {
         double* ws = ar.take<double>(e);
@@ -378,6 +658,55 @@ int rqlp_project(const void* A, int64_t lda, int64_t m, int64_t n, const void* V
     if (!ar.ok()) return RQLP_E_WORKSPACE;
     return gemm<float>(true, false, n, c, m, (const float*)A, lda, (const float*)V, ldv, (float*)B, ldb, true, 1.0f, 0.0f,
                        ws, e, s);
+}
+
+int rqlp_encode(const float* A, int64_t lda, int64_t m, int64_t n, int precision, int transpose, uint16_t* Ahi,
+                uint16_t* Alo, int64_t ldh, int32_t* colexp, int32_t* gexp, void* stream) {
+    if (m < 0) return -3;
+    if (n < 0) return -4;
+    if (lda < (m > 1 ? m : 1)) return -2;
+    if (!is_mixed(precision)) return -5;
+    const int64_t rows_h = transpose ? n : m;
+    if (ldh < (rows_h > 1 ? rows_h : 1)) return -9;
+    if (m * n == 0) return 0;
+    if (!A) return -1;
+    if (!Ahi) return -7;
+    if ((Alo != nullptr) != (precision == RQLP_MIXED_BF16X3)) return -8;
+    const bool fp16 = precision == RQLP_MIXED_FP16;
+    if (fp16 && !colexp) return -10;
+    if (fp16 && !gexp) return -11;
+    hipStream_t s = (hipStream_t)stream;
+    if (fp16) RQLP_TRY(column_exponents(m, n, A, lda, colexp, gexp, s));
+    return cast_to_lp(precision, m, n, A, lda, (unsigned short*)Ahi, (unsigned short*)Alo, ldh, transpose != 0,
+                      nullptr, fp16 ? colexp : nullptr, nullptr, s);
+}
+
+int rqlp_project_encoded(const uint16_t* Ahi, const uint16_t* Alo, int64_t ldh, const int32_t* colexp, int64_t m,
+                         int64_t n, const float* V, int64_t ldv, int64_t c, float* B, int64_t ldb, int precision,
+                         void* work, size_t work_bytes, void* stream) {
+    if (ldh < (m > 1 ? m : 1)) return -3;
+    if (m < 0) return -5;
+    if (n < 0) return -6;
+    if (ldv < (m > 1 ? m : 1)) return -8;
+    if (c < 0) return -9;
+    if (ldb < (c > 1 ? c : 1)) return -11;
+    if (!is_mixed(precision)) return -12;
+    if (n * c == 0) return 0;
+    if (!Ahi) return -1;
+    if ((Alo != nullptr) != (precision == RQLP_MIXED_BF16X3)) return -2;
+    if (precision == RQLP_MIXED_FP16 && !colexp) return -4;
+    if (!V) return -7;
+    if (!B) return -10;
+    Arena ar = arena_for(work, work_bytes);
+    unsigned short* Vh = ar.take<unsigned short>(m * c);
+    unsigned short* Vl = precision == RQLP_MIXED_BF16X3 ? ar.take<unsigned short>(m * c) : nullptr;
+    const size_t e = gemm_lp_workspace_elems(n, c, m);
+    float* ws = ar.take<float>(e);
+    if (!ar.ok()) return RQLP_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    RQLP_TRY(cast_to_lp(precision, m, c, V, ldv, Vh, Vl, m, false, nullptr, nullptr, nullptr, s));
+    return gemm_lp<float>(precision, n, c, m, (const unsigned short*)Ahi, (const unsigned short*)Alo, ldh, Vh, Vl, m,
+                          B, ldb, true, precision == RQLP_MIXED_FP16 ? colexp : nullptr, nullptr, ws, e, s);
 }
 
 int rqlp_orthonormalize_workspace(int64_t m, int64_t c, size_t* bytes) {

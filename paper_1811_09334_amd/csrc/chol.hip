@@ -49,10 +49,13 @@ size_t chol_inv_lds_bytes(int64_t c) {
            (size_t)(2 * CH_NB * CH_PS + ch_prows_alloc(c) * CH_PS + CH_NB * (ch_xcols(c) + 1));
 }
 
-__global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const double* __restrict__ G, int64_t ldg,
+template <typename TG>
+__global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const TG* __restrict__ G, int64_t ldg,
                                                         double shift_scale, double* __restrict__ W,
-                                                        double* __restrict__ X, int64_t ldw, int32_t* info,
-                                                        int prows, int xcols) {
+                                                        double* __restrict__ X, float* __restrict__ Xf,
+                                                        int64_t ldw, int32_t* info, int prows, int xcols,
+                                                        const int32_t* __restrict__ run_flag,
+                                                        int32_t* __restrict__ shifted_out) {
     extern __shared__ double lds[];
     double* D = lds;                           // [NB][NB+1] factored diagonal block
     double* Dinv = D + CH_NB * CH_PS;          // [NB][NB+1] its inverse
@@ -66,10 +69,22 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const double* __r
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     constexpr int NWAVE = CH_T / 64;
 
+    // conditional pass: when *run_flag is 0 the factor is the identity
+    if (run_flag && *run_flag == 0) {
+        for (int j = wave; j < c; j += NWAVE)
+            for (int i = lane; i < c; i += 64) {
+                const double v = (i == j) ? 1.0 : 0.0;
+                W[i + (int64_t)j * ldw] = v;
+                X[i + (int64_t)j * ldw] = v;
+                if (Xf) Xf[i + (int64_t)j * ldw] = (float)v;
+            }
+        return;
+    }
+
     // trace(G) for the shift
     {
         double t = 0.0;
-        for (int i = tid; i < c; i += CH_T) t += G[i + i * ldg];
+        for (int i = tid; i < c; i += CH_T) t += (double)G[i + i * ldg];
         t = wave_sum(t);
         if (lane == 0) s_red[wave] = t;
         __syncthreads();
@@ -81,11 +96,12 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const double* __r
         __syncthreads();
     }
 
-    for (int attempt = 0; attempt < 2; ++attempt) {
+    int attempt = 0;
+    for (; attempt < 2; ++attempt) {
         const double shift = attempt == 0 ? 0.0 : shift_scale * s_trace;
         for (int j = wave; j < c; j += NWAVE) {
             for (int i = lane; i < c; i += 64) {
-                if (i >= j) W[i + (int64_t)j * ldw] = G[i + (int64_t)j * ldg] + (i == j ? shift : 0.0);
+                if (i >= j) W[i + (int64_t)j * ldw] = (double)G[i + (int64_t)j * ldg] + (i == j ? shift : 0.0);
                 X[i + (int64_t)j * ldw] = (i == j) ? 1.0 : 0.0;
             }
         }
@@ -280,22 +296,32 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const double* __r
     // L^{-1} (lower; its strictly upper part is zero); zero W's upper part.
     for (int j = wave; j < c; j += NWAVE)
         for (int i = lane; i < j; i += 64) W[i + (int64_t)j * ldw] = 0.0;
+    if (shifted_out && tid == 0) *shifted_out = attempt > 0 ? 1 : 0;
+    // optional FP32 copy of L^{-1} for FP32 panel updates
+    if (Xf)
+        for (int j = wave; j < c; j += NWAVE)
+            for (int i = lane; i < c; i += 64) Xf[i + (int64_t)j * ldw] = (float)X[i + (int64_t)j * ldw];
 }
 
-int chol_inv(int64_t c, const double* G, int64_t ldg, double* L, double* Linv, int64_t ld, double shift_scale,
-             int32_t* info, hipStream_t s) {
+template <typename TG>
+int chol_inv(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
+             double shift_scale, int32_t* info, hipStream_t s, const int32_t* run_flag, int32_t* shifted_out) {
     if (c <= 0) return 0;
     const size_t lds = chol_inv_lds_bytes(c);
     static bool attr_set = false;
     if (!attr_set) {
-        RQLP_HIP_TRY(hipFuncSetAttribute((const void*)chol_inv_kernel,
+        RQLP_HIP_TRY(hipFuncSetAttribute((const void*)chol_inv_kernel<TG>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)chol_inv_lds_bytes(1 << 20)));
         attr_set = true;
     }
-    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(CH_T), lds, s, (int)c, G, ldg, shift_scale, L, Linv, ld,
-                       info, ch_prows(c), ch_xcols(c));
+    hipLaunchKernelGGL((chol_inv_kernel<TG>), dim3(1), dim3(CH_T), lds, s, (int)c, G, ldg, shift_scale, L, Linv,
+                       Linv32, ld, info, ch_prows(c), ch_xcols(c), run_flag, shifted_out);
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
+template int chol_inv<double>(int64_t, const double*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
+                              hipStream_t, const int32_t*, int32_t*);
+template int chol_inv<float>(int64_t, const float*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
+                             hipStream_t, const int32_t*, int32_t*);
 
 }  // namespace rqlp

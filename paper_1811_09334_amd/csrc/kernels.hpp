@@ -16,15 +16,43 @@ template <typename T>
 int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64_t ldb,
          T* C, int64_t ldc, bool trans_out, T alpha, T beta, T* ws, size_t ws_elems, hipStream_t s);
 
+// --- gemm_lp.hip ------------------------------------------------------------
+// C(i, j) = 2^(gexp + rexp[i]) sum_k P(k + i ldp) Q(k + j ldq) with 16-bit
+// operands (bfloat16 or IEEE half per kind) and FP32 accumulation; M x N
+// output C (or its transpose when trans_out) of type TO.  Plo / Qlo: the lo
+// parts of split bfloat16 operands (kind RQLP_MIXED_BF16X3 only, else NULL).
+// rexp / gexp may be NULL (no scaling).  ws: gemm_lp_workspace_elems floats.
+size_t gemm_lp_workspace_elems(int64_t M, int64_t N, int64_t K);
+template <typename TO>
+int gemm_lp(int kind, int64_t M, int64_t N, int64_t K, const unsigned short* P, const unsigned short* Plo,
+            int64_t ldp, const unsigned short* Q, const unsigned short* Qlo, int64_t ldq, TO* C, int64_t ldc,
+            bool trans_out, const int* rexp, const int* gexp, float* ws, size_t ws_elems, hipStream_t s);
+// dst = 16-bit 2^(rexp[i] - cexp[j] - gexp) src(i, j) (src^T when transpose);
+// dlo: the rounded remainder (bf16x3 only).
+int cast_to_lp(int kind, int64_t rows, int64_t cols, const float* src, int64_t lds, unsigned short* dst,
+               unsigned short* dlo, int64_t ldd, bool transpose, const int* rexp, const int* cexp, const int* gexp,
+               hipStream_t s);
+// per-column power-of-two exponents of an FP32 matrix for IEEE half storage
+int column_exponents(int64_t rows, int64_t cols, const float* A, int64_t lda, int* colexp, int* gexp,
+                     hipStream_t s);
+template <typename S, typename D>
+int cast_matrix(int64_t rows, int64_t cols, const S* src, int64_t lds, D* dst, int64_t ldd, hipStream_t s);
+
 // --- chol.hip ---------------------------------------------------------------
 // Cholesky G = L L^T of the c x c Gram matrix (lower triangle read) and the
 // inverse of L, in one workgroup.  On breakdown the factorisation restarts
 // from G + shift_scale * trace(G) * I (RQLP_INFO_CHOLQR_SHIFTED).  Outputs:
 // L and Linv (c x c lower triangular, leading dimension ld, zero above the
-// diagonal); both are also the kernel's working storage.
+// diagonal); both are also the kernel's working storage.  G may be FP32 (it
+// is widened); Linv32 (optional, leading dimension ld) gets Linv in FP32.
+// run_flag (optional device word): when it reads 0 the kernel only writes
+// identities (a conditional extra pass); shifted_out (optional) receives 1
+// when the shifted retry was used, else 0.
 size_t chol_inv_lds_bytes(int64_t c);
-int chol_inv(int64_t c, const double* G, int64_t ldg, double* L, double* Linv, int64_t ld, double shift_scale,
-             int32_t* info, hipStream_t s);
+template <typename TG>
+int chol_inv(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
+             double shift_scale, int32_t* info, hipStream_t s, const int32_t* run_flag = nullptr,
+             int32_t* shifted_out = nullptr);
 
 // --- cpqr.hip ---------------------------------------------------------------
 struct CpqrScratch {

@@ -83,3 +83,33 @@ def test_building_block_argument_checks(lib):
     assert _lib.rqlp_cpqr(1, 3, 4, 6, None, None, 0, None, 0, None, 0, None, None, 0, None) == -2
     assert _lib.rqlp_orthonormalize(1, 10, 10, 11, 1, 10, None, 0, None, None, 0, None) == -4
     assert _lib.rqlp_generate_omega(10, 3, 0, 9, 1, 10, None) == -4
+
+
+def test_encode_argument_checks(lib):
+    # (A, lda, m, n, precision, transpose, Ahi, Alo, ldh, colexp, gexp, stream)
+    assert _lib.rqlp_encode(1, 9, 10, 5, 2, 0, 1, None, 10, None, None, None) == -2
+    assert _lib.rqlp_encode(1, 10, 10, 5, 0, 0, 1, None, 10, None, None, None) == -5     # not a mixed type
+    assert _lib.rqlp_encode(1, 10, 10, 5, 2, 1, 1, None, 4, None, None, None) == -9      # A^T needs ldh >= n
+    assert _lib.rqlp_encode(None, 10, 10, 5, 2, 0, 1, None, 10, None, None, None) == -1
+    assert _lib.rqlp_encode(1, 10, 10, 5, 2, 0, 1, 1, 10, None, None, None) == -8        # lo only for bf16x3
+    assert _lib.rqlp_encode(1, 10, 10, 5, 4, 0, 1, None, 10, None, None, None) == -8
+    assert _lib.rqlp_encode(1, 10, 10, 5, 3, 0, 1, None, 10, None, 1, None) == -10       # fp16 needs colexp
+    assert _lib.rqlp_encode(1, 10, 0, 5, 2, 0, None, None, 10, None, None, None) == 0    # empty: nothing to do
+    # (Ahi, Alo, ldh, colexp, m, n, V, ldv, c, B, ldb, precision, work, bytes, stream)
+    assert _lib.rqlp_project_encoded(1, None, 9, None, 10, 5, 1, 10, 3, 1, 3, 2, None, 0, None) == -3
+    assert _lib.rqlp_project_encoded(1, None, 10, None, 10, 5, 1, 10, 3, 1, 2, 2, None, 0, None) == -11
+    assert _lib.rqlp_project_encoded(1, None, 10, None, 10, 5, 1, 10, 3, 1, 3, 1, None, 0, None) == -12
+    assert _lib.rqlp_project_encoded(1, None, 10, None, 10, 5, 1, 10, 3, 1, 3, 3, None, 0, None) == -4
+    assert _lib.rqlp_project_encoded(1, None, 10, None, 10, 5, 1, 10, 3, 1, 3, 2, None, 0, None) == -1000
+
+
+def test_mixed_workspace_holds_the_16bit_copies(lib):
+    m, n, k, p = 32768, 16384, 256, 16
+    b = rq.workspace_size(m, n, k, p, 2, 2, 0, "bf16")
+    assert b >= 2 * 2 * m * n                       # column- and row-major bfloat16 copies of A
+    assert rq.workspace_size(m, n, k, p, 2, 2, 0, "bf16x3") >= b + 2 * 2 * m * n
+
+
+def test_unsupported_combinations_are_reported(lib):
+    assert _factor_status(precision=1) == -1002      # FP32 forward
+    assert _factor_status(b=4) == -1002              # block RQLP
