@@ -31,6 +31,7 @@ struct OrthoScratch {
     double* L1;     // c x c Cholesky factor of pass 1
     double* L2;     // c x c Cholesky factor of pass 2
     double* Li;     // c x c inverse of the current factor
+    unsigned* sync; // flags of the multi-workgroup Cholesky
 };
 
 void carve_ortho(Arena& ar, int64_t c, OrthoScratch* o) {
@@ -38,6 +39,7 @@ void carve_ortho(Arena& ar, int64_t c, OrthoScratch* o) {
     o->L1 = ar.take<double>(c * c);
     o->L2 = ar.take<double>(c * c);
     o->Li = ar.take<double>(c * c);
+    o->sync = ar.take<unsigned>(CHOL_SYNC_WORDS);
 }
 
 struct Ctx {
@@ -61,7 +63,8 @@ int cholqr2(Ctx& cx, int64_t rows, int64_t c, double* buf0, double* buf1, int64_
         RQLP_TRY(gemm<double>(true, false, c, c, rows, cur, ld, cur, ld, cx.o.G, c, false, 1.0, 0.0, cx.gws,
                               cx.gws_elems, cx.s));
         double* Lp = pass == 0 ? cx.o.L1 : cx.o.L2;
-        RQLP_TRY(chol_inv<double>(c, cx.o.G, c, Lp, cx.o.Li, nullptr, c, shift_scale(rows, c), cx.info, cx.s));
+        RQLP_TRY(chol_inv<double>(c, cx.o.G, c, Lp, cx.o.Li, nullptr, c, shift_scale(rows, c), cx.info, cx.s,
+                                  nullptr, nullptr, cx.o.sync));
         RQLP_TRY(gemm<double>(false, true, rows, c, c, cur, ld, cx.o.Li, c, nxt, ld, false, 1.0, 0.0, cx.gws,
                               cx.gws_elems, cx.s));
         double* t = cur;
@@ -87,6 +90,7 @@ struct Ctx32 {
     double* L;      // c x c (FP64 factor, discarded)
     double* Lid;    // c x c (FP64 inverse)
     int32_t* shifted;   // device word: the first pass used the shifted retry
+    unsigned* sync;     // flags of the multi-workgroup Cholesky
 };
 
 // CholeskyQR2 of an FP32 panel, made shifted CholeskyQR3 (Fukaya et al.
@@ -101,7 +105,7 @@ int cholqr_f32(Ctx32& cx, int64_t rows, int64_t c, float* buf0, float* buf1, int
         RQLP_TRY(gemm<float>(true, false, c, c, rows, cur, ld, cur, ld, cx.G, c, false, 1.0f, 0.0f, cx.ws,
                              cx.ws_elems, cx.s));
         RQLP_TRY(chol_inv<float>(c, cx.G, c, cx.L, cx.Lid, cx.Li, c, shift_scale32(rows, c), cx.info, cx.s,
-                                 pass == 2 ? cx.shifted : nullptr, pass == 0 ? cx.shifted : nullptr));
+                                 pass == 2 ? cx.shifted : nullptr, pass == 0 ? cx.shifted : nullptr, cx.sync));
         RQLP_TRY(gemm<float>(false, true, rows, c, c, cur, ld, cx.Li, c, nxt, ld, false, 1.0f, 0.0f, cx.ws,
                              cx.ws_elems, cx.s));
         float* t = cur;
@@ -515,7 +519,7 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
                               f.gws_elems, s));
     } else {
         RangeBufsLP& r = Lay.rlp;
-        Ctx32 c32{s, inf, r.fws, r.fws_elems, r.G, r.Li, f.o.L1, f.o.Li, r.shifted};
+        Ctx32 c32{s, inf, r.fws, r.fws_elems, r.G, r.Li, f.o.L1, f.o.Li, r.shifted, f.o.sync};
         float* V = nullptr;
         RQLP_TRY(range_and_project_lp(c32, r, f, precision, (const float*)A, lda, m, n, l, q, seed,
                                       (const float*)Omega, ldo, &V));

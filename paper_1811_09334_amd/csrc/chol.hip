@@ -305,8 +305,11 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const TG* __restr
 
 template <typename TG>
 int chol_inv(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
-             double shift_scale, int32_t* info, hipStream_t s, const int32_t* run_flag, int32_t* shifted_out) {
+             double shift_scale, int32_t* info, hipStream_t s, const int32_t* run_flag, int32_t* shifted_out,
+             unsigned* sync) {
     if (c <= 0) return 0;
+    if (sync && c <= CHOL_MW_MAXC)
+        return chol_mw<TG>(c, G, ldg, L, Linv, Linv32, ld, shift_scale, info, sync, s, run_flag, shifted_out);
     const size_t lds = chol_inv_lds_bytes(c);
     static bool attr_set = false;
     if (!attr_set) {
@@ -320,8 +323,8 @@ int chol_inv(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 template int chol_inv<double>(int64_t, const double*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
-                              hipStream_t, const int32_t*, int32_t*);
+                              hipStream_t, const int32_t*, int32_t*, unsigned*);
 template int chol_inv<float>(int64_t, const float*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
-                             hipStream_t, const int32_t*, int32_t*);
+                             hipStream_t, const int32_t*, int32_t*, unsigned*);
 
 }  // namespace rqlp

@@ -1,0 +1,379 @@
+// Cholesky factor and inverse of a c x c Gram matrix (c <= 512) on many
+// workgroups: the orthonormalisation step of CholeskyQR ("[V, ~] = qr(Y)",
+// Algorithm 2.1 step 3, and the inner QR steps of Algorithm 2.2).
+//
+// Workgroup J owns block column J (16 columns) of both the factor L and of
+// X = L^{-1}, rows 16 J .. c-1, in LDS for the whole factorisation.  The
+// right-looking block algorithm runs as a pipeline of point-to-point flags
+// instead of grid barriers:
+//   step K (owner K): factor the 16 x 16 diagonal block, L_KK and its
+//     inverse D_K = L_KK^{-1} (one wave, LDS-resident), solve the panel
+//     L(i, K) = W(i, K) D_K^T for the rows below, publish L(:, K) and D_K in
+//     the output arrays and raise flag K;
+//   workgroup J > K, on flag K: W(:, J) -= L(:, K) L(J, K)^T  (16 x 16 FP64
+//     MFMA tiles);
+//   workgroup J < K, on flag K: X(K, J) <- D_K X(K, J), then
+//     X(i, J) -= L(i, K) X(K, J) for the block rows i below K (block forward
+//     substitution of L X = I fused into the same sweep).
+// A workgroup waits only for the flags it needs, so the critical path is
+// one flag hand-off, one rank-16 update and one diagonal factorisation per
+// block step.  Flags carry a per-launch epoch, so no reset is needed.
+//
+// Breakdown (a non-positive or non-finite pivot) in the plain attempt sets
+// RQLP_INFO_CHOLQR_SHIFTED and the device word *retry; a second launch of
+// the same kernel, gated on *retry, then factors G + shift_scale trace(G) I
+// (Fukaya et al. 2020) and flags RQLP_INFO_CHOL_FAILED if that breaks too.
+// Cross-workgroup data uses relaxed device-scope atomic loads / stores.
+#include <time.h>
+#include <unistd.h>
+
+#include <atomic>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rqlp {
+
+constexpr int MW_T = 256;
+constexpr int MW_NW = MW_T / 64;
+constexpr int MW_S = 17;                               // LDS row stride in doubles
+constexpr unsigned long long MW_SPIN_LIMIT = 1ull << 22;
+
+__device__ __forceinline__ void mw_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wave: D (16 x 16, row stride ds, lower triangle read) <- its Cholesky
+// factor (lower), Dv <- the inverse of that factor (lower, zero above).
+// Returns true when a pivot was non-positive or not finite (it is then
+// replaced by 1 so that the arithmetic stays finite).
+__device__ bool mw_factor_diag(double* D, double* Dv, int lane) {
+    bool bad = false;
+    for (int e = 0; e < 4; ++e) {
+        const int idx = lane + 64 * e, i = idx & 15, j = idx >> 4;
+        Dv[i * MW_S + j] = (i == j) ? 1.0 : 0.0;
+    }
+    for (int j = 0; j < 16; ++j) {
+        mw_wave_sync();
+        const double pj = D[j * MW_S + j];
+        const bool ok = (pj > 0.0) && (pj < 1.0e308);
+        bad |= !ok;
+        const double sj = ok ? sqrt(pj) : 1.0;
+        mw_wave_sync();
+        if (lane == j) D[j * MW_S + j] = sj;
+        else if (lane > j && lane < 16) D[lane * MW_S + j] /= sj;
+        mw_wave_sync();
+        double u[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = lane + 64 * e, i = idx & 15, jj = idx >> 4;
+            u[e] = D[i * MW_S + jj] - D[i * MW_S + j] * D[jj * MW_S + j];
+        }
+        mw_wave_sync();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = lane + 64 * e, i = idx & 15, jj = idx >> 4;
+            if (jj > j && i >= jj) D[i * MW_S + jj] = u[e];
+        }
+    }
+    // rows of L X = I in order: X(t, :) = (row t so far) / L(t, t), then the
+    // rows below subtract L(i, t) X(t, :)
+    for (int t = 0; t < 16; ++t) {
+        mw_wave_sync();
+        const double rt = 1.0 / D[t * MW_S + t];
+        if (lane <= t) Dv[t * MW_S + lane] *= rt;
+        mw_wave_sync();
+        double u[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = lane + 64 * e, i = idx & 15, jj = idx >> 4;
+            u[e] = Dv[i * MW_S + jj] - D[i * MW_S + t] * Dv[t * MW_S + jj];
+        }
+        mw_wave_sync();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = lane + 64 * e, i = idx & 15, jj = idx >> 4;
+            if (i > t && jj <= t) Dv[i * MW_S + jj] = u[e];
+        }
+    }
+    mw_wave_sync();
+    return bad;
+}
+
+// gate_mode: 0 always run; 1 when *gate == 0 write identities and return
+// (conditional extra CholeskyQR pass); 2 when *gate == 0 return (retry launch).
+template <typename TG>
+__global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restrict__ G, int64_t ldg,
+                                                       double shift_scale, int attempt, double* __restrict__ Lo,
+                                                       double* __restrict__ Xo, float* __restrict__ Xf, int64_t ld,
+                                                       int32_t* info, unsigned* flags, unsigned epoch,
+                                                       int32_t* retry, const int32_t* gate, int gate_mode,
+                                                       int32_t* shifted_out) {
+    extern __shared__ double lds[];
+    const int J = blockIdx.x, NB = gridDim.x;
+    const int j0 = 16 * J;
+    const int kb = (c - j0) < 16 ? (c - j0) : 16;
+    const int nrt = (c - j0 + 15) >> 4;                 // row tiles of this block column
+    double* Wc = lds;                                   // [16 nrt][MW_S]: W, then L (rows j0..)
+    double* Xc = Wc + (size_t)nrt * 16 * MW_S;          // [16 nrt][MW_S]: X = L^{-1} (rows j0..)
+    double* Dv = Xc + (size_t)nrt * 16 * MW_S;          // [16][MW_S]
+    __shared__ double s_red[MW_NW];
+    __shared__ int s_bad;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int fr = lane & 15, fk = lane >> 4;
+
+    if (gate_mode != 0 && *gate == 0) {
+        if (gate_mode == 1) {
+            for (int idx = tid; idx < c * 16; idx += MW_T) {
+                const int i = idx % c, t = idx / c;
+                if (t >= kb) continue;
+                const int64_t col = j0 + t;
+                const double v = (i == col) ? 1.0 : 0.0;
+                Lo[i + col * ld] = v;
+                Xo[i + col * ld] = v;
+                if (Xf) Xf[i + col * ld] = (float)v;
+            }
+            if (J == 0 && tid == 0) {
+                if (retry) *retry = 0;
+                if (shifted_out) *shifted_out = 0;
+            }
+        }
+        return;
+    }
+
+    double shift = 0.0;
+    if (attempt) {
+        double t = 0.0;
+        for (int i = tid; i < c; i += MW_T) t += (double)G[i + (int64_t)i * ldg];
+        t = wave_sum(t);
+        if (lane == 0) s_red[wave] = t;
+        __syncthreads();
+        double tr = 0.0;
+        for (int w = 0; w < MW_NW; ++w) tr += s_red[w];
+        shift = shift_scale * tr;
+    }
+    for (int idx = tid; idx < nrt * 16 * 16; idx += MW_T) {
+        const int r = idx >> 4, t = idx & 15;
+        const int i = j0 + r;
+        double w = 0.0;
+        if (t < kb && i < c && r >= t) w = (double)G[i + (int64_t)(j0 + t) * ldg] + (r == t ? shift : 0.0);
+        if (t >= kb && r == t) w = 1.0;                 // identity padding of a ragged last block
+        Wc[r * MW_S + t] = w;
+        Xc[r * MW_S + t] = (r == t) ? 1.0 : 0.0;
+    }
+    if (J == 0 && tid == 0) {
+        if (attempt == 0 && retry) __hip_atomic_store(retry, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (shifted_out) *shifted_out = attempt;
+    }
+    __syncthreads();
+
+    for (int K = 0; K < NB; ++K) {
+        const int64_t kc = 16 * (int64_t)K;
+        if (K != J) {
+            if (tid == 0) {
+                unsigned long long spins = 0;
+                while (ld_coherent_u32(flags + K) != epoch) {
+                    if (++spins > MW_SPIN_LIMIT) {
+                        if (info) atomicOr(info, RQLP_INFO_BARRIER_TIMEOUT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            __syncthreads();
+        }
+        if (K < J) {
+            // W(:, J) -= L(:, K) L(J, K)^T over the rows j0.. of this block column
+            for (int tile = wave; tile < nrt; tile += MW_NW) {
+                const int r0 = 16 * tile;
+                double a[4], b[4];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int64_t col = kc + 4 * ks + fk;
+                    const int i = j0 + r0 + fr, jt = j0 + fr;
+                    a[ks] = (i < c) ? -ld_coherent(Lo + i + col * ld) : 0.0;
+                    b[ks] = (jt < c) ? ld_coherent(Lo + jt + col * ld) : 0.0;
+                }
+                double4_t acc;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] = Wc[(r0 + fk + 4 * r) * MW_S + fr];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Wc[(r0 + fk + 4 * r) * MW_S + fr] = acc[r];
+            }
+            __syncthreads();
+        } else if (K == J) {
+            // ---- own step: diagonal factor, panel, publication ----
+            if (wave == 0) {
+                const bool bad = mw_factor_diag(Wc, Dv, lane);
+                if (lane == 0) s_bad = bad ? 1 : 0;
+            }
+            __syncthreads();
+            if (s_bad && tid == 0) {
+                if (attempt == 0) {
+                    if (info) atomicOr(info, RQLP_INFO_CHOLQR_SHIFTED);
+                    if (retry) __hip_atomic_store(retry, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } else if (info) {
+                    atomicOr(info, RQLP_INFO_CHOL_FAILED);
+                }
+            }
+            // panel rows below the diagonal block: L(i, J) = W(i, J) D^T
+            for (int tile = 1 + wave; tile < nrt; tile += MW_NW) {
+                const int r0 = 16 * tile;
+                double a[4], b[4];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int k = 4 * ks + fk;
+                    a[ks] = Wc[(r0 + fr) * MW_S + k];
+                    b[ks] = Dv[fr * MW_S + k];
+                }
+                double4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Wc[(r0 + fk + 4 * r) * MW_S + fr] = acc[r];
+            }
+            // X(J, J) = D
+            for (int idx = tid; idx < 256; idx += MW_T) {
+                const int r = idx >> 4, t = idx & 15;
+                Xc[r * MW_S + t] = (r >= t) ? Dv[r * MW_S + t] : 0.0;
+            }
+            __syncthreads();
+            // publish L(j0.., J) and D into the outputs, then raise flag J
+            for (int idx = tid; idx < nrt * 16 * 16; idx += MW_T) {
+                const int r = idx >> 4, t = idx & 15;
+                const int i = j0 + r;
+                if (i >= c || t >= kb) continue;
+                const int64_t col = j0 + t;
+                st_coherent(Lo + i + col * ld, r >= t ? Wc[r * MW_S + t] : 0.0);
+                if (r < 16) st_coherent(Xo + i + col * ld, r >= t ? Dv[r * MW_S + t] : 0.0);
+            }
+            drain_and_sync();
+            if (tid == 0) st_coherent_u32(flags + J, epoch);
+            // X(i, J) -= L(i, J) X(J, J) for the rows below, from LDS
+            for (int tile = 1 + wave; tile < nrt; tile += MW_NW) {
+                const int r0 = 16 * tile;
+                double a[4], b[4];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int k = 4 * ks + fk;
+                    a[ks] = -Wc[(r0 + fr) * MW_S + k];
+                    b[ks] = Xc[k * MW_S + fr];
+                }
+                double4_t acc;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] = Xc[(r0 + fk + 4 * r) * MW_S + fr];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Xc[(r0 + fk + 4 * r) * MW_S + fr] = acc[r];
+            }
+            __syncthreads();
+        } else {
+            // ---- K > J: X(K, J) <- D_K X(K, J); X(i, J) -= L(i, K) X(K, J) below ----
+            const int rK = (int)(kc - j0);
+            if (wave == 0) {
+                double a[4], b[4];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int k = 4 * ks + fk;
+                    const int64_t s_ = kc + fr, kk = kc + k;
+                    a[ks] = (s_ < c && kk < c && kk <= s_) ? ld_coherent(Xo + s_ + kk * ld) : 0.0;
+                    b[ks] = Xc[(rK + k) * MW_S + fr];
+                }
+                double4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
+                mw_wave_sync();
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Xc[(rK + fk + 4 * r) * MW_S + fr] = acc[r];
+            }
+            __syncthreads();
+            for (int tile = (rK >> 4) + 1 + wave; tile < nrt; tile += MW_NW) {
+                const int r0 = 16 * tile;
+                double a[4], b[4];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int k = 4 * ks + fk;
+                    const int i = j0 + r0 + fr;
+                    a[ks] = (i < c && kc + k < c) ? -ld_coherent(Lo + i + (kc + k) * ld) : 0.0;
+                    b[ks] = Xc[(rK + k) * MW_S + fr];
+                }
+                double4_t acc;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] = Xc[(r0 + fk + 4 * r) * MW_S + fr];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Xc[(r0 + fk + 4 * r) * MW_S + fr] = acc[r];
+            }
+            __syncthreads();
+        }
+    }
+    // outputs of this block column: zeros above row j0, X (and its FP32 copy) below
+    for (int idx = tid; idx < c * 16; idx += MW_T) {
+        const int i = idx % c, t = idx / c;
+        if (t >= kb) continue;
+        const int64_t col = j0 + t;
+        if (i < j0) {
+            Lo[i + col * ld] = 0.0;
+            Xo[i + col * ld] = 0.0;
+            if (Xf) Xf[i + col * ld] = 0.0f;
+        } else {
+            const double x = Xc[(i - j0) * MW_S + t];
+            if (i - j0 >= 16) Xo[i + col * ld] = x;
+            if (Xf) Xf[i + col * ld] = (float)x;
+        }
+    }
+}
+
+size_t chol_mw_lds_bytes(int64_t c) {
+    const int64_t nrt = (c + 15) / 16;
+    return sizeof(double) * (size_t)((2 * nrt * 16 + 16) * MW_S);
+}
+
+template <typename TG>
+int chol_mw(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
+            double shift_scale, int32_t* info, unsigned* sync, hipStream_t s, const int32_t* run_flag,
+            int32_t* shifted_out) {
+    // per-process start value, so that flag words left in reused memory by
+    // another process are unlikely to match
+    static std::atomic<unsigned> epoch_counter{(unsigned)(getpid() * 2654435761u) ^ (unsigned)time(nullptr)};
+    static bool attr_set = false;
+    if (!attr_set) {
+        RQLP_HIP_TRY(hipFuncSetAttribute((const void*)chol_mw_kernel<TG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)chol_mw_lds_bytes(CHOL_MW_MAXC)));
+        attr_set = true;
+    }
+    const int NB = (int)((c + 15) / 16);
+    const size_t lds = chol_mw_lds_bytes(c);
+    // epochs: odd and distinct per launch (a zeroed flag word never matches)
+    const unsigned e0 = 2u * epoch_counter.fetch_add(2) + 1u;
+    unsigned* flags = sync;                        // NB words (first attempt)
+    unsigned* flags1 = sync + CHOL_MW_MAXC / 16;   // NB words (shifted retry)
+    int32_t* retry = (int32_t*)(sync + 2 * (CHOL_MW_MAXC / 16));
+    int cc = (int)c;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        int a = attempt;
+        unsigned ep = e0 + 2u * (unsigned)attempt;
+        unsigned* fl = attempt ? flags1 : flags;
+        const int32_t* gate = attempt ? retry : run_flag;
+        int gate_mode = attempt ? 2 : (run_flag ? 1 : 0);
+        int32_t* shout = shifted_out;
+        void* args[] = {&cc, (void*)&G, &ldg, &shift_scale, &a, &L, &Linv, &Linv32, &ld, &info, &fl, &ep, &retry,
+                        (void*)&gate, &gate_mode, &shout};
+        RQLP_HIP_TRY(hipLaunchCooperativeKernel((const void*)chol_mw_kernel<TG>, dim3(NB), dim3(MW_T), args,
+                                                (unsigned)lds, s));
+    }
+    return 0;
+}
+
+template int chol_mw<double>(int64_t, const double*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
+                             unsigned*, hipStream_t, const int32_t*, int32_t*);
+template int chol_mw<float>(int64_t, const float*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
+                            unsigned*, hipStream_t, const int32_t*, int32_t*);
+
+}  // namespace rqlp

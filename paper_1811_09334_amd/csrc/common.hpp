@@ -125,4 +125,31 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned nblocks, un
     return s_ok != 0;
 }
 
+
+// Cross-workgroup exchange inside one kernel uses relaxed device-scope atomic
+// loads and stores (coherent at the memory side, they bypass the per-XCD L2
+// caches) plus completion waits for ordering: a workgroup's data stores are
+// waited for (s_waitcnt) before it publishes a flag, and readers issue their
+// loads after they observed the flag.  This avoids device-scope
+// release/acquire fences, which write back and invalidate the whole L2.
+__device__ __forceinline__ void st_coherent(double* p, double v) {
+    __hip_atomic_store((unsigned long long*)p, (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coherent(const double* p) {
+    return __longlong_as_double(
+        (long long)__hip_atomic_load((unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st_coherent_u32(unsigned* p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned ld_coherent_u32(const unsigned* p) {
+    return __hip_atomic_load((unsigned*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// every wave waits for its outstanding memory operations, then workgroup barrier
+__device__ __forceinline__ void drain_and_sync() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
 }  // namespace rqlp

@@ -42,25 +42,8 @@ __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v,
 }
 
 // Cross-workgroup traffic of the CPQR uses only relaxed device-scope atomic
-// loads and stores (coherent at the memory side, they bypass the per-XCD L2
-// caches) plus completion waits for ordering: a workgroup's data stores are
-// waited for (s_waitcnt) before the barrier arrival is issued, and readers
-// issue their loads after they observed the barrier release.  This avoids
-// device-scope release/acquire fences, which write back and invalidate the
-// whole L2 once per workgroup and step.
-__device__ __forceinline__ void st_coherent(double* p, double v) {
-    __hip_atomic_store((unsigned long long*)p, (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double ld_coherent(const double* p) {
-    return __longlong_as_double(
-        (long long)__hip_atomic_load((unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-}
-// every wave waits for its outstanding memory operations, then workgroup barrier
-__device__ __forceinline__ void drain_and_sync() {
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-}
+// loads and stores (st_coherent / ld_coherent) plus completion waits for
+// ordering (drain_and_sync).
 
 // Two-level grid barrier: workgroups arrive on the counter of their group of
 // 16 (each counter on its own 128-byte line), the last of a group forwards

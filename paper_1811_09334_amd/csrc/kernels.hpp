@@ -48,11 +48,19 @@ int cast_matrix(int64_t rows, int64_t cols, const S* src, int64_t lds, D* dst, i
 // run_flag (optional device word): when it reads 0 the kernel only writes
 // identities (a conditional extra pass); shifted_out (optional) receives 1
 // when the shifted retry was used, else 0.
+// sync: CHOL_SYNC_WORDS words of device scratch (flags of the multi-workgroup
+// kernel used for c <= CHOL_MW_MAXC); NULL selects the one-workgroup kernel.
+constexpr int CHOL_MW_MAXC = 512;
+constexpr int CHOL_SYNC_WORDS = 128;
 size_t chol_inv_lds_bytes(int64_t c);
 template <typename TG>
 int chol_inv(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
              double shift_scale, int32_t* info, hipStream_t s, const int32_t* run_flag = nullptr,
-             int32_t* shifted_out = nullptr);
+             int32_t* shifted_out = nullptr, unsigned* sync = nullptr);
+template <typename TG>
+int chol_mw(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
+            double shift_scale, int32_t* info, unsigned* sync, hipStream_t s, const int32_t* run_flag,
+            int32_t* shifted_out);
 
 // --- cpqr.hip ---------------------------------------------------------------
 struct CpqrScratch {

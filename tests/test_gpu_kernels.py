@@ -111,3 +111,32 @@ def test_cpqr_rank_deficient_stop(gpu):
     assert np.allclose(R[6:, :], 0.0)
     # after the stop the remaining pivots are the smallest unused indices
     assert np.array_equal(piv[6:], ref.perm[6:40])
+
+
+def test_cholqr2_shifted_retry_on_singular_gram(gpu):
+    """A zero column makes a pivot of the Gram's Cholesky exactly 0: the
+    first attempt breaks down, the shifted retry runs (flag 0x1, not 0x10)
+    and the result is a finite basis whose range still contains Y."""
+    rng = np.random.default_rng(3)
+    Y = rng.standard_normal((500, 40))
+    Y[:, 17] = 0.0
+    V, R, info = gpu.orthonormalize(to_dev(Y), want_r=True)
+    V, info = to_np(V), int(to_np(info)[0])
+    assert info & 0x1 and not info & 0x10
+    assert np.all(np.isfinite(V))
+    resid = Y - V @ np.linalg.lstsq(V, Y, rcond=None)[0]
+    assert np.linalg.norm(resid) < 1e-8 * np.linalg.norm(Y)
+
+
+@pytest.mark.parametrize("c", [1, 15, 16, 17, 100, 256, 257, 511, 512, 513, 700])
+def test_cholqr2_panel_widths(gpu, c):
+    """Panel widths around the 16-column blocks and the multi-workgroup limit."""
+    rng = np.random.default_rng(c)
+    m = max(2 * c, 64)
+    Y = rng.standard_normal((m, c)) * np.logspace(0, -2, c)[None, :]
+    V, R, info = gpu.orthonormalize(to_dev(Y), want_r=True)
+    V, R = to_np(V), to_np(R)
+    assert int(to_np(info)[0]) == 0
+    assert np.abs(V.T @ V - np.eye(c)).max() < 1e-12 * max(10, c)
+    assert np.linalg.norm(Y - V @ R) < 1e-13 * np.linalg.norm(Y) * max(10, c)
+    assert np.allclose(np.tril(R, -1), 0.0) and np.all(np.diag(R) > 0)
