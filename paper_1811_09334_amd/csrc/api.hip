@@ -32,6 +32,7 @@ struct OrthoScratch {
     double* L2;     // c x c Cholesky factor of pass 2
     double* Li;     // c x c inverse of the current factor
     unsigned* sync; // flags of the multi-workgroup Cholesky
+    int32_t* shifted;
 };
 
 void carve_ortho(Arena& ar, int64_t c, OrthoScratch* o) {
@@ -40,6 +41,7 @@ void carve_ortho(Arena& ar, int64_t c, OrthoScratch* o) {
     o->L2 = ar.take<double>(c * c);
     o->Li = ar.take<double>(c * c);
     o->sync = ar.take<unsigned>(CHOL_SYNC_WORDS);
+    o->shifted = ar.take<int32_t>(1);
 }
 
 struct Ctx {
@@ -48,6 +50,7 @@ struct Ctx {
     double* gws;
     size_t gws_elems;
     OrthoScratch o;
+    int32_t* shifted;   // device word: the first pass used the shifted retry
 };
 
 // CholeskyQR2 of the rows x c panel held in buf0 (leading dimension ld):
@@ -55,18 +58,23 @@ struct Ctx {
 // holding the orthonormal result (buf0 or buf1; buf0 is overwritten).  RT
 // (c x c, optional) receives R^T = L1 L2 (lower triangular), where
 // X_in = V R is the QR factorisation with diag(R) > 0.
+// With final == false (an intermediate basis of the subspace iteration,
+// which only has to span range(X) and be well conditioned) the second pass
+// runs only when the first Cholesky needed the shifted retry; it is then
+// gated on the device word cx.shifted and a skipped pass copies X through.
 int cholqr2(Ctx& cx, int64_t rows, int64_t c, double* buf0, double* buf1, int64_t ld, double* RT,
-            double** out) {
+            double** out, bool final = true) {
     double* cur = buf0;
     double* nxt = buf1;
     for (int pass = 0; pass < 2; ++pass) {
+        const int32_t* gate = (!final && pass == 1) ? cx.shifted : nullptr;
         RQLP_TRY(gemm<double>(true, false, c, c, rows, cur, ld, cur, ld, cx.o.G, c, false, 1.0, 0.0, cx.gws,
-                              cx.gws_elems, cx.s));
+                              cx.gws_elems, cx.s, gate, 1));
         double* Lp = pass == 0 ? cx.o.L1 : cx.o.L2;
         RQLP_TRY(chol_inv<double>(c, cx.o.G, c, Lp, cx.o.Li, nullptr, c, shift_scale(rows, c), cx.info, cx.s,
-                                  nullptr, nullptr, cx.o.sync));
+                                  gate, (!final && pass == 0) ? cx.shifted : nullptr, cx.o.sync));
         RQLP_TRY(gemm<double>(false, true, rows, c, c, cur, ld, cx.o.Li, c, nxt, ld, false, 1.0, 0.0, cx.gws,
-                              cx.gws_elems, cx.s));
+                              cx.gws_elems, cx.s, gate, 2));
         double* t = cur;
         cur = nxt;
         nxt = t;
@@ -93,21 +101,26 @@ struct Ctx32 {
     unsigned* sync;     // flags of the multi-workgroup Cholesky
 };
 
-// CholeskyQR2 of an FP32 panel, made shifted CholeskyQR3 (Fukaya et al.
-// 2020) when the first Cholesky breaks down: a third pass runs, but only
-// does work when the device word cx.shifted was set by the first pass (its
-// factor is the identity otherwise, so X is carried over exactly).  The
-// result is always in buf1.
-int cholqr_f32(Ctx32& cx, int64_t rows, int64_t c, float* buf0, float* buf1, int64_t ld, float** out) {
+// CholeskyQR of an FP32 panel as shifted CholeskyQR3 (Fukaya et al. 2020):
+// three passes, of which the first `always` run unconditionally (2 for the
+// final basis: CholeskyQR2; 1 for an intermediate basis of the subspace
+// iteration, which only has to span range(X) and be well conditioned) and
+// the rest only when a Cholesky of an earlier pass needed the shifted retry
+// (device word cx.shifted, set by any such pass).  A skipped pass forms no
+// Gram and its update copies X through, so the result is always in buf1.
+int cholqr_f32(Ctx32& cx, int64_t rows, int64_t c, float* buf0, float* buf1, int64_t ld, float** out,
+               bool final = true) {
     float* cur = buf0;
     float* nxt = buf1;
+    const int always = final ? 2 : 1;
     for (int pass = 0; pass < 3; ++pass) {
+        const int32_t* gate = pass >= always ? cx.shifted : nullptr;
         RQLP_TRY(gemm<float>(true, false, c, c, rows, cur, ld, cur, ld, cx.G, c, false, 1.0f, 0.0f, cx.ws,
-                             cx.ws_elems, cx.s));
+                             cx.ws_elems, cx.s, gate, 1));
         RQLP_TRY(chol_inv<float>(c, cx.G, c, cx.L, cx.Lid, cx.Li, c, shift_scale32(rows, c), cx.info, cx.s,
-                                 pass == 2 ? cx.shifted : nullptr, pass == 0 ? cx.shifted : nullptr, cx.sync));
+                                 gate, pass < 2 ? cx.shifted : nullptr, cx.sync, pass == 0 ? 1 : 2));
         RQLP_TRY(gemm<float>(false, true, rows, c, c, cur, ld, cx.Li, c, nxt, ld, false, 1.0f, 0.0f, cx.ws,
-                             cx.ws_elems, cx.s));
+                             cx.ws_elems, cx.s, gate, 2));
         float* t = cur;
         cur = nxt;
         nxt = t;
@@ -374,16 +387,16 @@ int range_and_project_f64(Ctx& cx, RangeBufs64& r, SmallBufs& f, const double* A
     }
     RQLP_TRY(gemm<double>(false, false, m, l, n, A, lda, Om, ldom, r.Y, m, false, 1.0, 0.0, f.gws, f.gws_elems, s));
     double* V = nullptr;
-    RQLP_TRY(cholqr2(cx, m, l, r.Y, r.Y2, m, nullptr, &V));
+    RQLP_TRY(cholqr2(cx, m, l, r.Y, r.Y2, m, nullptr, &V, q == 0));
     for (int it = 0; it < q; ++it) {
         // Z = A^T V into the small stage's n x l buffers (free until the CPQR)
         RQLP_TRY(gemm<double>(true, false, n, l, m, A, lda, V, m, f.Z, n, false, 1.0, 0.0, f.gws, f.gws_elems, s));
         double* W = nullptr;
-        RQLP_TRY(cholqr2(cx, n, l, f.Z, f.Z2, n, nullptr, &W));
+        RQLP_TRY(cholqr2(cx, n, l, f.Z, f.Z2, n, nullptr, &W, false));
         double* ydst = (V == r.Y) ? r.Y2 : r.Y;
         RQLP_TRY(gemm<double>(false, false, m, l, n, A, lda, W, n, ydst, m, false, 1.0, 0.0, f.gws, f.gws_elems, s));
         double* other = (ydst == r.Y) ? r.Y2 : r.Y;
-        RQLP_TRY(cholqr2(cx, m, l, ydst, other, m, nullptr, &V));
+        RQLP_TRY(cholqr2(cx, m, l, ydst, other, m, nullptr, &V, it == q - 1));
     }
     // B = V^T A, computed as (A^T V)^T and stored l x n
     RQLP_TRY(gemm<double>(true, false, n, l, m, A, lda, V, m, f.B, l, true, 1.0, 0.0, f.gws, f.gws_elems, s));
@@ -403,8 +416,7 @@ int range_and_project_lp(Ctx32& c32, RangeBufsLP& r, SmallBufs& f, int kind, con
     const int* cexp = fp16 ? r.colexp : nullptr;
     const int* gexp = fp16 ? r.gexp : nullptr;
     if (fp16) RQLP_TRY(column_exponents(m, n, A, lda, r.colexp, r.gexp, s));
-    RQLP_TRY(cast_to_lp(kind, m, n, A, lda, r.Ac, r.Aclo, m, false, nullptr, cexp, nullptr, s));
-    RQLP_TRY(cast_to_lp(kind, m, n, A, lda, r.Ar, r.Arlo, n, true, nullptr, cexp, nullptr, s));
+    RQLP_TRY(encode_both(kind, m, n, A, lda, r.Ac, r.Aclo, m, r.Ar, r.Arlo, n, cexp, s));
     if (!Om) {
         RQLP_TRY(generate_omega(n, l, seed, kind, r.Om, n, s));
         Om = r.Om;
@@ -415,21 +427,21 @@ int range_and_project_lp(Ctx32& c32, RangeBufsLP& r, SmallBufs& f, int kind, con
     RQLP_TRY(gemm_lp<float>(kind, m, l, n, r.Ar, r.Arlo, n, r.X16, r.X16lo, n, r.Y, m, false, nullptr, gexp, r.lpws,
                             r.lpws_elems, s));
     float* V = nullptr;
-    RQLP_TRY(cholqr_f32(c32, m, l, r.Y, r.Y2, m, &V));
+    RQLP_TRY(cholqr_f32(c32, m, l, r.Y, r.Y2, m, &V, q == 0));
     for (int it = 0; it < q; ++it) {
         // Z = A^T V  (FP16: D (A D^-1)^T V)
         RQLP_TRY(cast_to_lp(kind, m, l, V, m, r.X16, r.X16lo, m, false, nullptr, nullptr, nullptr, s));
         RQLP_TRY(gemm_lp<float>(kind, n, l, m, r.Ac, r.Aclo, m, r.X16, r.X16lo, m, r.Z, n, false, cexp, nullptr,
                                 r.lpws, r.lpws_elems, s));
         float* W = nullptr;
-        RQLP_TRY(cholqr_f32(c32, n, l, r.Z, r.Z2, n, &W));
+        RQLP_TRY(cholqr_f32(c32, n, l, r.Z, r.Z2, n, &W, false));
         // Y = A W
         RQLP_TRY(cast_to_lp(kind, n, l, W, n, r.X16, r.X16lo, n, false, cexp, nullptr, gexp, s));
         float* ydst = (V == r.Y) ? r.Y2 : r.Y;
         RQLP_TRY(gemm_lp<float>(kind, m, l, n, r.Ar, r.Arlo, n, r.X16, r.X16lo, n, ydst, m, false, nullptr, gexp,
                                 r.lpws, r.lpws_elems, s));
         float* other = (ydst == r.Y) ? r.Y2 : r.Y;
-        RQLP_TRY(cholqr_f32(c32, m, l, ydst, other, m, &V));
+        RQLP_TRY(cholqr_f32(c32, m, l, ydst, other, m, &V, it == q - 1));
     }
     // B = V^T A = (A^T V)^T, FP32 accumulation, stored l x n in FP64
     RQLP_TRY(cast_to_lp(kind, m, l, V, m, r.X16, r.X16lo, m, false, nullptr, nullptr, nullptr, s));
@@ -505,7 +517,7 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
     }
     int32_t* inf = info ? info : f.info;
     RQLP_TRY(fill_zero_bytes(inf, sizeof(int32_t), s));
-    Ctx cx{s, inf, f.gws, f.gws_elems, f.o};
+    Ctx cx{s, inf, f.gws, f.gws_elems, f.o, f.o.shifted};
     char tri = 'L';
     double* QB = nullptr;
 
@@ -757,7 +769,7 @@ int rqlp_orthonormalize(const double* Y, int64_t ldy, int64_t m, int64_t c, doub
     int32_t* inf = info ? info : linfo;
     RQLP_TRY(fill_zero_bytes(inf, sizeof(int32_t), s));
     RQLP_TRY(copy_matrix(m, c, Y, ldy, b0, m, s));
-    Ctx cx{s, inf, gws, e, o};
+    Ctx cx{s, inf, gws, e, o, o.shifted};
     double* out = nullptr;
     RQLP_TRY(cholqr2(cx, m, c, b0, b1, m, R ? RT : nullptr, &out));
     if (R) RQLP_TRY(transpose_matrix(c, c, RT, c, R, ldr, 'U', s));

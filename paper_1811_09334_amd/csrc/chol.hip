@@ -55,7 +55,7 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const TG* __restr
                                                         double* __restrict__ X, float* __restrict__ Xf,
                                                         int64_t ldw, int32_t* info, int prows, int xcols,
                                                         const int32_t* __restrict__ run_flag,
-                                                        int32_t* __restrict__ shifted_out) {
+                                                        int32_t* __restrict__ shifted_out, int shifted_mode) {
     extern __shared__ double lds[];
     double* D = lds;                           // [NB][NB+1] factored diagonal block
     double* Dinv = D + CH_NB * CH_PS;          // [NB][NB+1] its inverse
@@ -296,7 +296,7 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const TG* __restr
     // L^{-1} (lower; its strictly upper part is zero); zero W's upper part.
     for (int j = wave; j < c; j += NWAVE)
         for (int i = lane; i < j; i += 64) W[i + (int64_t)j * ldw] = 0.0;
-    if (shifted_out && tid == 0) *shifted_out = attempt > 0 ? 1 : 0;
+    if (shifted_out && tid == 0 && (shifted_mode == 1 || attempt > 0)) *shifted_out = attempt > 0 ? 1 : 0;
     // optional FP32 copy of L^{-1} for FP32 panel updates
     if (Xf)
         for (int j = wave; j < c; j += NWAVE)
@@ -306,10 +306,11 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const TG* __restr
 template <typename TG>
 int chol_inv(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
              double shift_scale, int32_t* info, hipStream_t s, const int32_t* run_flag, int32_t* shifted_out,
-             unsigned* sync) {
+             unsigned* sync, int shifted_mode) {
     if (c <= 0) return 0;
     if (sync && c <= CHOL_MW_MAXC)
-        return chol_mw<TG>(c, G, ldg, L, Linv, Linv32, ld, shift_scale, info, sync, s, run_flag, shifted_out);
+        return chol_mw<TG>(c, G, ldg, L, Linv, Linv32, ld, shift_scale, info, sync, s, run_flag, shifted_out,
+                           shifted_mode);
     const size_t lds = chol_inv_lds_bytes(c);
     static bool attr_set = false;
     if (!attr_set) {
@@ -319,12 +320,12 @@ int chol_inv(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float
         attr_set = true;
     }
     hipLaunchKernelGGL((chol_inv_kernel<TG>), dim3(1), dim3(CH_T), lds, s, (int)c, G, ldg, shift_scale, L, Linv,
-                       Linv32, ld, info, ch_prows(c), ch_xcols(c), run_flag, shifted_out);
+                       Linv32, ld, info, ch_prows(c), ch_xcols(c), run_flag, shifted_out, shifted_mode);
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 template int chol_inv<double>(int64_t, const double*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
-                              hipStream_t, const int32_t*, int32_t*, unsigned*);
+                              hipStream_t, const int32_t*, int32_t*, unsigned*, int);
 template int chol_inv<float>(int64_t, const float*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
-                             hipStream_t, const int32_t*, int32_t*, unsigned*);
+                             hipStream_t, const int32_t*, int32_t*, unsigned*, int);
 
 }  // namespace rqlp

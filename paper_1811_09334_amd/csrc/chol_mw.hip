@@ -38,67 +38,63 @@ constexpr int MW_T = 256;
 constexpr int MW_NW = MW_T / 64;
 constexpr int MW_S = 17;                               // LDS row stride in doubles
 constexpr unsigned long long MW_SPIN_LIMIT = 1ull << 22;
+constexpr int MW_MAXT = CHOL_MW_MAXC / 16 / MW_NW;       // row tiles per wave (at most)
 
-__device__ __forceinline__ void mw_wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+__device__ __forceinline__ double mw_readlane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// One wave: D (16 x 16, row stride ds, lower triangle read) <- its Cholesky
-// factor (lower), Dv <- the inverse of that factor (lower, zero above).
-// Returns true when a pivot was non-positive or not finite (it is then
-// replaced by 1 so that the arithmetic stays finite).
-__device__ bool mw_factor_diag(double* D, double* Dv, int lane) {
+// One wave, registers only: lane (i = lane % 16, g = lane / 16) holds
+// d[e] = D(i, 4 g + e) of the 16 x 16 block (lower triangle read).  On
+// return d holds the Cholesky factor L (zero above the diagonal) and x its
+// inverse X = L^{-1} (zero above the diagonal).  Returns true when a pivot
+// was non-positive or not finite (it is then replaced by 1).  Each column
+// step broadcasts the pivot with a read-lane and gathers L(i, j), L(k, j)
+// with lane shuffles; the inverse is the row sweep of L X = I.
+__device__ bool mw_factor_diag(double d[4], double x[4], int lane) {
+    const int i = lane & 15, g = lane >> 4;
     bool bad = false;
-    for (int e = 0; e < 4; ++e) {
-        const int idx = lane + 64 * e, i = idx & 15, j = idx >> 4;
-        Dv[i * MW_S + j] = (i == j) ? 1.0 : 0.0;
-    }
+    double rdiag[16];
+#pragma unroll
     for (int j = 0; j < 16; ++j) {
-        mw_wave_sync();
-        const double pj = D[j * MW_S + j];
-        const bool ok = (pj > 0.0) && (pj < 1.0e308);
+        const int gj = j >> 2, ej = j & 3;
+        const double piv = mw_readlane(d[ej], j + 16 * gj);
+        const bool ok = (piv > 0.0) && (piv < 1.0e308);
         bad |= !ok;
-        const double sj = ok ? sqrt(pj) : 1.0;
-        mw_wave_sync();
-        if (lane == j) D[j * MW_S + j] = sj;
-        else if (lane > j && lane < 16) D[lane * MW_S + j] /= sj;
-        mw_wave_sync();
-        double u[4];
+        // 1 / sqrt(piv) from the hardware estimate and one Newton step
+        // (relative error ~1e-16), then sqrt(piv) = piv / sqrt(piv)
+        const double p = ok ? piv : 1.0;
+        double rinv = __builtin_amdgcn_rsq(p);
+        rinv = rinv * (1.5 - 0.5 * p * rinv * rinv);
+        const double lj = p * rinv;
+        rdiag[j] = rinv;
+        if (g == gj) d[ej] = (i == j) ? lj : (i > j ? d[ej] * rinv : 0.0);
+        const double lij = __shfl(d[ej], i + 16 * gj, 64);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int idx = lane + 64 * e, i = idx & 15, jj = idx >> 4;
-            u[e] = D[i * MW_S + jj] - D[i * MW_S + j] * D[jj * MW_S + j];
-        }
-        mw_wave_sync();
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int idx = lane + 64 * e, i = idx & 15, jj = idx >> 4;
-            if (jj > j && i >= jj) D[i * MW_S + jj] = u[e];
+            const double lkj = __shfl(d[ej], 4 * g + e + 16 * gj, 64);
+            if (4 * g + e > j) d[e] -= lij * lkj;
         }
     }
-    // rows of L X = I in order: X(t, :) = (row t so far) / L(t, t), then the
-    // rows below subtract L(i, t) X(t, :)
+    double lrow[16];                       // L(i, t) of this lane's row
+#pragma unroll
+    for (int t = 0; t < 16; ++t) lrow[t] = __shfl(d[t & 3], i + 16 * (t >> 2), 64);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) x[e] = (i == 4 * g + e) ? 1.0 : 0.0;
+#pragma unroll
     for (int t = 0; t < 16; ++t) {
-        mw_wave_sync();
-        const double rt = 1.0 / D[t * MW_S + t];
-        if (lane <= t) Dv[t * MW_S + lane] *= rt;
-        mw_wave_sync();
-        double u[4];
+        if (i == t) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int idx = lane + 64 * e, i = idx & 15, jj = idx >> 4;
-            u[e] = Dv[i * MW_S + jj] - D[i * MW_S + t] * Dv[t * MW_S + jj];
+            for (int e = 0; e < 4; ++e) x[e] *= rdiag[t];
         }
-        mw_wave_sync();
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int idx = lane + 64 * e, i = idx & 15, jj = idx >> 4;
-            if (i > t && jj <= t) Dv[i * MW_S + jj] = u[e];
+            const double xt = __shfl(x[e], t + 16 * g, 64);
+            if (i > t) x[e] -= lrow[t] * xt;
         }
     }
-    mw_wave_sync();
     return bad;
 }
 
@@ -110,7 +106,7 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
                                                        double* __restrict__ Xo, float* __restrict__ Xf, int64_t ld,
                                                        int32_t* info, unsigned* flags, unsigned epoch,
                                                        int32_t* retry, const int32_t* gate, int gate_mode,
-                                                       int32_t* shifted_out) {
+                                                       int32_t* shifted_out, int shifted_mode) {
     extern __shared__ double lds[];
     const int J = blockIdx.x, NB = gridDim.x;
     const int j0 = 16 * J;
@@ -137,7 +133,7 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
             }
             if (J == 0 && tid == 0) {
                 if (retry) *retry = 0;
-                if (shifted_out) *shifted_out = 0;
+                if (shifted_out && shifted_mode == 1) *shifted_out = 0;
             }
         }
         return;
@@ -165,7 +161,9 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
     }
     if (J == 0 && tid == 0) {
         if (attempt == 0 && retry) __hip_atomic_store(retry, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (shifted_out) *shifted_out = attempt;
+        // shifted_mode 1: *shifted_out = "this factorisation used the shift";
+        // 2: only ever set (accumulates over several factorisations)
+        if (shifted_out && (shifted_mode == 1 || attempt == 1)) *shifted_out = attempt;
     }
     __syncthreads();
 
@@ -186,21 +184,38 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
         }
         if (K < J) {
             // W(:, J) -= L(:, K) L(J, K)^T over the rows j0.. of this block column
-            for (int tile = wave; tile < nrt; tile += MW_NW) {
-                const int r0 = 16 * tile;
-                double a[4], b[4];
+            // b = L(J, K)^T is the same for every tile of this workgroup
+            double b[4];
+            {
+                const int jt = j0 + fr;
+                const int jc = jt < c ? jt : c - 1;
 #pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                    const int64_t col = kc + 4 * ks + fk;
-                    const int i = j0 + r0 + fr, jt = j0 + fr;
-                    a[ks] = (i < c) ? -ld_coherent(Lo + i + col * ld) : 0.0;
-                    b[ks] = (jt < c) ? ld_coherent(Lo + jt + col * ld) : 0.0;
-                }
+                for (int ks = 0; ks < 4; ++ks) b[ks] = ld_coherent(Lo + jc + (kc + 4 * ks + fk) * ld);
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) b[ks] = jt < c ? b[ks] : 0.0;
+            }
+            // all panel loads of this wave's tiles are issued before the first use
+            double a[MW_MAXT][4];
+#pragma unroll
+            for (int q = 0; q < MW_MAXT; ++q) {
+                const int tile = wave + MW_NW * q;
+                const int i = j0 + 16 * tile + fr;
+                const int ic = (tile < nrt && i < c) ? i : c - 1;
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) a[q][ks] = ld_coherent(Lo + ic + (kc + 4 * ks + fk) * ld);
+            }
+#pragma unroll
+            for (int q = 0; q < MW_MAXT; ++q) {
+                const int tile = wave + MW_NW * q;
+                if (tile >= nrt) break;
+                const int r0 = 16 * tile;
+                const bool in = j0 + r0 + fr < c;
                 double4_t acc;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) acc[r] = Wc[(r0 + fk + 4 * r) * MW_S + fr];
 #pragma unroll
-                for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
+                for (int ks = 0; ks < 4; ++ks)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? -a[q][ks] : 0.0, b[ks], acc, 0, 0, 0);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) Wc[(r0 + fk + 4 * r) * MW_S + fr] = acc[r];
             }
@@ -208,7 +223,16 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
         } else if (K == J) {
             // ---- own step: diagonal factor, panel, publication ----
             if (wave == 0) {
-                const bool bad = mw_factor_diag(Wc, Dv, lane);
+                const int i = lane & 15, g = lane >> 4;
+                double d[4], x[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) d[e] = Wc[i * MW_S + 4 * g + e];
+                const bool bad = mw_factor_diag(d, x, lane);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    Wc[i * MW_S + 4 * g + e] = d[e];
+                    Dv[i * MW_S + 4 * g + e] = x[e];
+                }
                 if (lane == 0) s_bad = bad ? 1 : 0;
             }
             __syncthreads();
@@ -277,38 +301,61 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
             const int rK = (int)(kc - j0);
             if (wave == 0) {
                 double a[4], b[4];
+                const int64_t s_ = kc + fr;
+                const int64_t sc_ = s_ < c ? s_ : c - 1;
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int64_t kk = kc + 4 * ks + fk;
+                    a[ks] = ld_coherent(Xo + sc_ + (kk < c ? kk : c - 1) * ld);
+                }
 #pragma unroll
                 for (int ks = 0; ks < 4; ++ks) {
                     const int k = 4 * ks + fk;
-                    const int64_t s_ = kc + fr, kk = kc + k;
-                    a[ks] = (s_ < c && kk < c && kk <= s_) ? ld_coherent(Xo + s_ + kk * ld) : 0.0;
+                    const int64_t kk = kc + k;
+                    a[ks] = (s_ < c && kk < c && kk <= s_) ? a[ks] : 0.0;
                     b[ks] = Xc[(rK + k) * MW_S + fr];
                 }
                 double4_t acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
-                mw_wave_sync();
 #pragma unroll
                 for (int r = 0; r < 4; ++r) Xc[(rK + fk + 4 * r) * MW_S + fr] = acc[r];
             }
             __syncthreads();
-            for (int tile = (rK >> 4) + 1 + wave; tile < nrt; tile += MW_NW) {
-                const int r0 = 16 * tile;
-                double a[4], b[4];
+            {
+                const int t0 = (rK >> 4) + 1;
+                double a[MW_MAXT][4];
 #pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                    const int k = 4 * ks + fk;
-                    const int i = j0 + r0 + fr;
-                    a[ks] = (i < c && kc + k < c) ? -ld_coherent(Lo + i + (kc + k) * ld) : 0.0;
-                    b[ks] = Xc[(rK + k) * MW_S + fr];
+                for (int q = 0; q < MW_MAXT; ++q) {
+                    const int tile = t0 + wave + MW_NW * q;
+                    const int i = j0 + 16 * tile + fr;
+                    const int ic = (tile < nrt && i < c) ? i : c - 1;
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        const int64_t kk = kc + 4 * ks + fk;
+                        a[q][ks] = ld_coherent(Lo + ic + (kk < c ? kk : c - 1) * ld);
+                    }
                 }
-                double4_t acc;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r] = Xc[(r0 + fk + 4 * r) * MW_S + fr];
+                for (int q = 0; q < MW_MAXT; ++q) {
+                    const int tile = t0 + wave + MW_NW * q;
+                    if (tile >= nrt) break;
+                    const int r0 = 16 * tile;
+                    const bool in = j0 + r0 + fr < c;
+                    double b[4];
 #pragma unroll
-                for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
+                    for (int ks = 0; ks < 4; ++ks) b[ks] = Xc[(rK + 4 * ks + fk) * MW_S + fr];
+                    double4_t acc;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) Xc[(r0 + fk + 4 * r) * MW_S + fr] = acc[r];
+                    for (int r = 0; r < 4; ++r) acc[r] = Xc[(r0 + fk + 4 * r) * MW_S + fr];
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) {
+                        const bool kin = kc + 4 * ks + fk < c;
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(in && kin ? -a[q][ks] : 0.0, b[ks], acc, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Xc[(r0 + fk + 4 * r) * MW_S + fr] = acc[r];
+                }
             }
             __syncthreads();
         }
@@ -338,7 +385,7 @@ size_t chol_mw_lds_bytes(int64_t c) {
 template <typename TG>
 int chol_mw(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
             double shift_scale, int32_t* info, unsigned* sync, hipStream_t s, const int32_t* run_flag,
-            int32_t* shifted_out) {
+            int32_t* shifted_out, int shifted_mode) {
     // per-process start value, so that flag words left in reused memory by
     // another process are unlikely to match
     static std::atomic<unsigned> epoch_counter{(unsigned)(getpid() * 2654435761u) ^ (unsigned)time(nullptr)};
@@ -363,8 +410,9 @@ int chol_mw(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float*
         const int32_t* gate = attempt ? retry : run_flag;
         int gate_mode = attempt ? 2 : (run_flag ? 1 : 0);
         int32_t* shout = shifted_out;
+        int smode = shifted_mode;
         void* args[] = {&cc, (void*)&G, &ldg, &shift_scale, &a, &L, &Linv, &Linv32, &ld, &info, &fl, &ep, &retry,
-                        (void*)&gate, &gate_mode, &shout};
+                        (void*)&gate, &gate_mode, &shout, &smode};
         RQLP_HIP_TRY(hipLaunchCooperativeKernel((const void*)chol_mw_kernel<TG>, dim3(NB), dim3(MW_T), args,
                                                 (unsigned)lds, s));
     }
@@ -372,8 +420,8 @@ int chol_mw(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float*
 }
 
 template int chol_mw<double>(int64_t, const double*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
-                             unsigned*, hipStream_t, const int32_t*, int32_t*);
+                             unsigned*, hipStream_t, const int32_t*, int32_t*, int);
 template int chol_mw<float>(int64_t, const float*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
-                            unsigned*, hipStream_t, const int32_t*, int32_t*);
+                            unsigned*, hipStream_t, const int32_t*, int32_t*, int);
 
 }  // namespace rqlp

@@ -59,7 +59,7 @@ template <typename T, bool TA, bool TB, int MB, int NB, int BK>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
     int64_t M, int64_t N, int64_t K, const T* __restrict__ A, int64_t lda,
     const T* __restrict__ B, int64_t ldb, T* __restrict__ C, int64_t ldc, int64_t split_stride,
-    int64_t kchunk) {
+    int64_t kchunk, const int32_t* __restrict__ gate, int gate_copy) {
     constexpr int BM = 64 * MB;
     constexpr int BN = 16 * NB;
     constexpr int SA = TA ? (BK + 2) : (BM + 16);
@@ -81,6 +81,16 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
     const int wave = tid >> 6;
     const int64_t m0 = (int64_t)blockIdx.x * BM;
     const int64_t n0 = (int64_t)blockIdx.y * BN;
+    // conditional product: when *gate is 0 nothing is computed; with gate_copy
+    // the tile of op(A) is copied to C instead (the product with an identity)
+    if (gate != nullptr && *gate == 0) {
+        if (gate_copy && !TA)
+            for (int idx = tid; idx < BM * BN; idx += GEMM_THREADS) {
+                const int64_t i = m0 + idx % BM, j = n0 + idx / BM;
+                if (i < M && j < N) C[i + j * ldc] = A[i + j * lda];
+            }
+        return;
+    }
     const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
     const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
 
@@ -211,7 +221,9 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
 template <typename T>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(int64_t M, int64_t N, const T* __restrict__ W,
                                                             int64_t ldw, int64_t split_stride, int S, T alpha,
-                                                            T beta, T* __restrict__ C, int64_t ldc) {
+                                                            T beta, T* __restrict__ C, int64_t ldc,
+                                                            const int32_t* __restrict__ gate) {
+    if (gate != nullptr && *gate == 0) return;
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= M * N) return;
     const int64_t i = idx % M, j = idx / M;
@@ -232,7 +244,9 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(int64_t M, int64_t N
 template <typename T>
 __global__ __launch_bounds__(256) void splitk_reduce_t_kernel(int64_t M, int64_t N, const T* __restrict__ W,
                                                               int64_t ldw, int64_t split_stride, int S, T alpha,
-                                                              T beta, T* __restrict__ C, int64_t ldc) {
+                                                              T beta, T* __restrict__ C, int64_t ldc,
+                                                              const int32_t* __restrict__ gate) {
+    if (gate != nullptr && *gate == 0) return;
     __shared__ T tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
     const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
@@ -297,18 +311,20 @@ GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K) {
 
 template <typename T, bool TA, bool TB, int NB>
 void launch_nb(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda,
-               const T* B, int64_t ldb, T* C, int64_t ldc, int64_t split_stride, hipStream_t s) {
+               const T* B, int64_t ldb, T* C, int64_t ldc, int64_t split_stride, const int32_t* gate, int gate_copy,
+               hipStream_t s) {
     dim3 grid((unsigned)p.tm, (unsigned)p.tn, (unsigned)p.S);
     hipLaunchKernelGGL((gemm_skinny_kernel<T, TA, TB, 1, NB, GEMM_BK>), grid, dim3(GEMM_THREADS), 0, s, M, N, K, A,
-                       lda, B, ldb, C, ldc, split_stride, p.kchunk);
+                       lda, B, ldb, C, ldc, split_stride, p.kchunk, gate, gate_copy);
 }
 
 template <typename T, bool TA, bool TB>
 void launch_dispatch(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda,
-                     const T* B, int64_t ldb, T* C, int64_t ldc, int64_t split_stride, hipStream_t s) {
+                     const T* B, int64_t ldb, T* C, int64_t ldc, int64_t split_stride, const int32_t* gate,
+                     int gate_copy, hipStream_t s) {
     switch (p.nb) {
 #define RQLP_NB_CASE(X) \
-    case X: launch_nb<T, TA, TB, X>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, s); break;
+    case X: launch_nb<T, TA, TB, X>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, s); break;
         RQLP_NB_CASE(1) RQLP_NB_CASE(2) RQLP_NB_CASE(3) RQLP_NB_CASE(4)
         RQLP_NB_CASE(5) RQLP_NB_CASE(6) RQLP_NB_CASE(7)
 #undef RQLP_NB_CASE
@@ -325,40 +341,45 @@ size_t gemm_workspace_elems(int64_t M, int64_t N, int64_t K) {
 template <typename T>
 static void launch_any(bool ta, bool tb, const GemmPlan& p, int64_t M, int64_t N, int64_t K, const T* A,
                        int64_t lda, const T* B, int64_t ldb, T* C, int64_t ldc, int64_t split_stride,
-                       hipStream_t s) {
+                       const int32_t* gate, int gate_copy, hipStream_t s) {
     if (ta && tb) return;   // not needed by the method
-    if (ta) launch_dispatch<T, true, false>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, s);
-    else if (tb) launch_dispatch<T, false, true>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, s);
-    else launch_dispatch<T, false, false>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, s);
+    if (ta) launch_dispatch<T, true, false>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, s);
+    else if (tb) launch_dispatch<T, false, true>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, s);
+    else launch_dispatch<T, false, false>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, s);
 }
 
 template <typename T>
 int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64_t ldb,
-         T* C, int64_t ldc, bool trans_out, T alpha, T beta, T* ws, size_t ws_elems, hipStream_t s) {
+         T* C, int64_t ldc, bool trans_out, T alpha, T beta, T* ws, size_t ws_elems, hipStream_t s,
+         const int32_t* gate, int gate_mode) {
     if (ta && tb) return RQLP_E_UNSUPPORTED;
     if (M <= 0 || N <= 0) return 0;
     GemmPlan p = plan_gemm(M, N, K);
     const bool direct = (p.S == 1 && !trans_out && alpha == T(1) && beta == T(0));
+    // the gated copy (gate_mode 2) writes op(A) straight into C: only for a
+    // direct product with op(A) = A of the output's shape
+    if (gate_mode == 2 && (!direct || ta || K != N)) return RQLP_E_UNSUPPORTED;
+    const int gate_copy = gate_mode == 2 ? 1 : 0;
     if (direct) {
-        launch_any<T>(ta, tb, p, M, N, K, A, lda, B, ldb, C, ldc, 0, s);
+        launch_any<T>(ta, tb, p, M, N, K, A, lda, B, ldb, C, ldc, 0, gate, gate_copy, s);
         return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
     }
     if ((size_t)(p.S * M * N) > ws_elems || ws == nullptr) return RQLP_E_WORKSPACE;
-    launch_any<T>(ta, tb, p, M, N, K, A, lda, B, ldb, ws, M, M * N, s);
+    launch_any<T>(ta, tb, p, M, N, K, A, lda, B, ldb, ws, M, M * N, gate, 0, s);
     if (trans_out) {
         dim3 grid((unsigned)ceil_div(M, 32), (unsigned)ceil_div(N, 32));
         hipLaunchKernelGGL((splitk_reduce_t_kernel<T>), grid, dim3(256), 0, s, M, N, ws, M, M * N, (int)p.S,
-                           alpha, beta, C, ldc);
+                           alpha, beta, C, ldc, gate);
     } else {
         hipLaunchKernelGGL((splitk_reduce_kernel<T>), dim3((unsigned)ceil_div(M * N, 256)), dim3(256), 0, s, M, N,
-                           ws, M, M * N, (int)p.S, alpha, beta, C, ldc);
+                           ws, M, M * N, (int)p.S, alpha, beta, C, ldc, gate);
     }
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 
 template int gemm<double>(bool, bool, int64_t, int64_t, int64_t, const double*, int64_t, const double*, int64_t,
-                          double*, int64_t, bool, double, double, double*, size_t, hipStream_t);
+                          double*, int64_t, bool, double, double, double*, size_t, hipStream_t, const int32_t*, int);
 template int gemm<float>(bool, bool, int64_t, int64_t, int64_t, const float*, int64_t, const float*, int64_t,
-                         float*, int64_t, bool, float, float, float*, size_t, hipStream_t);
+                         float*, int64_t, bool, float, float, float*, size_t, hipStream_t, const int32_t*, int);
 
 }  // namespace rqlp

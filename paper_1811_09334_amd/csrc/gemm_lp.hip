@@ -47,12 +47,14 @@ __device__ __forceinline__ float4_t mfma_lp(u16x8_t a, u16x8_t b, float4_t c) {
 }
 
 // X3: operands come in (hi, lo) pairs at the same offsets of P / Plo and Q / Qlo.
-template <int KIND, int NB, bool X3>
+// VEC: every 8-element k-chunk is 16-byte aligned and lies wholly inside or
+// outside [0, K) (K, ldp, ldq multiples of 8, aligned bases), so tiles load
+// with plain 16-byte loads; otherwise element loads with bounds checks.
+template <int KIND, int NB, bool X3, bool VEC>
 __global__ __launch_bounds__(LP_THREADS) void gemm_lp_kernel(
     int64_t M, int64_t N, int64_t K, const unsigned short* __restrict__ P, const unsigned short* __restrict__ Plo,
     int64_t ldp, const unsigned short* __restrict__ Q, const unsigned short* __restrict__ Qlo, int64_t ldq,
-    float* __restrict__ C, int64_t ldc, int64_t split_stride, int64_t kchunk, const int* __restrict__ rexp,
-    const int* __restrict__ gexp) {
+    float* __restrict__ C, int64_t ldc, int64_t split_stride, int64_t kchunk) {
     constexpr int NP = X3 ? 2 : 1;                                  // operand parts
     constexpr int BN = 16 * NB;
     constexpr int A_CH = LP_BM * LP_BK / 8 / LP_THREADS;            // 16-byte chunks per thread: 2
@@ -76,14 +78,12 @@ __global__ __launch_bounds__(LP_THREADS) void gemm_lp_kernel(
     // 16-byte chunk ch of a tile row: k = 8 (ch % 4) .. +7 of row ch / 4
     auto load8 = [&](const unsigned short* base, int64_t ld, int64_t row, int64_t rows, int64_t k) {
         u16x8_t v = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (row < rows) {
+        if constexpr (VEC) {
+            if (row < rows && k < kend) v = *(const u16x8_t*)(base + k + row * ld);
+        } else if (row < rows) {
             const unsigned short* p = base + k + row * ld;
-            if (k + 8 <= kend && (((uintptr_t)p) & 15) == 0) {
-                v = *(const u16x8_t*)p;
-            } else {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) v[e] = (k + e < kend) ? p[e] : (unsigned short)0;
-            }
+            for (int e = 0; e < 8; ++e) v[e] = (k + e < kend) ? p[e] : (unsigned short)0;
         }
         return v;
     };
@@ -155,31 +155,32 @@ __global__ __launch_bounds__(LP_THREADS) void gemm_lp_kernel(
     }
     // accumulator element r of lane l holds C(4 (l / 16) + r, l % 16)
     float* Cs = C + (int64_t)blockIdx.z * split_stride;
-    const int g = gexp ? *gexp : 0;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t i = m0 + wave * 32 + a * 16 + 4 * (lane >> 4) + r;
             if (i >= M) continue;
-            const int e = g + (rexp ? rexp[i] : 0);
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const int64_t j = n0 + b * 16 + fr;
-                if (j < N) Cs[i + j * ldc] = e ? ldexpf(acc[a][b][r], e) : acc[a][b][r];
+                if (j < N) Cs[i + j * ldc] = acc[a][b][r];
             }
         }
 }
 
-// C = sum_s W_s (M x N FP32 partials, fixed order), converted to TO, written
+// C = 2^(gexp + rexp[i]) sum_s W_s (M x N FP32 partials, fixed order; the
+// exponents only for the IEEE half form, else NULL), converted to TO, written
 // as C (M x N) or, transposed, as C^T (N x M) through 32 x 32 LDS tiles.
 template <typename TO, bool TRANS>
 __global__ __launch_bounds__(256) void lp_reduce_kernel(int64_t M, int64_t N, const float* __restrict__ W,
                                                         int64_t split_stride, int S, TO* __restrict__ C,
-                                                        int64_t ldc) {
+                                                        int64_t ldc, const int* __restrict__ rexp,
+                                                        const int* __restrict__ gexp) {
     __shared__ float tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
+    const int g = gexp ? *gexp : 0;
     for (int jj = ty; jj < 32; jj += 8) {
         const int64_t i = i0 + tx, j = j0 + jj;
         float v0 = 0.f, v1 = 0.f;
@@ -191,9 +192,11 @@ __global__ __launch_bounds__(256) void lp_reduce_kernel(int64_t M, int64_t N, co
                 v1 += w[(s + 1) * split_stride];
             }
             if (s < S) v0 += w[s * split_stride];
-            if (!TRANS) C[i + j * ldc] = (TO)(v0 + v1);
+            const int e = g + (rexp ? rexp[i] : 0);
+            v0 = e ? ldexpf(v0 + v1, e) : v0 + v1;
+            if (!TRANS) C[i + j * ldc] = (TO)v0;
         }
-        if (TRANS) tile[jj][tx] = v0 + v1;
+        if (TRANS) tile[jj][tx] = v0;
     }
     if (!TRANS) return;
     __syncthreads();
@@ -241,19 +244,26 @@ LpPlan plan_lp(int64_t M, int64_t N, int64_t K) {
 template <int KIND, int NB, bool X3>
 void launch_lp(const LpPlan& p, int64_t M, int64_t N, int64_t K, const unsigned short* P, const unsigned short* Plo,
                int64_t ldp, const unsigned short* Q, const unsigned short* Qlo, int64_t ldq, float* C, int64_t ldc,
-               int64_t ss, const int* rexp, const int* gexp, hipStream_t s) {
-    hipLaunchKernelGGL((gemm_lp_kernel<KIND, NB, X3>), dim3((unsigned)p.tm, (unsigned)p.tn, (unsigned)p.S),
-                       dim3(LP_THREADS), 0, s, M, N, K, P, Plo, ldp, Q, Qlo, ldq, C, ldc, ss, p.kchunk, rexp, gexp);
+               int64_t ss, hipStream_t s) {
+    auto al16 = [](const void* q) { return q == nullptr || (((uintptr_t)q) & 15) == 0; };
+    const bool vec = (K % 8 == 0) && (ldp % 8 == 0) && (ldq % 8 == 0) && al16(P) && al16(Plo) && al16(Q) && al16(Qlo);
+    const dim3 grid((unsigned)p.tm, (unsigned)p.tn, (unsigned)p.S);
+    if (vec)
+        hipLaunchKernelGGL((gemm_lp_kernel<KIND, NB, X3, true>), grid, dim3(LP_THREADS), 0, s, M, N, K, P, Plo, ldp, Q,
+                           Qlo, ldq, C, ldc, ss, p.kchunk);
+    else
+        hipLaunchKernelGGL((gemm_lp_kernel<KIND, NB, X3, false>), grid, dim3(LP_THREADS), 0, s, M, N, K, P, Plo, ldp,
+                           Q, Qlo, ldq, C, ldc, ss, p.kchunk);
 }
 
 template <int KIND, bool X3>
 void dispatch_lp(const LpPlan& p, int64_t M, int64_t N, int64_t K, const unsigned short* P,
                  const unsigned short* Plo, int64_t ldp, const unsigned short* Q, const unsigned short* Qlo,
-                 int64_t ldq, float* C, int64_t ldc, int64_t ss, const int* rexp, const int* gexp, hipStream_t s) {
+                 int64_t ldq, float* C, int64_t ldc, int64_t ss, hipStream_t s) {
     switch (p.nb) {
 #define RQLP_LP_CASE(X)                                                                                      \
     case X:                                                                                                  \
-        launch_lp<KIND, X, X3>(p, M, N, K, P, Plo, ldp, Q, Qlo, ldq, C, ldc, ss, rexp, gexp, s);            \
+        launch_lp<KIND, X, X3>(p, M, N, K, P, Plo, ldp, Q, Qlo, ldq, C, ldc, ss, s);                        \
         break;
         RQLP_LP_CASE(1) RQLP_LP_CASE(2) RQLP_LP_CASE(3) RQLP_LP_CASE(4) RQLP_LP_CASE(6)
         RQLP_LP_CASE(8) RQLP_LP_CASE(9) RQLP_LP_CASE(12) RQLP_LP_CASE(17) RQLP_LP_CASE(18)
@@ -276,23 +286,26 @@ int gemm_lp(int kind, int64_t M, int64_t N, int64_t K, const unsigned short* P, 
     const bool x3 = (Plo != nullptr && Qlo != nullptr);
     if (x3 != (kind == RQLP_MIXED_BF16X3)) return RQLP_E_UNSUPPORTED;
     LpPlan p = plan_lp(M, N, K);
-    const bool direct = (p.S == 1 && !trans_out && sizeof(TO) == sizeof(float));
+    const bool scaled = rexp != nullptr || gexp != nullptr;
+    const bool direct = (p.S == 1 && !trans_out && !scaled && sizeof(TO) == sizeof(float));
     float* dst = direct ? (float*)C : ws;
     const int64_t ld = direct ? ldc : M;
     if (!direct && ((size_t)(p.S * M * N) > ws_elems || ws == nullptr)) return RQLP_E_WORKSPACE;
     if (kind == RQLP_MIXED_FP16)
-        dispatch_lp<RQLP_MIXED_FP16, false>(p, M, N, K, P, Plo, ldp, Q, Qlo, ldq, dst, ld, M * N, rexp, gexp, s);
+        dispatch_lp<RQLP_MIXED_FP16, false>(p, M, N, K, P, Plo, ldp, Q, Qlo, ldq, dst, ld, M * N, s);
     else if (x3)
-        dispatch_lp<RQLP_MIXED_BF16, true>(p, M, N, K, P, Plo, ldp, Q, Qlo, ldq, dst, ld, M * N, rexp, gexp, s);
+        dispatch_lp<RQLP_MIXED_BF16, true>(p, M, N, K, P, Plo, ldp, Q, Qlo, ldq, dst, ld, M * N, s);
     else
-        dispatch_lp<RQLP_MIXED_BF16, false>(p, M, N, K, P, Plo, ldp, Q, Qlo, ldq, dst, ld, M * N, rexp, gexp, s);
+        dispatch_lp<RQLP_MIXED_BF16, false>(p, M, N, K, P, Plo, ldp, Q, Qlo, ldq, dst, ld, M * N, s);
     if (hipGetLastError() != hipSuccess) return RQLP_E_HIP;
     if (direct) return 0;
     dim3 grid((unsigned)ceil_div(M, 32), (unsigned)ceil_div(N, 32));
     if (trans_out)
-        hipLaunchKernelGGL((lp_reduce_kernel<TO, true>), grid, dim3(256), 0, s, M, N, ws, M * N, (int)p.S, C, ldc);
+        hipLaunchKernelGGL((lp_reduce_kernel<TO, true>), grid, dim3(256), 0, s, M, N, ws, M * N, (int)p.S, C, ldc, rexp,
+                           gexp);
     else
-        hipLaunchKernelGGL((lp_reduce_kernel<TO, false>), grid, dim3(256), 0, s, M, N, ws, M * N, (int)p.S, C, ldc);
+        hipLaunchKernelGGL((lp_reduce_kernel<TO, false>), grid, dim3(256), 0, s, M, N, ws, M * N, (int)p.S, C, ldc,
+                           rexp, gexp);
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 
@@ -359,6 +372,90 @@ __global__ __launch_bounds__(256) void cast_lp_kernel(int64_t rows, int64_t cols
             if (dlo) dlo[j + i * ldd] = t[1][tx][ii];
         }
     }
+}
+
+// Both 16-bit layouts of the m x n FP32 matrix A in one pass over A:
+// Ac (m x n, column-major, ldc) and Ar (= A^T, n x m, ldr), with the bf16x3
+// remainders (Aclo / Arlo) and the FP16 column exponents (cexp) as in
+// cast_lp_kernel.  64 x 64 tiles: 16-byte reads of A, 8-byte writes of Ac,
+// the transpose through LDS and 16-byte writes of Ar.  Needs m, lda, ldc
+// multiples of 4, ldr a multiple of 8 and 16-byte aligned bases.
+__global__ __launch_bounds__(256) void encode_both_kernel(int64_t m, int64_t n, const float* __restrict__ A,
+                                                          int64_t lda, unsigned short* __restrict__ Ac,
+                                                          unsigned short* __restrict__ Aclo, int64_t ldc,
+                                                          unsigned short* __restrict__ Ar,
+                                                          unsigned short* __restrict__ Arlo, int64_t ldr, int kind,
+                                                          const int* __restrict__ cexp) {
+    typedef unsigned short u16x4_t __attribute__((ext_vector_type(4)));
+    __shared__ __attribute__((aligned(16))) unsigned short t[2][64][64 + 8];   // [part][column][row]
+    const int tid = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
+    const bool split = Aclo != nullptr;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int idx = tid + 256 * e;
+        const int cj = idx >> 4, ri = (idx & 15) * 4;
+        const int64_t i = i0 + ri, j = j0 + cj;
+        u16x4_t v = {0, 0, 0, 0}, vl = {0, 0, 0, 0};
+        if (j < n && i < m) {
+            const float4_t x = *(const float4_t*)(A + i + j * lda);     // m % 4 == 0: whole chunk inside
+            const int ex = cexp ? -cexp[j] : 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float y = ex ? ldexpf(x[q], ex) : x[q];
+                if (kind == RQLP_MIXED_FP16) {
+                    v[q] = f32_to_f16_bits(y);
+                } else {
+                    v[q] = f32_to_bf16_bits(y);
+                    if (split) vl[q] = f32_to_bf16_bits(y - bf16_bits_to_f32(v[q]));
+                }
+            }
+            *(u16x4_t*)(Ac + i + j * ldc) = v;
+            if (split) *(u16x4_t*)(Aclo + i + j * ldc) = vl;
+        }
+        *(u16x4_t*)&t[0][cj][ri] = v;
+        *(u16x4_t*)&t[1][cj][ri] = vl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int idx = tid + 256 * e;
+        const int ri = idx >> 3, cc = (idx & 7) * 8;
+        const int64_t i = i0 + ri, j = j0 + cc;
+        if (i >= m || j >= n) continue;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            unsigned short* D = h ? Arlo : Ar;
+            if (!D) continue;
+            u16x8_t v;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = t[h][cc + q][ri];
+            if (j + 8 <= n) {
+                *(u16x8_t*)(D + j + i * ldr) = v;
+            } else {
+                for (int q = 0; q < 8; ++q)
+                    if (j + q < n) D[j + q + i * ldr] = v[q];
+            }
+        }
+    }
+}
+
+int encode_both(int kind, int64_t m, int64_t n, const float* A, int64_t lda, unsigned short* Ac, unsigned short* Aclo,
+                int64_t ldc, unsigned short* Ar, unsigned short* Arlo, int64_t ldr, const int* cexp, hipStream_t s) {
+    if (m <= 0 || n <= 0) return 0;
+    if ((kind == RQLP_MIXED_BF16X3) != (Aclo != nullptr) || (Aclo != nullptr) != (Arlo != nullptr))
+        return RQLP_E_UNSUPPORTED;
+    auto al16 = [](const void* q) { return q == nullptr || (((uintptr_t)q) & 15) == 0; };
+    const bool fast = m % 4 == 0 && lda % 4 == 0 && ldc % 4 == 0 && ldr % 8 == 0 && al16(A) && al16(Ac) &&
+                      al16(Aclo) && al16(Ar) && al16(Arlo);
+    if (!fast) {
+        RQLP_TRY(cast_to_lp(kind, m, n, A, lda, Ac, Aclo, ldc, false, nullptr, cexp, nullptr, s));
+        return cast_to_lp(kind, m, n, A, lda, Ar, Arlo, ldr, true, nullptr, cexp, nullptr, s);
+    }
+    dim3 grid((unsigned)ceil_div(m, 64), (unsigned)ceil_div(n, 64));
+    hipLaunchKernelGGL(encode_both_kernel, grid, dim3(256), 0, s, m, n, A, lda, Ac, Aclo, ldc, Ar, Arlo, ldr, kind,
+                       cexp);
+    return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 
 int cast_to_lp(int kind, int64_t rows, int64_t cols, const float* src, int64_t lds_, unsigned short* dst,

@@ -10,11 +10,15 @@ namespace rqlp {
 // or A^T (ta = true, A is K x M); op(B) = B (tb = false, B is K x N) or B^T
 // (tb = true, B is N x K; not combined with ta); C is M x N, or N x M when
 // trans_out (C = (op(A) op(B))^T).  ws must hold gemm_workspace_elems(M, N, K)
-// elements unless the product goes straight to C.
+// elements unless the product goes straight to C.  Conditional products:
+// gate (device word, optional) read at run time; when it is 0, gate_mode 1
+// computes nothing, gate_mode 2 copies op(A) to C (the product with an
+// identity B, direct products with op(A) = A and K == N only).
 size_t gemm_workspace_elems(int64_t M, int64_t N, int64_t K);
 template <typename T>
 int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64_t ldb,
-         T* C, int64_t ldc, bool trans_out, T alpha, T beta, T* ws, size_t ws_elems, hipStream_t s);
+         T* C, int64_t ldc, bool trans_out, T alpha, T beta, T* ws, size_t ws_elems, hipStream_t s,
+         const int32_t* gate = nullptr, int gate_mode = 0);
 
 // --- gemm_lp.hip ------------------------------------------------------------
 // C(i, j) = 2^(gexp + rexp[i]) sum_k P(k + i ldp) Q(k + j ldq) with 16-bit
@@ -32,6 +36,9 @@ int gemm_lp(int kind, int64_t M, int64_t N, int64_t K, const unsigned short* P, 
 int cast_to_lp(int kind, int64_t rows, int64_t cols, const float* src, int64_t lds, unsigned short* dst,
                unsigned short* dlo, int64_t ldd, bool transpose, const int* rexp, const int* cexp, const int* gexp,
                hipStream_t s);
+// both 16-bit layouts of A (column-major Ac and A^T in Ar) in one pass
+int encode_both(int kind, int64_t m, int64_t n, const float* A, int64_t lda, unsigned short* Ac, unsigned short* Aclo,
+                int64_t ldc, unsigned short* Ar, unsigned short* Arlo, int64_t ldr, const int* cexp, hipStream_t s);
 // per-column power-of-two exponents of an FP32 matrix for IEEE half storage
 int column_exponents(int64_t rows, int64_t cols, const float* A, int64_t lda, int* colexp, int* gexp,
                      hipStream_t s);
@@ -46,8 +53,9 @@ int cast_matrix(int64_t rows, int64_t cols, const S* src, int64_t lds, D* dst, i
 // diagonal); both are also the kernel's working storage.  G may be FP32 (it
 // is widened); Linv32 (optional, leading dimension ld) gets Linv in FP32.
 // run_flag (optional device word): when it reads 0 the kernel only writes
-// identities (a conditional extra pass); shifted_out (optional) receives 1
-// when the shifted retry was used, else 0.
+// identities (a conditional extra pass); shifted_out (optional): with
+// shifted_mode 1 it receives 1 when the shifted retry was used, else 0; with
+// shifted_mode 2 it is only ever set to 1 (accumulates over passes).
 // sync: CHOL_SYNC_WORDS words of device scratch (flags of the multi-workgroup
 // kernel used for c <= CHOL_MW_MAXC); NULL selects the one-workgroup kernel.
 constexpr int CHOL_MW_MAXC = 512;
@@ -56,11 +64,11 @@ size_t chol_inv_lds_bytes(int64_t c);
 template <typename TG>
 int chol_inv(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
              double shift_scale, int32_t* info, hipStream_t s, const int32_t* run_flag = nullptr,
-             int32_t* shifted_out = nullptr, unsigned* sync = nullptr);
+             int32_t* shifted_out = nullptr, unsigned* sync = nullptr, int shifted_mode = 1);
 template <typename TG>
 int chol_mw(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
             double shift_scale, int32_t* info, unsigned* sync, hipStream_t s, const int32_t* run_flag,
-            int32_t* shifted_out);
+            int32_t* shifted_out, int shifted_mode);
 
 // --- cpqr.hip ---------------------------------------------------------------
 struct CpqrScratch {
