@@ -302,33 +302,68 @@ struct RangeBufsLP {
     float* QB;              // l x l
     double* Pd;             // n x l
     int32_t* shifted;       // 1 word
+    float* B32;             // l x n (FP32 form: projection before widening)
 };
 
+// Buffers of the FP32 and mixed-precision range finders (the FP32 form needs
+// no 16-bit copies and runs every product as an FP32 MFMA product).
 void carve_range_lp(Arena& ar, int64_t m, int64_t n, int64_t l, int precision, bool need_omega, RangeBufsLP* r) {
     const bool x3 = precision == RQLP_MIXED_BF16X3;
-    r->Ac = ar.take<unsigned short>(m * n);
-    r->Ar = ar.take<unsigned short>(m * n);
+    const bool f32 = precision == RQLP_F32;
+    r->Ac = f32 ? nullptr : ar.take<unsigned short>(m * n);
+    r->Ar = f32 ? nullptr : ar.take<unsigned short>(m * n);
     r->Aclo = x3 ? ar.take<unsigned short>(m * n) : nullptr;
     r->Arlo = x3 ? ar.take<unsigned short>(m * n) : nullptr;
     r->colexp = ar.take<int>(n);
     r->gexp = ar.take<int>(1);
     r->Om = need_omega ? ar.take<float>(n * l) : nullptr;
     const int64_t mx = m > n ? m : n;
-    r->X16 = ar.take<unsigned short>(mx * l);
+    r->X16 = f32 ? nullptr : ar.take<unsigned short>(mx * l);
     r->X16lo = x3 ? ar.take<unsigned short>(mx * l) : nullptr;
     r->Y = ar.take<float>(m * l);
     r->Y2 = ar.take<float>(m * l);
     r->Z = ar.take<float>(n * l);
     r->Z2 = ar.take<float>(n * l);
-    r->lpws_elems = max_ws(gemm_lp_workspace_elems, {{m, l, n}, {n, l, m}});
-    r->lpws = ar.take<float>(r->lpws_elems);
-    r->fws_elems = max_ws(gemm_workspace_elems, {{l, l, m}, {l, l, n}, {m, l, l}, {n, l, l}});
+    r->lpws_elems = f32 ? 0 : max_ws(gemm_lp_workspace_elems, {{m, l, n}, {n, l, m}});
+    r->lpws = f32 ? nullptr : ar.take<float>(r->lpws_elems);
+    r->fws_elems = f32 ? max_ws(gemm_workspace_elems, {{l, l, m}, {l, l, n}, {m, l, l}, {n, l, l}, {m, l, n}, {n, l, m}})
+                       : max_ws(gemm_workspace_elems, {{l, l, m}, {l, l, n}, {m, l, l}, {n, l, l}});
     r->fws = ar.take<float>(r->fws_elems);
+    r->B32 = f32 ? ar.take<float>(l * n) : nullptr;
     r->G = ar.take<float>(l * l);
     r->Li = ar.take<float>(l * l);
     r->QB = ar.take<float>(l * l);
     r->Pd = ar.take<double>(n * l);
     r->shifted = ar.take<int32_t>(1);
+}
+
+// FP32 range finder and projection (RQLP_F32): every pass over A is an FP32
+// MFMA product, the panels are orthonormalised by FP32 CholeskyQR, and
+// B = V^T A is widened to FP64 for the small stage.  Returns V (m x l).
+int range_and_project_f32(Ctx32& c32, RangeBufsLP& r, SmallBufs& f, const float* A, int64_t lda, int64_t m,
+                          int64_t n, int64_t l, int q, uint64_t seed, const float* Om, int64_t ldom, float** Vout) {
+    hipStream_t s = c32.s;
+    if (!Om) {
+        RQLP_TRY(generate_omega(n, l, seed, RQLP_F32, r.Om, n, s));
+        Om = r.Om;
+        ldom = n;
+    }
+    RQLP_TRY(gemm<float>(false, false, m, l, n, A, lda, Om, ldom, r.Y, m, false, 1.0f, 0.0f, r.fws, r.fws_elems, s));
+    float* V = nullptr;
+    RQLP_TRY(cholqr_f32(c32, m, l, r.Y, r.Y2, m, &V, q == 0));
+    for (int it = 0; it < q; ++it) {
+        RQLP_TRY(gemm<float>(true, false, n, l, m, A, lda, V, m, r.Z, n, false, 1.0f, 0.0f, r.fws, r.fws_elems, s));
+        float* W = nullptr;
+        RQLP_TRY(cholqr_f32(c32, n, l, r.Z, r.Z2, n, &W, false));
+        float* ydst = (V == r.Y) ? r.Y2 : r.Y;
+        RQLP_TRY(gemm<float>(false, false, m, l, n, A, lda, W, n, ydst, m, false, 1.0f, 0.0f, r.fws, r.fws_elems, s));
+        float* other = (ydst == r.Y) ? r.Y2 : r.Y;
+        RQLP_TRY(cholqr_f32(c32, m, l, ydst, other, m, &V, it == q - 1));
+    }
+    RQLP_TRY(gemm<float>(true, false, n, l, m, A, lda, V, m, r.B32, l, true, 1.0f, 0.0f, r.fws, r.fws_elems, s));
+    RQLP_TRY((cast_matrix<float, double>(l, n, r.B32, l, f.B, l, s)));
+    *Vout = V;
+    return 0;
 }
 
 bool valid_precision(int p) { return p >= RQLP_F64 && p <= RQLP_MIXED_BF16X3; }
@@ -502,7 +537,7 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
     if (!P) return -18;
     if (ldp < n) return -19;
     if (!work) return -25;
-    if (b != 0 || precision == RQLP_F32) return RQLP_E_UNSUPPORTED;
+    if (b != 0) return RQLP_E_UNSUPPORTED;
 
     hipStream_t s = (hipStream_t)stream;
     Arena ar = arena_for(work, work_bytes);
@@ -533,8 +568,12 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
         RangeBufsLP& r = Lay.rlp;
         Ctx32 c32{s, inf, r.fws, r.fws_elems, r.G, r.Li, f.o.L1, f.o.Li, r.shifted, f.o.sync};
         float* V = nullptr;
-        RQLP_TRY(range_and_project_lp(c32, r, f, precision, (const float*)A, lda, m, n, l, q, seed,
-                                      (const float*)Omega, ldo, &V));
+        if (precision == RQLP_F32)
+            RQLP_TRY(range_and_project_f32(c32, r, f, (const float*)A, lda, m, n, l, q, seed, (const float*)Omega,
+                                           ldo, &V));
+        else
+            RQLP_TRY(range_and_project_lp(c32, r, f, precision, (const float*)A, lda, m, n, l, q, seed,
+                                          (const float*)Omega, ldo, &V));
         RQLP_TRY(qlp_of_B(cx, f, l, n, d, r.Pd, n, T, ldt, &tri, &QB));
         // assembly in FP32: P = P_B, Q = V Q_B
         RQLP_TRY((cast_matrix<double, float>(n, l, r.Pd, n, (float*)P, ldp, s)));

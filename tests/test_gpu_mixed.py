@@ -177,3 +177,25 @@ def test_encoded_projection_equals_one_shot_projection(gpu, kind):
     B1 = to_np(gpu.project_encoded(E, Vd))
     B2 = to_np(gpu.project(Ad, Vd, precision=kind))
     assert np.array_equal(B1, B2)
+
+
+@pytest.mark.parametrize("m,n,k,p,q,d", [(1000, 500, 20, 5, 1, 0), (2048, 1024, 100, 12, 2, 2), (777, 333, 40, 8, 0, 1)])
+def test_f32_path_matches_oracle(gpu, m, n, k, p, q, d):
+    """FP32 forward (FP32 MFMA products and CholeskyQR, FP64 small stage): L-values
+    within 1e-5 of the FP64 oracle run on the same pivots; free comparison reported."""
+    rng = np.random.default_rng(m + 3 * n)
+    A = (rng.standard_normal((m, n)) / np.sqrt(n) +
+         inputs.svd_matrix(m, n, np.r_[10.0 / np.arange(1, 17), np.zeros(n - 16)], m + n)).astype(np.float32)
+    Om = rng.standard_normal((n, k + p)).astype(np.float32).astype(np.float64)
+    f, g = _mixed_factor(gpu, A, Om, k, p, q, d, "f32")
+    assert int(g["info"][0]) == 0
+    frozen = oracle_rqlp(A.astype(np.float64), Om, k, p, q=q, d=d, piv0=g["piv0"], piv1=g["piv1"] if d == 0 else None)
+    rel = np.abs(g["lvals"][:k] - frozen.lvals[:k]) / frozen.lvals[:k]
+    free = oracle_rqlp(A.astype(np.float64), Om, k, p, q=q, d=d)
+    rel_free = np.abs(g["lvals"][:k] - free.lvals[:k]) / free.lvals[:k]
+    print(f"[f32 {A.shape} k={k} q={q} d={d}] frozen {rel.max():.2e} free {rel_free.max():.2e} "
+          f"divergence {first_difference(g['piv0'], free.piv0)}")
+    assert rel.max() < 1e-5
+    Q, P = g["Q"].astype(np.float64), g["P"].astype(np.float64)
+    l = k + p
+    assert np.abs(Q.T @ Q - np.eye(l)).max() < 2e-5 and np.abs(P.T @ P - np.eye(l)).max() < 2e-5

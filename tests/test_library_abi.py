@@ -111,5 +111,4 @@ def test_mixed_workspace_holds_the_16bit_copies(lib):
 
 
 def test_unsupported_combinations_are_reported(lib):
-    assert _factor_status(precision=1) == -1002      # FP32 forward
     assert _factor_status(b=4) == -1002              # block RQLP
