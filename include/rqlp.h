@@ -70,6 +70,7 @@ enum rqlp_status {
 #define RQLP_INFO_NONFINITE        0x4  /* NaN / Inf met in A or an intermediate     */
 #define RQLP_INFO_BARRIER_TIMEOUT  0x8  /* a grid-wide wait exceeded its spin bound  */
 #define RQLP_INFO_CHOL_FAILED      0x10 /* Cholesky failed even after the shift      */
+#define RQLP_INFO_BAD_PIVOTS       0x20 /* rqlp_backward: frozen pivots not valid    */
 
 /* Library version string (host, static storage). */
 const char* rqlp_version(void);
@@ -139,6 +140,44 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
                 void* work, size_t work_bytes, void* stream);
 
 /* ---- building blocks (the steps of Algorithm 2.1, usable on their own) ---- */
+
+/* Adjoint of rqlp_factor with frozen pivots: dA = d<dT, T>/dA, the gradient
+ * of any loss of the triangular factor T (the L-values of Section 1 are
+ * diag(T)) with respect to A.  The pivot sequences piv0 / piv1 returned by
+ * the forward call are held fixed, which makes T a smooth function of A
+ * (any fixed pivot order gives a valid QLP).  The forward pipeline
+ * (Algorithm 2.1 with q subspace iterations) is recomputed from A and Omega
+ * inside the call; nothing has to be kept from the forward call.
+ *
+ *   A, lda, m, n, k, p, q, d, b, precision, seed, Omega, ldo: as for the
+ *          forward call that produced the pivots (same Omega, or same seed
+ *          with Omega == NULL).  Supported here: d == 0, b == 0,
+ *          precision RQLP_F64 or RQLP_F32 (others: RQLP_E_UNSUPPORTED).
+ *   piv0   l int64: the forward's first pivots (distinct, in [0, n)).
+ *   piv1   l int64: the forward's second pivots (a permutation of [0, l)).
+ *          Invalid pivots set RQLP_INFO_BAD_PIVOTS in *info; dA is then
+ *          meaningless but no memory outside the arguments is touched.
+ *   dT     l x l double (lddt >= l): cotangent of T; entries above the
+ *          diagonal are ignored (T is lower triangular for d == 0).
+ *   dQ, dP cotangents of Q and P: must be NULL (not supported here).
+ *   saved  must be NULL (no forward state is kept; always recomputed).
+ *   dA     m x n output (ldda >= m), element type of A; overwritten.
+ *   info   device int32 (may be NULL): RQLP_INFO_* flags, overwritten.
+ *   work   device workspace, >= rqlp_backward_workspace_size() bytes.
+ * Arithmetic: the passes over A and the panel orthonormalisations in the
+ * precision of A; the l x l and n x l algebra in FP64. */
+int rqlp_backward(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int64_t p,
+                  int q, int d, int b, int precision, uint64_t seed,
+                  const void* Omega, int64_t ldo, const int64_t* piv0, const int64_t* piv1,
+                  const double* dT, int64_t lddt, const void* dQ, int64_t lddq,
+                  const void* dP, int64_t lddp, const void* saved,
+                  void* dA, int64_t ldda, int32_t* info, void* work, size_t work_bytes,
+                  void* stream);
+
+/* Bytes of device workspace rqlp_backward needs (host out).  Arguments as
+ * for rqlp_backward; RQLP_E_UNSUPPORTED for the combinations it rejects. */
+int rqlp_backward_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p, int q, int d, int b,
+                                 int precision, size_t* bytes);
 
 /* Y = A X  (Algorithm 2.1 step 2, and every pass of the subspace iteration):
  * A m x n, X n x c, Y m x c, all double (RQLP_F64) or all float (any other

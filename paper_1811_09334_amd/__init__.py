@@ -19,7 +19,7 @@ from . import _lib
 
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "fp16": 3, "bf16x3": 4}
 INFO_FLAGS = {"cholqr_shifted": 0x1, "rank_deficient": 0x2, "nonfinite": 0x4, "barrier_timeout": 0x8,
-              "chol_failed": 0x10}
+              "chol_failed": 0x10, "bad_pivots": 0x20}
 
 
 def _torch():
@@ -127,6 +127,84 @@ def factor(A, k: int, p: int, q: int = 0, d: int = 0, b: int = 0, precision="f64
                           ctypes.byref(uplo), work.data_ptr(), work.numel(), _stream(dev))
     check("rqlp_factor", st)
     return Factorization(Q=Q, T=T, P=P, piv0=piv0, piv1=piv1, lvals=lv, info=info, uplo=uplo.value.decode())
+
+
+def backward(A, k: int, p: int, piv0, piv1, dT, q: int = 0, d: int = 0, b: int = 0, precision=None, seed: int = 0,
+             Omega=None, work=None):
+    """dA = d<dT, T>/dA with the pivots frozen, through ``rqlp_backward``.
+
+    ``A``, ``q``, ``d``, ``b``, ``precision``, ``seed`` and ``Omega`` as in the
+    forward ``factor`` call that produced ``piv0`` / ``piv1``; ``dT`` is an
+    l x l float64 device tensor.  Returns (dA, info)."""
+    torch = _torch()
+    load()
+    if precision is None:
+        precision = "f64" if A.dtype == torch.float64 else "f32"
+    prec = _prec(precision)
+    A = colmajor(A)
+    m, n = A.shape
+    l = k + p
+    dev = A.device
+    dT = colmajor(dT.to(torch.float64))
+    if Omega is not None:
+        Omega = colmajor(Omega)
+    dA = empty_colmajor(m, n, A.dtype, dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    nbytes = _lib.rqlp_backward_workspace_size(m, n, k, p, q, d, b, prec)
+    if work is None or work.numel() < nbytes:
+        work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    piv0 = piv0.to(torch.int64).contiguous()
+    piv1 = piv1.to(torch.int64).contiguous()
+    st = _lib.rqlp_backward(A.data_ptr(), ld(A), m, n, k, p, q, d, b, prec, seed, _ptr(Omega),
+                            ld(Omega) if Omega is not None else max(n, 1), piv0.data_ptr(), piv1.data_ptr(),
+                            dT.data_ptr(), ld(dT), None, max(m, 1), None, max(n, 1), None, dA.data_ptr(), ld(dA),
+                            info.data_ptr(), work.data_ptr(), work.numel(), _stream(dev))
+    check("rqlp_backward", st)
+    return dA, info
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class RQLPFunction(torch.autograd.Function):
+        """T (differentiable), Q, P of the randomized QLP; the backward calls
+        rqlp_backward with the forward's pivots frozen (Q and P carry no
+        gradient)."""
+
+        @staticmethod
+        def forward(ctx, A, k, p, q, d, precision, seed, Omega):
+            f = factor(A.detach(), k, p, q=q, d=d, precision=precision, seed=seed, Omega=Omega)
+            ctx.save_for_backward(A, f.piv0, f.piv1)
+            ctx.args = (k, p, q, d, precision, seed, Omega)
+            ctx.mark_non_differentiable(f.Q, f.P)
+            return f.T, f.Q, f.P
+
+        @staticmethod
+        def backward(ctx, dT, dQ, dP):
+            A, piv0, piv1 = ctx.saved_tensors
+            k, p, q, d, precision, seed, Omega = ctx.args
+            if dT is None:
+                return (None,) * 8
+            dA, _ = backward(A.detach(), k, p, piv0, piv1, dT, q=q, d=d, precision=precision, seed=seed,
+                             Omega=Omega)
+            return dA, None, None, None, None, None, None, None
+
+    return RQLPFunction
+
+
+_RQLP_FN = None
+
+
+def rqlp(A, k: int, p: int, q: int = 0, d: int = 0, precision=None, seed: int = 0, Omega=None):
+    """Differentiable randomized QLP: returns (T, Q, P) with T differentiable
+    with respect to A (pivots frozen at the forward's choice)."""
+    global _RQLP_FN
+    torch = _torch()
+    if _RQLP_FN is None:
+        _RQLP_FN = _autograd_function()
+    if precision is None:
+        precision = "f64" if A.dtype == torch.float64 else "f32"
+    return _RQLP_FN.apply(A, k, p, q, d, precision, seed, Omega)
 
 
 def generate_omega(n: int, l: int, seed: int, precision="f64", device="cuda"):

@@ -25,6 +25,12 @@ SIGNATURES = {
                             c_uint64, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                             c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_char), c_void_p, c_size_t,
                             c_void_p]),
+    "rqlp_backward": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_int64, c_int64, c_int, c_int, c_int, c_int,
+                              c_uint64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_int64,
+                              c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_size_t,
+                              c_void_p]),
+    "rqlp_backward_workspace_size": (c_int, [c_int64, c_int64, c_int64, c_int64, c_int, c_int, c_int, c_int,
+                                             POINTER(c_size_t)]),
     "rqlp_sketch": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_int64, c_void_p, c_int64,
                             c_int, c_void_p, c_size_t, c_void_p]),
     "rqlp_project": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_int64, c_void_p, c_int64,
@@ -99,6 +105,19 @@ def rqlp_factor(A, lda, m, n, k, p, q, d, b, precision, seed, Omega, ldo, Q, ldq
                 piv0, piv1, lvals, info, uplo, work, work_bytes, stream) -> int:
     return _call("rqlp_factor", A, lda, m, n, k, p, q, d, b, precision, seed, Omega, ldo, Q, ldq, T, ldt, P, ldp,
                  piv0, piv1, lvals, info, uplo, work, work_bytes, stream)
+
+
+def rqlp_backward(A, lda, m, n, k, p, q, d, b, precision, seed, Omega, ldo, piv0, piv1, dT, lddt, dQ, lddq, dP,
+                  lddp, saved, dA, ldda, info, work, work_bytes, stream) -> int:
+    return _call("rqlp_backward", A, lda, m, n, k, p, q, d, b, precision, seed, Omega, ldo, piv0, piv1, dT, lddt,
+                 dQ, lddq, dP, lddp, saved, dA, ldda, info, work, work_bytes, stream)
+
+
+def rqlp_backward_workspace_size(m, n, k, p, q, d, b, precision) -> int:
+    out = c_size_t(0)
+    check("rqlp_backward_workspace_size", _call("rqlp_backward_workspace_size", m, n, k, p, q, d, b, precision,
+                                                ctypes.byref(out)))
+    return out.value
 
 
 def rqlp_sketch(A, lda, m, n, X, ldx, c, Y, ldy, precision, work, work_bytes, stream) -> int:

@@ -55,10 +55,12 @@ constexpr int GEMM_BK = 16;        // K depth of one LDS stage (two stages resid
 constexpr int GEMM_MAX_NB = 7;     // at most 7 blocks of 16 columns per tile: 3 workgroups per CU
 constexpr int GEMM_THREADS = 256;
 
-template <typename T, bool TA, bool TB, int MB, int NB, int BK>
+// T: arithmetic (MFMA) type; TI: element type of A and B (converted to T on
+// load); TC: element type of C / of the split-K partials.
+template <typename T, bool TA, bool TB, int MB, int NB, int BK, typename TI, typename TC>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
-    int64_t M, int64_t N, int64_t K, const T* __restrict__ A, int64_t lda,
-    const T* __restrict__ B, int64_t ldb, T* __restrict__ C, int64_t ldc, int64_t split_stride,
+    int64_t M, int64_t N, int64_t K, const TI* __restrict__ A, int64_t lda,
+    const TI* __restrict__ B, int64_t ldb, TC* __restrict__ C, int64_t ldc, int64_t split_stride,
     int64_t kchunk, const int32_t* __restrict__ gate, int gate_copy) {
     constexpr int BM = 64 * MB;
     constexpr int BN = 16 * NB;
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
         if (gate_copy && !TA)
             for (int idx = tid; idx < BM * BN; idx += GEMM_THREADS) {
                 const int64_t i = m0 + idx % BM, j = n0 + idx / BM;
-                if (i < M && j < N) C[i + j * ldc] = A[i + j * lda];
+                if (i < M && j < N) C[i + j * ldc] = (TC)A[i + j * lda];
             }
         return;
     }
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
                 for (int c = 0; c < BK / 4; ++c) {
                     const int64_t i = m0 + (tid & 63) + 64 * r;
                     const int64_t k = kt + (tid >> 6) + 4 * c;
-                    ra[r * (BK / 4) + c] = (i < M && k < kend) ? A[i + k * lda] : T(0);
+                    ra[r * (BK / 4) + c] = (i < M && k < kend) ? (T)A[i + k * lda] : T(0);
                 }
         } else {
             // op(A) = A^T: k = tid % BK, i = tid / BK + KSTEP r (runs along k)
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
             for (int r = 0; r < A_PER_T; ++r) {
                 const int64_t k = kt + (tid % BK);
                 const int64_t i = m0 + (tid / BK) + KSTEP * r;
-                ra[r] = (i < M && k < kend) ? A[k + i * lda] : T(0);
+                ra[r] = (i < M && k < kend) ? (T)A[k + i * lda] : T(0);
             }
         }
         if (!TB) {
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
             for (int r = 0; r < B_PER_T; ++r) {
                 const int64_t k = kt + (tid % BK);
                 const int64_t j = n0 + (tid / BK) + KSTEP * r;
-                rb[r] = (j < N && k < kend) ? B[k + j * ldb] : T(0);
+                rb[r] = (j < N && k < kend) ? (T)B[k + j * ldb] : T(0);
             }
         } else {
             // op(B) = B^T, B stored N x K: consecutive threads run along j
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
                 const int e = tid + GEMM_THREADS * r;
                 const int64_t j = n0 + e % BN;
                 const int64_t k = kt + e / BN;
-                rb[r] = (j < N && k < kend) ? B[j + k * ldb] : T(0);
+                rb[r] = (j < N && k < kend) ? (T)B[j + k * ldb] : T(0);
             }
         }
     };
@@ -201,7 +203,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
     }
 
     // ---- write C (or this split's partial) ----
-    T* Cs = C + (int64_t)blockIdx.z * split_stride;
+    TC* Cs = C + (int64_t)blockIdx.z * split_stride;
 #pragma unroll
     for (int a = 0; a < MB; ++a)
 #pragma unroll
@@ -211,17 +213,17 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = m0 + wave * 16 * MB + a * 16 + Mfma<T>::row(lane, r);
-                if (i < M) Cs[i + j * ldc] = acc[a][b][r];
+                if (i < M) Cs[i + j * ldc] = (TC)acc[a][b][r];
             }
         }
 }
 
 // C (M x N) = alpha * sum_s W_s + beta * C, one output element per thread,
 // summed in the fixed order s = 0, 1, ...
-template <typename T>
+template <typename T, typename TO>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(int64_t M, int64_t N, const T* __restrict__ W,
                                                             int64_t ldw, int64_t split_stride, int S, T alpha,
-                                                            T beta, T* __restrict__ C, int64_t ldc,
+                                                            T beta, TO* __restrict__ C, int64_t ldc,
                                                             const int32_t* __restrict__ gate) {
     if (gate != nullptr && *gate == 0) return;
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -236,15 +238,15 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(int64_t M, int64_t N
     }
     if (s < S) v0 += w[s * split_stride];
     T v = alpha * (v0 + v1);
-    if (beta != T(0)) v += beta * C[i + j * ldc];
-    C[i + j * ldc] = v;
+    if (beta != T(0)) v += beta * (T)C[i + j * ldc];
+    C[i + j * ldc] = (TO)v;
 }
 
 // C (N x M) = (alpha * sum_s W_s + beta * C^T)^T through 32 x 32 LDS tiles.
-template <typename T>
+template <typename T, typename TO>
 __global__ __launch_bounds__(256) void splitk_reduce_t_kernel(int64_t M, int64_t N, const T* __restrict__ W,
                                                               int64_t ldw, int64_t split_stride, int S, T alpha,
-                                                              T beta, T* __restrict__ C, int64_t ldc,
+                                                              T beta, TO* __restrict__ C, int64_t ldc,
                                                               const int32_t* __restrict__ gate) {
     if (gate != nullptr && *gate == 0) return;
     __shared__ T tile[32][33];
@@ -264,8 +266,8 @@ __global__ __launch_bounds__(256) void splitk_reduce_t_kernel(int64_t M, int64_t
         const int64_t j = j0 + tx, i = i0 + ii;
         if (i < M && j < N) {
             T v = tile[tx][ii];
-            if (beta != T(0)) v += beta * C[j + i * ldc];
-            C[j + i * ldc] = v;
+            if (beta != T(0)) v += beta * (T)C[j + i * ldc];
+            C[j + i * ldc] = (TO)v;
         }
     }
 }
@@ -309,22 +311,24 @@ GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K) {
     return p;
 }
 
-template <typename T, bool TA, bool TB, int NB>
-void launch_nb(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda,
-               const T* B, int64_t ldb, T* C, int64_t ldc, int64_t split_stride, const int32_t* gate, int gate_copy,
+template <typename T, typename TI, typename TC, bool TA, bool TB, int NB>
+void launch_nb(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const TI* A, int64_t lda,
+               const TI* B, int64_t ldb, TC* C, int64_t ldc, int64_t split_stride, const int32_t* gate, int gate_copy,
                hipStream_t s) {
     dim3 grid((unsigned)p.tm, (unsigned)p.tn, (unsigned)p.S);
-    hipLaunchKernelGGL((gemm_skinny_kernel<T, TA, TB, 1, NB, GEMM_BK>), grid, dim3(GEMM_THREADS), 0, s, M, N, K, A,
-                       lda, B, ldb, C, ldc, split_stride, p.kchunk, gate, gate_copy);
+    hipLaunchKernelGGL((gemm_skinny_kernel<T, TA, TB, 1, NB, GEMM_BK, TI, TC>), grid, dim3(GEMM_THREADS), 0, s, M, N,
+                       K, A, lda, B, ldb, C, ldc, split_stride, p.kchunk, gate, gate_copy);
 }
 
-template <typename T, bool TA, bool TB>
-void launch_dispatch(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda,
-                     const T* B, int64_t ldb, T* C, int64_t ldc, int64_t split_stride, const int32_t* gate,
+template <typename T, typename TI, typename TC, bool TA, bool TB>
+void launch_dispatch(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const TI* A, int64_t lda,
+                     const TI* B, int64_t ldb, TC* C, int64_t ldc, int64_t split_stride, const int32_t* gate,
                      int gate_copy, hipStream_t s) {
     switch (p.nb) {
-#define RQLP_NB_CASE(X) \
-    case X: launch_nb<T, TA, TB, X>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, s); break;
+#define RQLP_NB_CASE(X)                                                                                           \
+    case X:                                                                                                       \
+        launch_nb<T, TI, TC, TA, TB, X>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, s);    \
+        break;
         RQLP_NB_CASE(1) RQLP_NB_CASE(2) RQLP_NB_CASE(3) RQLP_NB_CASE(4)
         RQLP_NB_CASE(5) RQLP_NB_CASE(6) RQLP_NB_CASE(7)
 #undef RQLP_NB_CASE
@@ -338,20 +342,25 @@ size_t gemm_workspace_elems(int64_t M, int64_t N, int64_t K) {
     return (size_t)(p.S * M * N);
 }
 
-template <typename T>
-static void launch_any(bool ta, bool tb, const GemmPlan& p, int64_t M, int64_t N, int64_t K, const T* A,
-                       int64_t lda, const T* B, int64_t ldb, T* C, int64_t ldc, int64_t split_stride,
+template <typename T, typename TI, typename TC>
+static void launch_any(bool ta, bool tb, const GemmPlan& p, int64_t M, int64_t N, int64_t K, const TI* A,
+                       int64_t lda, const TI* B, int64_t ldb, TC* C, int64_t ldc, int64_t split_stride,
                        const int32_t* gate, int gate_copy, hipStream_t s) {
     if (ta && tb) return;   // not needed by the method
-    if (ta) launch_dispatch<T, true, false>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, s);
-    else if (tb) launch_dispatch<T, false, true>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, s);
-    else launch_dispatch<T, false, false>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, s);
+    if (ta)
+        launch_dispatch<T, TI, TC, true, false>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, s);
+    else if (tb)
+        launch_dispatch<T, TI, TC, false, true>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, s);
+    else
+        launch_dispatch<T, TI, TC, false, false>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy,
+                                                 s);
 }
 
-template <typename T>
-int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64_t ldb,
-         T* C, int64_t ldc, bool trans_out, T alpha, T beta, T* ws, size_t ws_elems, hipStream_t s,
-         const int32_t* gate, int gate_mode) {
+// T: arithmetic and split-K partial type; TI: A, B; TC: C.
+template <typename T, typename TI, typename TC>
+static int gemm_impl(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const TI* A, int64_t lda, const TI* B,
+                     int64_t ldb, TC* C, int64_t ldc, bool trans_out, T alpha, T beta, T* ws, size_t ws_elems,
+                     hipStream_t s, const int32_t* gate, int gate_mode) {
     if (ta && tb) return RQLP_E_UNSUPPORTED;
     if (M <= 0 || N <= 0) return 0;
     GemmPlan p = plan_gemm(M, N, K);
@@ -361,20 +370,35 @@ int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A, int64_t 
     if (gate_mode == 2 && (!direct || ta || K != N)) return RQLP_E_UNSUPPORTED;
     const int gate_copy = gate_mode == 2 ? 1 : 0;
     if (direct) {
-        launch_any<T>(ta, tb, p, M, N, K, A, lda, B, ldb, C, ldc, 0, gate, gate_copy, s);
+        launch_any<T, TI, TC>(ta, tb, p, M, N, K, A, lda, B, ldb, C, ldc, 0, gate, gate_copy, s);
         return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
     }
     if ((size_t)(p.S * M * N) > ws_elems || ws == nullptr) return RQLP_E_WORKSPACE;
-    launch_any<T>(ta, tb, p, M, N, K, A, lda, B, ldb, ws, M, M * N, gate, 0, s);
+    launch_any<T, TI, T>(ta, tb, p, M, N, K, A, lda, B, ldb, ws, M, M * N, gate, 0, s);
     if (trans_out) {
         dim3 grid((unsigned)ceil_div(M, 32), (unsigned)ceil_div(N, 32));
-        hipLaunchKernelGGL((splitk_reduce_t_kernel<T>), grid, dim3(256), 0, s, M, N, ws, M, M * N, (int)p.S,
+        hipLaunchKernelGGL((splitk_reduce_t_kernel<T, TC>), grid, dim3(256), 0, s, M, N, ws, M, M * N, (int)p.S,
                            alpha, beta, C, ldc, gate);
     } else {
-        hipLaunchKernelGGL((splitk_reduce_kernel<T>), dim3((unsigned)ceil_div(M * N, 256)), dim3(256), 0, s, M, N,
-                           ws, M, M * N, (int)p.S, alpha, beta, C, ldc, gate);
+        hipLaunchKernelGGL((splitk_reduce_kernel<T, TC>), dim3((unsigned)ceil_div(M * N, 256)), dim3(256), 0, s, M,
+                           N, ws, M, M * N, (int)p.S, alpha, beta, C, ldc, gate);
     }
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
+}
+
+template <typename T>
+int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64_t ldb,
+         T* C, int64_t ldc, bool trans_out, T alpha, T beta, T* ws, size_t ws_elems, hipStream_t s,
+         const int32_t* gate, int gate_mode) {
+    return gemm_impl<T, T, T>(ta, tb, M, N, K, A, lda, B, ldb, C, ldc, trans_out, alpha, beta, ws, ws_elems, s, gate,
+                              gate_mode);
+}
+
+int gemm_f32_acc64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
+                   int64_t ldb, float* C, int64_t ldc, bool trans_out, double alpha, double beta, double* ws,
+                   size_t ws_elems, hipStream_t s, const int32_t* gate, int gate_mode) {
+    return gemm_impl<double, float, float>(ta, tb, M, N, K, A, lda, B, ldb, C, ldc, trans_out, alpha, beta, ws,
+                                           ws_elems, s, gate, gate_mode);
 }
 
 template int gemm<double>(bool, bool, int64_t, int64_t, int64_t, const double*, int64_t, const double*, int64_t,

@@ -19,6 +19,11 @@ template <typename T>
 int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64_t ldb,
          T* C, int64_t ldc, bool trans_out, T alpha, T beta, T* ws, size_t ws_elems, hipStream_t s,
          const int32_t* gate = nullptr, int gate_mode = 0);
+// The same product with FP32 operands and result but FP64 MFMA arithmetic
+// (exact products, FP64 sums; split-K partials in ws are FP64).
+int gemm_f32_acc64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
+                   int64_t ldb, float* C, int64_t ldc, bool trans_out, double alpha, double beta, double* ws,
+                   size_t ws_elems, hipStream_t s, const int32_t* gate = nullptr, int gate_mode = 0);
 
 // --- gemm_lp.hip ------------------------------------------------------------
 // C(i, j) = 2^(gexp + rexp[i]) sum_k P(k + i ldp) Q(k + j ldq) with 16-bit

@@ -112,3 +112,31 @@ def test_mixed_workspace_holds_the_16bit_copies(lib):
 
 def test_unsupported_combinations_are_reported(lib):
     assert _factor_status(b=4) == -1002              # block RQLP
+
+
+def _backward_status(**kw):
+    a = dict(A=1, lda=100, m=100, n=50, k=5, p=3, q=0, d=0, b=0, precision=0, seed=0, Omega=None, ldo=50,
+             piv0=1, piv1=1, dT=1, lddt=8, dQ=None, lddq=100, dP=None, lddp=50, saved=None, dA=1, ldda=100,
+             info=None, work=1, work_bytes=0, stream=None)
+    a.update(kw)
+    return _lib.rqlp_backward(*a.values())
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(A=None), -1), (dict(lda=99), -2), (dict(m=0), -3), (dict(n=101), -4), (dict(k=1), -5), (dict(p=1), -6),
+    (dict(q=-1), -7), (dict(d=-1), -8), (dict(b=-1), -9), (dict(precision=9), -10), (dict(Omega=1, ldo=49), -13),
+    (dict(piv0=None), -14), (dict(piv1=None), -15), (dict(dT=None), -16), (dict(lddt=7), -17),
+    (dict(dQ=1, lddq=99), -19), (dict(dP=1, lddp=49), -21), (dict(dA=None), -23), (dict(ldda=99), -24),
+    (dict(work=None), -26),
+    (dict(d=1), -1002), (dict(b=4), -1002), (dict(precision=2), -1002), (dict(dQ=1), -1002), (dict(saved=1), -1002),
+    (dict(work_bytes=16), -1000),
+])
+def test_backward_rejects_invalid_or_unsupported_arguments(lib, kw, code):
+    assert _backward_status(**kw) == code
+
+
+def test_backward_workspace_query(lib):
+    b = rq._lib.rqlp_backward_workspace_size(16384, 4096, 128, 8, 1, 0, 0, 1)
+    assert b >= 4 * (16384 + 4096) * 4 * 136          # the two (2q + 2) l panels
+    with pytest.raises(rq.RQLPError):
+        rq._lib.rqlp_backward_workspace_size(100, 50, 5, 3, 0, 1, 0, 0)
