@@ -156,12 +156,15 @@ def rqlp(A: np.ndarray, Omega: np.ndarray, k: int, p: int, q: int = 0, d: int = 
 # block RQLP (Alg. 4.1)
 # ---------------------------------------------------------------------------
 def brqlp(A: np.ndarray, Omega: np.ndarray, k: int, p: int, b: int, q: int = 0,
-          deflate: bool = True) -> QLPResult:
+          deflate: bool = True, piv0: Optional[Sequence[int]] = None,
+          piv1: Optional[Sequence[int]] = None) -> QLPResult:
     """Block randomized QLP.  Blocks of b columns of Omega (the last one ragged
     when b does not divide l).  Per block j: Y_j = A Omega_j, V_j = qr(Y_j)
     (+ q power iterations on the original A), V_j re-orthogonalised against
     V_1..V_{j-1} (twice), B_j = V_j^T A^(j-1), A^(j) = A^(j-1) - V_j B_j,
-    pivoted QLP of B_j, Q_j = V_j QB_j, P_j = PB_j; T = blkdiag(L_j)."""
+    pivoted QLP of B_j, Q_j = V_j QB_j, P_j = PB_j; T = blkdiag(L_j).
+    piv0 / piv1 (optional, per block and concatenated as returned) freeze the
+    pivots of the per-block factorisations."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     l = k + p
@@ -179,7 +182,9 @@ def brqlp(A: np.ndarray, Omega: np.ndarray, k: int, p: int, b: int, q: int = 0,
         Bj = Vj.T @ Aj
         if deflate:
             Aj = Aj - Vj @ Bj
-        QB, Lj, PB, p0, p1, _, _ = qlp_reduced(Bj, 0)
+        f0 = None if piv0 is None else np.asarray(piv0)[s0:s1]
+        f1 = None if piv1 is None else np.asarray(piv1)[s0:s1]
+        QB, Lj, PB, p0, p1, _, _ = qlp_reduced(Bj, 0, f0, f1)
         Vs.append(Vj)
         Qs.append(Vj @ QB)
         Ps.append(PB)

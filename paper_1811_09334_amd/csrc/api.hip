@@ -166,7 +166,8 @@ struct SmallBufs {
 };
 
 // extra FP64 product shapes (M, N, K) of the caller that share gws
-void carve_small(Arena& ar, int64_t n, int64_t l, std::initializer_list<std::array<int64_t, 3>> extra, SmallBufs* f) {
+void carve_small(Arena& ar, int64_t n, int64_t l, int64_t cp_rows, std::initializer_list<std::array<int64_t, 3>> extra,
+                 SmallBufs* f) {
     f->B = ar.take<double>(l * n);
     f->Z = ar.take<double>(n * l);
     f->Z2 = ar.take<double>(n * l);
@@ -175,7 +176,7 @@ void carve_small(Arena& ar, int64_t n, int64_t l, std::initializer_list<std::arr
     f->gws_elems = e > e2 ? e : e2;
     f->gws = ar.take<double>(f->gws_elems);
     carve_ortho(ar, l, &f->o);
-    cpqr_carve(ar, l, n, &f->cs);
+    cpqr_carve(ar, cp_rows, n, &f->cs);
     f->Vh0 = ar.take<double>(l * l);
     f->beta0 = ar.take<double>(l);
     f->piv0 = ar.take<int64_t>(l);
@@ -337,11 +338,89 @@ void carve_range_lp(Arena& ar, int64_t m, int64_t n, int64_t l, int precision, b
     r->shifted = ar.take<int32_t>(1);
 }
 
+// Scratch of the block reorthogonalisation.
+struct BcgsScratch {
+    void* C;        // l x bs coefficients
+    void* p0;       // rows x bs panels
+    void* p1;
+    void* ws;       // split-K partials (T)
+    size_t ws_elems;
+};
+
+// Block classical Gram-Schmidt with reorthogonalisation (the twice-applied
+// step 5 of Algorithm 4.1) over the rows x l panel V whose bs-column blocks
+// are already orthonormal: for every block j > 0, twice,
+// V_j <- V_j - V_{<j} (V_{<j}^T V_j), V_j <- qr(V_j).
+template <typename T, typename CtxT>
+int bcgs2(CtxT& cx, int64_t rows, int64_t l, int64_t bs, T* V, int64_t ld, BcgsScratch& sc, hipStream_t s) {
+    T* C = (T*)sc.C;
+    T* p0 = (T*)sc.p0;
+    T* p1 = (T*)sc.p1;
+    T* ws = (T*)sc.ws;
+    for (int64_t s0 = bs; s0 < l; s0 += bs) {
+        const int64_t bj = (l - s0) < bs ? (l - s0) : bs;
+        T* Vj = V + s0 * ld;
+        for (int pass = 0; pass < 2; ++pass) {
+            RQLP_TRY(gemm<T>(true, false, s0, bj, rows, V, ld, Vj, ld, C, s0, false, T(1), T(0), ws, sc.ws_elems, s));
+            RQLP_TRY(gemm<T>(false, false, rows, bj, s0, V, ld, C, s0, Vj, ld, false, T(-1), T(1), ws, sc.ws_elems, s));
+            T* o = nullptr;
+            if constexpr (sizeof(T) == sizeof(double)) {
+                RQLP_TRY(copy_matrix(rows, bj, (const double*)Vj, ld, (double*)p0, rows, s));
+                RQLP_TRY(cholqr2(cx, rows, bj, (double*)p0, (double*)p1, rows, nullptr, (double**)&o, true));
+                RQLP_TRY(copy_matrix(rows, bj, (const double*)o, rows, (double*)Vj, ld, s));
+            } else {
+                RQLP_TRY((cast_matrix<float, float>(rows, bj, (const float*)Vj, ld, (float*)p0, rows, s)));
+                RQLP_TRY(cholqr_f32(cx, rows, bj, (float*)p0, (float*)p1, rows, (float**)&o, true));
+                RQLP_TRY((cast_matrix<float, float>(rows, bj, (const float*)o, rows, (float*)Vj, ld, s)));
+            }
+        }
+    }
+    return 0;
+}
+
+// Orthonormalisation of a rows x l panel: as a whole (bs == 0, CholeskyQR),
+// or by blocks of bs columns (the last one ragged): a QR of every block,
+// then block Gram-Schmidt twice against the earlier blocks.  Both forms are
+// triangular (column j of the result lies in the span of columns 0..j of
+// the input), so the leading blocks of the range finder's basis span the
+// images of the leading blocks of Omega: the blocks of Algorithm 4.1.  The
+// result is in *out (buf0 or buf1).
+int ortho_f64(Ctx& cx, int64_t rows, int64_t l, int64_t bs, double* buf0, double* buf1, int64_t ld, double** out,
+              bool final, BcgsScratch& bc) {
+    if (bs <= 0 || bs >= l) return cholqr2(cx, rows, l, buf0, buf1, ld, nullptr, out, final);
+    double* res = buf0;
+    for (int64_t s0 = 0; s0 < l; s0 += bs) {
+        const int64_t bj = (l - s0) < bs ? (l - s0) : bs;
+        double* o = nullptr;
+        RQLP_TRY(cholqr2(cx, rows, bj, buf0 + s0 * ld, buf1 + s0 * ld, ld, nullptr, &o, final));
+        res = (o == buf0 + s0 * ld) ? buf0 : buf1;
+    }
+    RQLP_TRY((bcgs2<double, Ctx>(cx, rows, l, bs, res, ld, bc, cx.s)));
+    *out = res;
+    return 0;
+}
+
+int ortho_f32(Ctx32& cx, int64_t rows, int64_t l, int64_t bs, float* buf0, float* buf1, int64_t ld, float** out,
+              bool final, BcgsScratch& bc) {
+    if (bs <= 0 || bs >= l) return cholqr_f32(cx, rows, l, buf0, buf1, ld, out, final);
+    float* res = buf0;
+    for (int64_t s0 = 0; s0 < l; s0 += bs) {
+        const int64_t bj = (l - s0) < bs ? (l - s0) : bs;
+        float* o = nullptr;
+        RQLP_TRY(cholqr_f32(cx, rows, bj, buf0 + s0 * ld, buf1 + s0 * ld, ld, &o, final));
+        res = (o == buf0 + s0 * ld) ? buf0 : buf1;
+    }
+    RQLP_TRY((bcgs2<float, Ctx32>(cx, rows, l, bs, res, ld, bc, cx.s)));
+    *out = res;
+    return 0;
+}
+
 // FP32 range finder and projection (RQLP_F32): every pass over A is an FP32
 // MFMA product, the panels are orthonormalised by FP32 CholeskyQR, and
 // B = V^T A is widened to FP64 for the small stage.  Returns V (m x l).
 int range_and_project_f32(Ctx32& c32, RangeBufsLP& r, SmallBufs& f, const float* A, int64_t lda, int64_t m,
-                          int64_t n, int64_t l, int q, uint64_t seed, const float* Om, int64_t ldom, float** Vout) {
+                          int64_t n, int64_t l, int q, uint64_t seed, const float* Om, int64_t ldom, float** Vout,
+                          int64_t bs, BcgsScratch& bc) {
     hipStream_t s = c32.s;
     if (!Om) {
         RQLP_TRY(generate_omega(n, l, seed, RQLP_F32, r.Om, n, s));
@@ -350,15 +429,15 @@ int range_and_project_f32(Ctx32& c32, RangeBufsLP& r, SmallBufs& f, const float*
     }
     RQLP_TRY(gemm<float>(false, false, m, l, n, A, lda, Om, ldom, r.Y, m, false, 1.0f, 0.0f, r.fws, r.fws_elems, s));
     float* V = nullptr;
-    RQLP_TRY(cholqr_f32(c32, m, l, r.Y, r.Y2, m, &V, q == 0));
+    RQLP_TRY(ortho_f32(c32, m, l, bs, r.Y, r.Y2, m, &V, q == 0, bc));
     for (int it = 0; it < q; ++it) {
         RQLP_TRY(gemm<float>(true, false, n, l, m, A, lda, V, m, r.Z, n, false, 1.0f, 0.0f, r.fws, r.fws_elems, s));
         float* W = nullptr;
-        RQLP_TRY(cholqr_f32(c32, n, l, r.Z, r.Z2, n, &W, false));
+        RQLP_TRY(ortho_f32(c32, n, l, bs, r.Z, r.Z2, n, &W, false, bc));
         float* ydst = (V == r.Y) ? r.Y2 : r.Y;
         RQLP_TRY(gemm<float>(false, false, m, l, n, A, lda, W, n, ydst, m, false, 1.0f, 0.0f, r.fws, r.fws_elems, s));
         float* other = (ydst == r.Y) ? r.Y2 : r.Y;
-        RQLP_TRY(cholqr_f32(c32, m, l, ydst, other, m, &V, it == q - 1));
+        RQLP_TRY(ortho_f32(c32, m, l, bs, ydst, other, m, &V, it == q - 1, bc));
     }
     RQLP_TRY(gemm<float>(true, false, n, l, m, A, lda, V, m, r.B32, l, true, 1.0f, 0.0f, r.fws, r.fws_elems, s));
     RQLP_TRY((cast_matrix<float, double>(l, n, r.B32, l, f.B, l, s)));
@@ -390,15 +469,31 @@ struct FactorLayout {
     RangeBufs64 r64;
     RangeBufsLP rlp;
     SmallBufs sm;
+    BcgsScratch bc;     // block RQLP only
+    double* Bj;         // block RQLP: one block row of B (bs x n)
 };
 
-void carve_factor(Arena& ar, int64_t m, int64_t n, int64_t l, int precision, bool need_omega, FactorLayout* L) {
+// bs: block size of block RQLP (0: unblocked).
+void carve_factor(Arena& ar, int64_t m, int64_t n, int64_t l, int precision, bool need_omega, int64_t bs,
+                  FactorLayout* L) {
+    const int64_t cp_rows = bs > 0 ? bs : l;     // rows of the reduced matrices the CPQR sees
     if (precision == RQLP_F64) {
         carve_range64(ar, m, n, l, need_omega, &L->r64);
-        carve_small(ar, n, l, {{m, l, n}, {n, l, m}, {l, l, m}, {m, l, l}, {l, n, m}}, &L->sm);
+        carve_small(ar, n, l, cp_rows, {{m, l, n}, {n, l, m}, {l, l, m}, {m, l, l}, {l, n, m}}, &L->sm);
     } else {
         carve_range_lp(ar, m, n, l, precision, need_omega, &L->rlp);
-        carve_small(ar, n, l, {}, &L->sm);
+        carve_small(ar, n, l, cp_rows, {}, &L->sm);
+    }
+    L->bc = BcgsScratch{nullptr, nullptr, nullptr, nullptr, 0};
+    L->Bj = nullptr;
+    if (bs > 0) {
+        const size_t es = precision == RQLP_F64 ? sizeof(double) : sizeof(float);
+        L->bc.C = ar.take<char>(l * bs * es);
+        L->bc.p0 = ar.take<char>(m * bs * es);
+        L->bc.p1 = ar.take<char>(m * bs * es);
+        L->bc.ws_elems = max_ws(gemm_workspace_elems, {{l, bs, m}, {m, bs, l}, {l, bs, n}, {n, bs, l}});
+        L->bc.ws = ar.take<char>(L->bc.ws_elems * es);
+        L->Bj = ar.take<double>(bs * n);
     }
 }
 
@@ -413,7 +508,8 @@ Arena arena_for(void* work, size_t bytes) {
 // FP64 range finder (Algorithm 2.1 steps 1-3 with q subspace iterations) and
 // projection B = V^T A (step 4).  Returns V (m x l) in *Vout.
 int range_and_project_f64(Ctx& cx, RangeBufs64& r, SmallBufs& f, const double* A, int64_t lda, int64_t m, int64_t n,
-                          int64_t l, int q, uint64_t seed, const double* Om, int64_t ldom, double** Vout) {
+                          int64_t l, int q, uint64_t seed, const double* Om, int64_t ldom, double** Vout, int64_t bs,
+                          BcgsScratch& bc) {
     hipStream_t s = cx.s;
     if (!Om) {
         RQLP_TRY(generate_omega(n, l, seed, RQLP_F64, r.Om, n, s));
@@ -422,16 +518,16 @@ int range_and_project_f64(Ctx& cx, RangeBufs64& r, SmallBufs& f, const double* A
     }
     RQLP_TRY(gemm<double>(false, false, m, l, n, A, lda, Om, ldom, r.Y, m, false, 1.0, 0.0, f.gws, f.gws_elems, s));
     double* V = nullptr;
-    RQLP_TRY(cholqr2(cx, m, l, r.Y, r.Y2, m, nullptr, &V, q == 0));
+    RQLP_TRY(ortho_f64(cx, m, l, bs, r.Y, r.Y2, m, &V, q == 0, bc));
     for (int it = 0; it < q; ++it) {
         // Z = A^T V into the small stage's n x l buffers (free until the CPQR)
         RQLP_TRY(gemm<double>(true, false, n, l, m, A, lda, V, m, f.Z, n, false, 1.0, 0.0, f.gws, f.gws_elems, s));
         double* W = nullptr;
-        RQLP_TRY(cholqr2(cx, n, l, f.Z, f.Z2, n, nullptr, &W, false));
+        RQLP_TRY(ortho_f64(cx, n, l, bs, f.Z, f.Z2, n, &W, false, bc));
         double* ydst = (V == r.Y) ? r.Y2 : r.Y;
         RQLP_TRY(gemm<double>(false, false, m, l, n, A, lda, W, n, ydst, m, false, 1.0, 0.0, f.gws, f.gws_elems, s));
         double* other = (ydst == r.Y) ? r.Y2 : r.Y;
-        RQLP_TRY(cholqr2(cx, m, l, ydst, other, m, nullptr, &V, it == q - 1));
+        RQLP_TRY(ortho_f64(cx, m, l, bs, ydst, other, m, &V, it == q - 1, bc));
     }
     // B = V^T A, computed as (A^T V)^T and stored l x n
     RQLP_TRY(gemm<double>(true, false, n, l, m, A, lda, V, m, f.B, l, true, 1.0, 0.0, f.gws, f.gws_elems, s));
@@ -445,7 +541,7 @@ int range_and_project_f64(Ctx& cx, RangeBufs64& r, SmallBufs& f, const double* A
 // Returns V (m x l, FP32) in *Vout.
 int range_and_project_lp(Ctx32& c32, RangeBufsLP& r, SmallBufs& f, int kind, const float* A, int64_t lda,
                          int64_t m, int64_t n, int64_t l, int q, uint64_t seed, const float* Om, int64_t ldom,
-                         float** Vout) {
+                         float** Vout, int64_t bs, BcgsScratch& bc) {
     hipStream_t s = c32.s;
     const bool fp16 = kind == RQLP_MIXED_FP16;
     const int* cexp = fp16 ? r.colexp : nullptr;
@@ -462,21 +558,21 @@ int range_and_project_lp(Ctx32& c32, RangeBufsLP& r, SmallBufs& f, int kind, con
     RQLP_TRY(gemm_lp<float>(kind, m, l, n, r.Ar, r.Arlo, n, r.X16, r.X16lo, n, r.Y, m, false, nullptr, gexp, r.lpws,
                             r.lpws_elems, s));
     float* V = nullptr;
-    RQLP_TRY(cholqr_f32(c32, m, l, r.Y, r.Y2, m, &V, q == 0));
+    RQLP_TRY(ortho_f32(c32, m, l, bs, r.Y, r.Y2, m, &V, q == 0, bc));
     for (int it = 0; it < q; ++it) {
         // Z = A^T V  (FP16: D (A D^-1)^T V)
         RQLP_TRY(cast_to_lp(kind, m, l, V, m, r.X16, r.X16lo, m, false, nullptr, nullptr, nullptr, s));
         RQLP_TRY(gemm_lp<float>(kind, n, l, m, r.Ac, r.Aclo, m, r.X16, r.X16lo, m, r.Z, n, false, cexp, nullptr,
                                 r.lpws, r.lpws_elems, s));
         float* W = nullptr;
-        RQLP_TRY(cholqr_f32(c32, n, l, r.Z, r.Z2, n, &W, false));
+        RQLP_TRY(ortho_f32(c32, n, l, bs, r.Z, r.Z2, n, &W, false, bc));
         // Y = A W
         RQLP_TRY(cast_to_lp(kind, n, l, W, n, r.X16, r.X16lo, n, false, cexp, nullptr, gexp, s));
         float* ydst = (V == r.Y) ? r.Y2 : r.Y;
         RQLP_TRY(gemm_lp<float>(kind, m, l, n, r.Ar, r.Arlo, n, r.X16, r.X16lo, n, ydst, m, false, nullptr, gexp,
                                 r.lpws, r.lpws_elems, s));
         float* other = (ydst == r.Y) ? r.Y2 : r.Y;
-        RQLP_TRY(cholqr_f32(c32, m, l, ydst, other, m, &V, it == q - 1));
+        RQLP_TRY(ortho_f32(c32, m, l, bs, ydst, other, m, &V, it == q - 1, bc));
     }
     // B = V^T A = (A^T V)^T, FP32 accumulation, stored l x n in FP64
     RQLP_TRY(cast_to_lp(kind, m, l, V, m, r.X16, r.X16lo, m, false, nullptr, nullptr, nullptr, s));
@@ -508,7 +604,7 @@ int rqlp_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p, int q, int d
     if (!bytes) return -9;
     Arena ar(nullptr, 0);
     FactorLayout L;
-    carve_factor(ar, m, n, k + p, precision, true, &L);
+    carve_factor(ar, m, n, k + p, precision, true, (b > 0 && b < k + p) ? b : 0, &L);
     *bytes = ar.used + 256;
     return 0;
 }
@@ -537,53 +633,80 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
     if (!P) return -18;
     if (ldp < n) return -19;
     if (!work) return -25;
-    if (b != 0) return RQLP_E_UNSUPPORTED;
+    // block RQLP with b >= l is a single block: plain RQLP
+    const int64_t bs = (b > 0 && b < l) ? b : 0;
 
     hipStream_t s = (hipStream_t)stream;
     Arena ar = arena_for(work, work_bytes);
     FactorLayout Lay;
-    carve_factor(ar, m, n, l, precision, Omega == nullptr, &Lay);
+    carve_factor(ar, m, n, l, precision, Omega == nullptr, bs, &Lay);
     if (!ar.ok()) return RQLP_E_WORKSPACE;
     SmallBufs& f = Lay.sm;
     {
+        const int64_t rows = bs > 0 ? bs : l;
         CpqrPlan pl;
-        RQLP_TRY(cpqr_plan(l, n, &pl));
-        RQLP_TRY(cpqr_plan(l, l, &pl));
+        RQLP_TRY(cpqr_plan(rows, n, &pl));
+        RQLP_TRY(cpqr_plan(rows, rows, &pl));
     }
     int32_t* inf = info ? info : f.info;
     RQLP_TRY(fill_zero_bytes(inf, sizeof(int32_t), s));
     Ctx cx{s, inf, f.gws, f.gws_elems, f.o, f.o.shifted};
     char tri = 'L';
     double* QB = nullptr;
-
-    if (precision == RQLP_F64) {
-        double* V = nullptr;
-        RQLP_TRY(range_and_project_f64(cx, Lay.r64, f, (const double*)A, lda, m, n, l, q, seed,
-                                       (const double*)Omega, ldo, &V));
-        RQLP_TRY(qlp_of_B(cx, f, l, n, d, (double*)P, ldp, T, ldt, &tri, &QB));
+    const bool f64 = precision == RQLP_F64;
+    RangeBufsLP& r = Lay.rlp;
+    Ctx32 c32{s, inf, r.fws, r.fws_elems, r.G, r.Li, f.o.L1, f.o.Li, r.shifted, f.o.sync};
+    double* V64 = nullptr;
+    float* V32 = nullptr;
+    if (f64)
+        RQLP_TRY(range_and_project_f64(cx, Lay.r64, f, (const double*)A, lda, m, n, l, q, seed, (const double*)Omega,
+                                       ldo, &V64, bs, Lay.bc));
+    else if (precision == RQLP_F32)
+        RQLP_TRY(range_and_project_f32(c32, r, f, (const float*)A, lda, m, n, l, q, seed, (const float*)Omega, ldo,
+                                       &V32, bs, Lay.bc));
+    else
+        RQLP_TRY(range_and_project_lp(c32, r, f, precision, (const float*)A, lda, m, n, l, q, seed,
+                                      (const float*)Omega, ldo, &V32, bs, Lay.bc));
+    double* Pd = f64 ? (double*)P : r.Pd;
+    const int64_t ldpd = f64 ? ldp : n;
+    if (bs == 0) {
+        RQLP_TRY(qlp_of_B(cx, f, l, n, d, Pd, ldpd, T, ldt, &tri, &QB));
         // assembly: Q = V Q_B
-        RQLP_TRY(gemm<double>(false, false, m, l, l, V, m, QB, l, (double*)Q, ldq, false, 1.0, 0.0, f.gws,
-                              f.gws_elems, s));
+        if (f64) {
+            RQLP_TRY(gemm<double>(false, false, m, l, l, V64, m, QB, l, (double*)Q, ldq, false, 1.0, 0.0, f.gws,
+                                  f.gws_elems, s));
+        } else {
+            RQLP_TRY((cast_matrix<double, float>(l, l, QB, l, r.QB, l, s)));
+            RQLP_TRY(gemm<float>(false, false, m, l, l, V32, m, r.QB, l, (float*)Q, ldq, false, 1.0f, 0.0f, r.fws,
+                                 r.fws_elems, s));
+        }
+        if (piv0) RQLP_TRY(copy_i64(l, f.piv0, piv0, s));
+        if (piv1) RQLP_TRY(copy_i64(l, d == 0 ? f.piv1 : nullptr, piv1, s));
     } else {
-        RangeBufsLP& r = Lay.rlp;
-        Ctx32 c32{s, inf, r.fws, r.fws_elems, r.G, r.Li, f.o.L1, f.o.Li, r.shifted, f.o.sync};
-        float* V = nullptr;
-        if (precision == RQLP_F32)
-            RQLP_TRY(range_and_project_f32(c32, r, f, (const float*)A, lda, m, n, l, q, seed, (const float*)Omega,
-                                           ldo, &V));
-        else
-            RQLP_TRY(range_and_project_lp(c32, r, f, precision, (const float*)A, lda, m, n, l, q, seed,
-                                          (const float*)Omega, ldo, &V));
-        RQLP_TRY(qlp_of_B(cx, f, l, n, d, r.Pd, n, T, ldt, &tri, &QB));
-        // assembly in FP32: P = P_B, Q = V Q_B
-        RQLP_TRY((cast_matrix<double, float>(n, l, r.Pd, n, (float*)P, ldp, s)));
-        RQLP_TRY((cast_matrix<double, float>(l, l, QB, l, r.QB, l, s)));
-        RQLP_TRY(gemm<float>(false, false, m, l, l, V, m, r.QB, l, (float*)Q, ldq, false, 1.0f, 0.0f, r.fws,
-                             r.fws_elems, s));
+        // Algorithm 4.1 steps 6-7, block by block: B_j = V_j^T A is block row j
+        // of B; pivoted QLP of B_j; Q_j = V_j Q_B(j), P_j = P_B(j); T = blkdiag(L_j)
+        RQLP_TRY(set_identity(l, T, ldt, s));
+        for (int64_t s0 = 0; s0 < l; s0 += bs) {
+            const int64_t bj = (l - s0) < bs ? (l - s0) : bs;
+            RQLP_TRY(copy_matrix(bj, n, f.B + s0, l, Lay.Bj, bj, s));
+            SmallBufs fj = f;
+            fj.B = Lay.Bj;
+            char tj = 'L';
+            RQLP_TRY(qlp_of_B(cx, fj, bj, n, 0, Pd + s0 * ldpd, ldpd, T + s0 + s0 * ldt, ldt, &tj, &QB));
+            if (f64) {
+                RQLP_TRY(gemm<double>(false, false, m, bj, bj, V64 + s0 * m, m, QB, bj, (double*)Q + s0 * ldq, ldq,
+                                      false, 1.0, 0.0, f.gws, f.gws_elems, s));
+            } else {
+                RQLP_TRY((cast_matrix<double, float>(bj, bj, QB, bj, r.QB, bj, s)));
+                RQLP_TRY(gemm<float>(false, false, m, bj, bj, V32 + s0 * m, m, r.QB, bj, (float*)Q + s0 * ldq, ldq,
+                                     false, 1.0f, 0.0f, r.fws, r.fws_elems, s));
+            }
+            if (piv0) RQLP_TRY(copy_i64(bj, f.piv0, piv0 + s0, s));
+            if (piv1) RQLP_TRY(copy_i64(bj, f.piv1, piv1 + s0, s));
+        }
     }
+    if (!f64) RQLP_TRY((cast_matrix<double, float>(n, l, r.Pd, n, (float*)P, ldp, s)));
     RQLP_TRY(finish_lvals(l, T, ldt, lvals, inf, s));
-    if (piv0) RQLP_TRY(copy_i64(l, f.piv0, piv0, s));
-    if (piv1) RQLP_TRY(copy_i64(l, d == 0 ? f.piv1 : nullptr, piv1, s));
     if (uplo) *uplo = tri;
     return 0;
 }

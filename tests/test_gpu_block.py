@@ -1,0 +1,78 @@
+"""GPU parity of block RQLP (Algorithm 4.1; rqlp_factor with b > 0) against
+the FP64 CPU oracle's brqlp on the same A and Omega.
+
+FP64: L-values within 1e-10, per-block pivots identical where separated by
+more than 1e-8 (else the oracle is re-run on the GPU's pivots), Q
+orthonormal, every b-column block of P orthonormal, Q T P^T equal to the
+oracle's (= V V^T A).  Mixed precision (IEEE half with per-column scaling,
+the block workload's arithmetic): frozen-pivot L-values within 1e-3."""
+import numpy as np
+import pytest
+
+from oracle.rqlp import brqlp
+from paper_1811_09334_amd import inputs
+
+from _helpers import first_difference, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_blocks(P, l, b, tol):
+    for s0 in range(0, l, b):
+        Pj = P[:, s0:s0 + b]
+        assert np.abs(Pj.T @ Pj - np.eye(Pj.shape[1])).max() < tol
+
+
+@pytest.mark.parametrize("m,n,k,p,b,q", [
+    (600, 300, 40, 8, 16, 0),      # 3 blocks of 16
+    (600, 300, 40, 10, 16, 1),     # ragged last block (50 = 3 x 16 + 2)
+    (1000, 500, 120, 8, 64, 1),    # 2 blocks of 64
+    (777, 333, 30, 5, 64, 0),      # b >= l: one block (plain RQLP)
+])
+def test_block_rqlp_f64_matches_oracle(gpu, m, n, k, p, b, q):
+    l = k + p
+    A = inputs.svd_matrix(m, n, inputs.spectrum_exp(n, n / 8.0), m + n + b)
+    Om = inputs.gaussian(n, l, m + 7)
+    f = gpu.factor(to_dev(A), k, p, q=q, b=b, Omega=to_dev(Om))
+    Q, T, P = to_np(f.Q), to_np(f.T), to_np(f.P)
+    piv0, piv1, lv = to_np(f.piv0), to_np(f.piv1), to_np(f.lvals)
+    assert int(to_np(f.info)[0]) == 0
+    ref = brqlp(A, Om, k, p, b, q=q, deflate=False)
+    if first_difference(piv0, ref.piv0) >= 0 or first_difference(piv1, ref.piv1) >= 0:
+        ref = brqlp(A, Om, k, p, b, q=q, deflate=False, piv0=piv0, piv1=piv1)
+    rel = np.abs(lv[:k] - ref.lvals[:k]) / ref.lvals[:k]
+    assert rel.max() < 1e-10, rel.max()
+    assert np.allclose(T, ref.T, atol=1e-10 * np.abs(ref.T).max())
+    assert np.abs(Q.T @ Q - np.eye(l)).max() < 1e-12
+    _check_blocks(P, l, b, 1e-12)
+    nA = np.linalg.norm(A)
+    assert np.linalg.norm(Q @ T @ P.T - ref.Q @ ref.T @ ref.P.T) / nA < 1e-10
+    assert f.uplo == "L"
+
+
+@pytest.mark.parametrize("kind", ["fp16", "bf16x3", "f32"])
+def test_block_rqlp_mixed_scaled_workload(gpu, kind):
+    """The block workload's recipe at 4096 x 1024 (k = 224, p = 32, b = 64,
+    q = 1) with s_j = exp(-j/tau), tau chosen so that s_l / s_1 = exp(-3.5)
+    as for l = 1056 and tau = 300 at full size; frozen-pivot gate 1e-3."""
+    import torch
+    m, n, k, p, b, q = 4096, 1024, 224, 32, 64, 1
+    l = k + p
+    A = inputs.svd_matrix(m, n, inputs.spectrum_exp(n, l / 3.5), 1003).astype(np.float32)
+    Om = inputs.gaussian(n, l, 2003)
+    Om = inputs.round_to_fp16(Om) if kind == "fp16" else inputs.round_to_bf16(Om) if kind == "bf16x3" else \
+        Om.astype(np.float32).astype(np.float64)
+    f = gpu.factor(to_dev(A, torch.float32), k, p, q=q, b=b, precision=kind, Omega=to_dev(Om, torch.float32))
+    piv0, piv1, lv = to_np(f.piv0), to_np(f.piv1), to_np(f.lvals)
+    assert int(to_np(f.info)[0]) == 0
+    A64 = A.astype(np.float64)
+    frozen = brqlp(A64, Om, k, p, b, q=q, deflate=False, piv0=piv0, piv1=piv1)
+    rel = np.abs(lv[:k] - frozen.lvals[:k]) / frozen.lvals[:k]
+    free = brqlp(A64, Om, k, p, b, q=q, deflate=False)
+    rel_free = np.abs(lv[:k] - free.lvals[:k]) / free.lvals[:k]
+    print(f"[block {kind} {A.shape} b={b}] frozen {rel.max():.2e} free {rel_free.max():.2e} "
+          f"divergence {first_difference(piv0, free.piv0)}")
+    assert rel.max() < (1e-6 if kind == "f32" else 1e-3)
+    Q = to_np(f.Q).astype(np.float64)
+    assert np.abs(Q.T @ Q - np.eye(l)).max() < 1e-4
+    _check_blocks(to_np(f.P).astype(np.float64), l, b, 1e-5)

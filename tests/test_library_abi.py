@@ -111,7 +111,7 @@ def test_mixed_workspace_holds_the_16bit_copies(lib):
 
 
 def test_unsupported_combinations_are_reported(lib):
-    assert _factor_status(b=4) == -1002              # block RQLP
+    assert _factor_status(b=4) == -1000              # block RQLP is supported: only the workspace is short
 
 
 def _backward_status(**kw):
