@@ -55,6 +55,8 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg (profiling runs)")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run on the mixed workload's matrix")
+    ap.add_argument("--no-others", action="store_true",
+                    help="skip the short timings of the other workloads (FP64 ERQLP, block RQLP, backward)")
     ap.add_argument("--gaussian-input", action="store_true",
                     help="A = N(0,1) instead of the prescribed spectrum (hardware-counter runs only: "
                          "skips the QR-based generation)")
@@ -157,6 +159,41 @@ def roofline_lp(rq, A, V, w, dev):
             "mfma_tflops": round(flops / t / 1e12, 2), "mfma_frac": round(flops / t / 1e12 / PEAK["bf16"], 4)}
 
 
+def other_workloads(rq, inputs, dev):
+    """Short timings (3 steps after 1 warm-up) of the other workloads of the
+    hot path, each on its own synthetic matrix: FP64 ERQLP (20000 x 10000),
+    block RQLP in FP16 (65536 x 8192, b = 64) and the FP32 forward + backward
+    of the differentiable workload (16384 x 4096)."""
+    import torch
+    out = {}
+    for name in ("erqlp_f64_20000x10000", "brqlp_fp16_65536x8192", "drqlp_f32_16384x4096"):
+        w = inputs.WORKLOADS[name]
+        A = inputs.make_matrix_torch(w, dev)
+        work = torch.empty(rq.workspace_size(w.m, w.n, w.k, w.p, w.q, w.d, w.b, w.precision), dtype=torch.uint8,
+                           device=dev)
+        ms, f = timed(lambda: rq.factor(A, w.k, w.p, q=w.q, d=w.d, b=w.b, precision=w.precision, seed=w.seed_omega,
+                                        work=work), 3, 1)
+        F = flop_model(w.m, w.n, w.l, w.q)
+        rec = {"ms_per_step": round(ms, 3), "tflops": round(F / (ms * 1e-3) / 1e12, 3), "precision": w.precision,
+               "m": w.m, "n": w.n, "k": w.k, "p": w.p, "q": w.q, "d": w.d, "b": w.b, "info": int(f.info.item())}
+        if name.startswith("drqlp"):
+            dT = torch.zeros(w.l, w.l, dtype=torch.float64, device=dev)
+            dT.diagonal()[: w.k] = torch.as_tensor(inputs.uniform_weights(w.k, 3000), device=dev)
+            bw = torch.empty(rq._lib.rqlp_backward_workspace_size(w.m, w.n, w.k, w.p, w.q, w.d, w.b,
+                                                                  rq.PRECISIONS[w.precision]),
+                             dtype=torch.uint8, device=dev)
+            msb, _ = timed(lambda: rq.backward(A, w.k, w.p, f.piv0, f.piv1, dT, q=w.q, precision=w.precision,
+                                               seed=w.seed_omega, work=bw), 3, 1)
+            rec["backward_ms"] = round(msb, 3)
+            del bw
+        out[name] = rec
+        print(f"# {name}: {ms:.3f} ms/step" + (f", backward {rec['backward_ms']:.3f} ms" if "backward_ms" in rec
+                                               else ""), file=sys.stderr, flush=True)
+        del A, work, f
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse_args()
     if args.gpus != 1:
@@ -195,7 +232,6 @@ def main():
                        dtype=torch.uint8, device=dev)
     ms, f = timed(lambda: rq.factor(A, w.k, w.p, q=w.q, d=w.d, b=w.b, precision=w.precision, seed=seed,
                                     work=work), args.steps, args.warmup)
-    del work
     info = int(f.info.item())
     F = flop_model(w.m, w.n, l, w.q)
     tflops = F / (ms * 1e-3) / 1e12
@@ -225,6 +261,12 @@ def main():
         V.copy_(f.Q)
         roof = roofline_lp(rq, A, V, w, dev) if mixed else roofline_f64(rq, A, V, w, dev)
         del V
+
+    others = None
+    if not args.no_others and args.workload == DEFAULT_WORKLOAD:
+        del work
+        torch.cuda.empty_cache()
+        others = other_workloads(rq, inputs, dev)
 
     # ---- CPU baseline: the FP64 oracle on the host cores, same A and Omega ----
     cpu = None
@@ -284,6 +326,7 @@ def main():
         "fp64_same_matrix": fp64,
         "speedup_vs_fp64": round(fp64["ms_per_step"] / ms, 3) if fp64 else None,
         **acc,
+        "other_workloads": others,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
