@@ -197,35 +197,57 @@ int rqlp_project(const void* A, int64_t lda, int64_t m, int64_t n, const void* V
                  int64_t c, void* B, int64_t ldb, int precision, void* work, size_t work_bytes,
                  void* stream);
 
-/* Bytes of work rqlp_sketch / rqlp_project / rqlp_project_encoded need for
+/* Bytes of work rqlp_sketch / rqlp_project / rqlp_project_encoded /
+ * rqlp_sketch_encoded need for
  * these shapes (host out). */
 int rqlp_gemm_workspace(int64_t m, int64_t n, int64_t c, int precision, size_t* bytes);
 
 /* 16-bit encoding of the FP32 matrix A (m x n) used by the MFMA products of
  * the mixed precisions (the sketch / projection operands of Algorithm 2.1
  * steps 2 and 4 in reduced precision).  precision is RQLP_MIXED_BF16,
- * RQLP_MIXED_FP16 or RQLP_MIXED_BF16X3:
- *   BF16   : Ahi = bf16(A) (round to nearest even);
- *   BF16X3 : Ahi = bf16(A), Alo = bf16(A - Ahi);
- *   FP16   : Ahi = half(A(:, j) 2^-e_j) with e_j chosen per column so that
- *            max_i |A(i, j)| 2^-e_j lies in [2^14, 2^15) (0 for a zero
- *            column); colexp (n int32) receives e_j and gexp (1 int32)
+ * RQLP_MIXED_FP16 or RQLP_MIXED_BF16X3; each element x of A becomes
+ *   BF16   : hi = bf16(x) (round to nearest even);
+ *   BF16X3 : hi = bf16(x), lo = bf16(x - hi);
+ *   FP16   : hi = half(x 2^-e_j) for x in column j, with e_j chosen per
+ *            column so that max_i |A(i, j)| 2^-e_j lies in [2^14, 2^15) (0 for
+ *            a zero column); colexp (n int32) receives e_j and gexp (1 int32)
  *            max_j e_j.  colexp / gexp are not used by the other types and
  *            may be NULL there.
- * transpose == 0: Ahi / Alo are column-major m x n (ldh >= m); otherwise
- * they hold A^T, n x m (ldh >= n).  Alo must be NULL unless BF16X3.  Elements
- * are the raw 16-bit patterns (uint16_t).  The caller owns all buffers. */
-int rqlp_encode(const float* A, int64_t lda, int64_t m, int64_t n, int precision, int transpose,
-                uint16_t* Ahi, uint16_t* Alo, int64_t ldh, int32_t* colexp, int32_t* gexp,
-                void* stream);
+ * Layout ("fragment tiles", the order in which the 16x16x32 matrix-core
+ * instruction consumes its operands): the encoded operand X (R x K) is
+ *   form RQLP_ENC_COLS: X = A^T (R = n, K = m), the operand of B = V^T A;
+ *   form RQLP_ENC_ROWS: X = A   (R = m, K = n), the operand of Y = A X;
+ * it is stored as ceil(R/16) * ceil(K/32) blocks of 512 elements, block
+ * (rb, kb) starting at element (rb * ceil(K/32) + kb) * 512 and holding
+ * X(16 rb + t % 16, 32 kb + 8 (t / 16) + e) at offset 8 t + e (t < 64, e < 8);
+ * entries beyond X are zero.  rqlp_encoded_elems gives the element count of
+ * Ahi (and of Alo, which must be NULL unless BF16X3).  Elements are raw
+ * 16-bit patterns.  The caller owns all buffers. */
+#define RQLP_ENC_COLS 0
+#define RQLP_ENC_ROWS 1
+int rqlp_encoded_elems(int64_t m, int64_t n, int form, size_t* elems);
+int rqlp_encode(const float* A, int64_t lda, int64_t m, int64_t n, int precision, int form,
+                uint16_t* Ahi, uint16_t* Alo, int32_t* colexp, int32_t* gexp, void* stream);
 
-/* B = V^T A (Algorithm 2.1 step 4) with A given as rqlp_encode's column-major
- * encoding (Ahi, Alo, ldh >= m; colexp for RQLP_MIXED_FP16, else NULL); V is
- * m x c float, rounded to the same 16-bit type inside; B is c x n float,
- * FP32 accumulation.  Lets a caller encode A once and reuse it. */
-int rqlp_project_encoded(const uint16_t* Ahi, const uint16_t* Alo, int64_t ldh, const int32_t* colexp,
-                         int64_t m, int64_t n, const float* V, int64_t ldv, int64_t c, float* B,
-                         int64_t ldb, int precision, void* work, size_t work_bytes, void* stream);
+/* B = V^T A (Algorithm 2.1 step 4) with A given by rqlp_encode in form
+ * RQLP_ENC_COLS (Ahi, Alo; colexp for RQLP_MIXED_FP16, else NULL; gexp is
+ * not used and may be NULL); V is m x c float, rounded to the same 16-bit
+ * type inside; B is c x n float, FP32 accumulation.  Lets a caller encode A
+ * once and reuse it.  Work: rqlp_gemm_workspace(m, n, c). */
+int rqlp_project_encoded(const uint16_t* Ahi, const uint16_t* Alo, const int32_t* colexp,
+                         const int32_t* gexp, int64_t m, int64_t n, const float* V, int64_t ldv,
+                         int64_t c, float* B, int64_t ldb, int precision, void* work,
+                         size_t work_bytes, void* stream);
+
+/* Y = A X (Algorithm 2.1 step 2 and the subspace iterations) with A given by
+ * rqlp_encode in form RQLP_ENC_ROWS (colexp and gexp required for
+ * RQLP_MIXED_FP16); X is n x c float, rounded inside (FP16: row j scaled by
+ * 2^(e_j - g), Y by 2^g); Y is m x c float.  Same error conventions as
+ * rqlp_project_encoded (argument numbers in this order). */
+int rqlp_sketch_encoded(const uint16_t* Ahi, const uint16_t* Alo, const int32_t* colexp,
+                        const int32_t* gexp, int64_t m, int64_t n, const float* X, int64_t ldx,
+                        int64_t c, float* Y, int64_t ldy, int precision, void* work,
+                        size_t work_bytes, void* stream);
 
 /* [V, ~] = qr(Y)  (Algorithm 2.1 step 3): V (m x c) gets an orthonormal basis
  * of range(Y) by CholeskyQR2 (shifted retry on breakdown); Y is m x c,

@@ -246,41 +246,46 @@ def project(A, V, precision=None):
     return B
 
 
+ENC_FORMS = {"cols": 0, "rows": 1}
+
+
 @dataclass
 class Encoded:
-    """A encoded for the 16-bit MFMA products (``rqlp_encode``)."""
-    hi: "object"          # uint16 bit patterns, column-major (m x n) or A^T (n x m)
+    """A encoded for the 16-bit MFMA products (``rqlp_encode``): flat fragment-tiled
+    copies (form "cols": the operand A^T of B = V^T A; "rows": the operand A of Y = A X)."""
+    hi: "object"          # uint16 bit patterns as int16, rqlp_encoded_elems entries
     lo: "object"          # bf16x3 remainders or None
     colexp: "object"      # int32 per-column exponents (FP16) or None
     gexp: "object"        # int32 max exponent (FP16) or None
     m: int
     n: int
     precision: int
-    transpose: bool
+    form: str
 
 
-def encode(A, precision="bf16", transpose: bool = False) -> Encoded:
+def encode(A, precision="bf16", form: str = "cols") -> Encoded:
     """16-bit encoding of the FP32 device matrix A through ``rqlp_encode``."""
     torch = _torch()
     prec = _prec(precision)
     A = colmajor(A)
     m, n = A.shape
-    rows, cols = (n, m) if transpose else (m, n)
-    hi = empty_colmajor(rows, cols, torch.int16, A.device)
-    lo = empty_colmajor(rows, cols, torch.int16, A.device) if prec == PRECISIONS["bf16x3"] else None
+    f = ENC_FORMS[form]
+    ne = _lib.rqlp_encoded_elems(m, n, f)
+    hi = torch.empty(max(ne, 1), dtype=torch.int16, device=A.device)
+    lo = torch.empty(max(ne, 1), dtype=torch.int16, device=A.device) if prec == PRECISIONS["bf16x3"] else None
     fp16 = prec == PRECISIONS["fp16"]
-    colexp = torch.empty(n, dtype=torch.int32, device=A.device) if fp16 else None
+    colexp = torch.empty(max(n, 1), dtype=torch.int32, device=A.device) if fp16 else None
     gexp = torch.empty(1, dtype=torch.int32, device=A.device) if fp16 else None
-    check("rqlp_encode", _lib.rqlp_encode(A.data_ptr(), ld(A), m, n, prec, int(transpose), hi.data_ptr(),
-                                          _ptr(lo), ld(hi), _ptr(colexp), _ptr(gexp), _stream(A.device)))
-    return Encoded(hi, lo, colexp, gexp, m, n, prec, transpose)
+    check("rqlp_encode", _lib.rqlp_encode(A.data_ptr(), ld(A), m, n, prec, f, hi.data_ptr(), _ptr(lo),
+                                          _ptr(colexp), _ptr(gexp), _stream(A.device)))
+    return Encoded(hi[:ne], None if lo is None else lo[:ne], colexp, gexp, m, n, prec, form)
 
 
 def project_encoded(E: Encoded, V, B=None, work=None):
-    """B = V^T A through ``rqlp_project_encoded`` with A pre-encoded (column-major form)."""
+    """B = V^T A through ``rqlp_project_encoded`` with A pre-encoded (form "cols")."""
     torch = _torch()
-    if E.transpose:
-        raise ValueError("project_encoded needs the column-major encoding")
+    if E.form != "cols":
+        raise ValueError("project_encoded needs the encoding of form 'cols'")
     V = colmajor(V)
     c = V.shape[1]
     if B is None:
@@ -288,11 +293,30 @@ def project_encoded(E: Encoded, V, B=None, work=None):
     nb = _lib.rqlp_gemm_workspace(E.m, E.n, c, E.precision)
     if work is None or work.numel() < nb:
         work = torch.empty(nb, dtype=torch.uint8, device=V.device)
-    check("rqlp_project_encoded", _lib.rqlp_project_encoded(E.hi.data_ptr(), _ptr(E.lo), ld(E.hi), _ptr(E.colexp),
-                                                            E.m, E.n, V.data_ptr(), ld(V), c, B.data_ptr(), ld(B),
-                                                            E.precision, work.data_ptr(), work.numel(),
-                                                            _stream(V.device)))
+    check("rqlp_project_encoded", _lib.rqlp_project_encoded(E.hi.data_ptr(), _ptr(E.lo), _ptr(E.colexp),
+                                                            _ptr(E.gexp), E.m, E.n, V.data_ptr(), ld(V), c,
+                                                            B.data_ptr(), ld(B), E.precision, work.data_ptr(),
+                                                            work.numel(), _stream(V.device)))
     return B
+
+
+def sketch_encoded(E: Encoded, X, Y=None, work=None):
+    """Y = A X through ``rqlp_sketch_encoded`` with A pre-encoded (form "rows")."""
+    torch = _torch()
+    if E.form != "rows":
+        raise ValueError("sketch_encoded needs the encoding of form 'rows'")
+    X = colmajor(X)
+    c = X.shape[1]
+    if Y is None:
+        Y = empty_colmajor(E.m, c, torch.float32, X.device)
+    nb = _lib.rqlp_gemm_workspace(E.m, E.n, c, E.precision)
+    if work is None or work.numel() < nb:
+        work = torch.empty(nb, dtype=torch.uint8, device=X.device)
+    check("rqlp_sketch_encoded", _lib.rqlp_sketch_encoded(E.hi.data_ptr(), _ptr(E.lo), _ptr(E.colexp),
+                                                          _ptr(E.gexp), E.m, E.n, X.data_ptr(), ld(X), c,
+                                                          Y.data_ptr(), ld(Y), E.precision, work.data_ptr(),
+                                                          work.numel(), _stream(X.device)))
+    return Y
 
 
 def orthonormalize(Y, want_r: bool = False):

@@ -36,10 +36,13 @@ SIGNATURES = {
     "rqlp_project": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_int64, c_void_p, c_int64,
                              c_int, c_void_p, c_size_t, c_void_p]),
     "rqlp_gemm_workspace": (c_int, [c_int64, c_int64, c_int64, c_int, POINTER(c_size_t)]),
-    "rqlp_encode": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_int, c_int, c_void_p, c_void_p, c_int64,
-                            c_void_p, c_void_p, c_void_p]),
-    "rqlp_project_encoded": (c_int, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int64, c_void_p, c_int64,
+    "rqlp_encoded_elems": (c_int, [c_int64, c_int64, c_int, POINTER(c_size_t)]),
+    "rqlp_encode": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                            c_void_p, c_void_p]),
+    "rqlp_project_encoded": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64,
                                      c_int64, c_void_p, c_int64, c_int, c_void_p, c_size_t, c_void_p]),
+    "rqlp_sketch_encoded": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_int64,
+                                    c_int64, c_void_p, c_int64, c_int, c_void_p, c_size_t, c_void_p]),
     "rqlp_orthonormalize": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                                     c_void_p, c_void_p, c_size_t, c_void_p]),
     "rqlp_orthonormalize_workspace": (c_int, [c_int64, c_int64, POINTER(c_size_t)]),
@@ -134,13 +137,25 @@ def rqlp_gemm_workspace(m, n, c, precision) -> int:
     return out.value
 
 
-def rqlp_encode(A, lda, m, n, precision, transpose, Ahi, Alo, ldh, colexp, gexp, stream) -> int:
-    return _call("rqlp_encode", A, lda, m, n, precision, transpose, Ahi, Alo, ldh, colexp, gexp, stream)
+def rqlp_encoded_elems(m, n, form) -> int:
+    out = c_size_t(0)
+    check("rqlp_encoded_elems", _call("rqlp_encoded_elems", m, n, form, ctypes.byref(out)))
+    return out.value
 
 
-def rqlp_project_encoded(Ahi, Alo, ldh, colexp, m, n, V, ldv, c, B, ldb, precision, work, work_bytes,
+def rqlp_encode(A, lda, m, n, precision, form, Ahi, Alo, colexp, gexp, stream) -> int:
+    return _call("rqlp_encode", A, lda, m, n, precision, form, Ahi, Alo, colexp, gexp, stream)
+
+
+def rqlp_project_encoded(Ahi, Alo, colexp, gexp, m, n, V, ldv, c, B, ldb, precision, work, work_bytes,
                          stream) -> int:
-    return _call("rqlp_project_encoded", Ahi, Alo, ldh, colexp, m, n, V, ldv, c, B, ldb, precision, work,
+    return _call("rqlp_project_encoded", Ahi, Alo, colexp, gexp, m, n, V, ldv, c, B, ldb, precision, work,
+                 work_bytes, stream)
+
+
+def rqlp_sketch_encoded(Ahi, Alo, colexp, gexp, m, n, X, ldx, c, Y, ldy, precision, work, work_bytes,
+                        stream) -> int:
+    return _call("rqlp_sketch_encoded", Ahi, Alo, colexp, gexp, m, n, X, ldx, c, Y, ldy, precision, work,
                  work_bytes, stream)
 
 

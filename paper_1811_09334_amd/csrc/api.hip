@@ -288,7 +288,7 @@ struct RangeBufsLP {
     int* colexp;            // n (FP16 only)
     int* gexp;              // 1
     float* Om;              // n x l (generated test matrix)
-    unsigned short* X16;    // max(m, n) x l 16-bit panel (Omega, W or V)
+    unsigned short* X16;    // tiled 16-bit panel operand (Omega^T, W^T or V^T: l x max(m, n))
     unsigned short* X16lo;
     float* Y;               // m x l
     float* Y2;
@@ -311,16 +311,17 @@ struct RangeBufsLP {
 void carve_range_lp(Arena& ar, int64_t m, int64_t n, int64_t l, int precision, bool need_omega, RangeBufsLP* r) {
     const bool x3 = precision == RQLP_MIXED_BF16X3;
     const bool f32 = precision == RQLP_F32;
-    r->Ac = f32 ? nullptr : ar.take<unsigned short>(m * n);
-    r->Ar = f32 ? nullptr : ar.take<unsigned short>(m * n);
-    r->Aclo = x3 ? ar.take<unsigned short>(m * n) : nullptr;
-    r->Arlo = x3 ? ar.take<unsigned short>(m * n) : nullptr;
+    const size_t ec = lp_tiled_elems(n, m), er = lp_tiled_elems(m, n);
+    r->Ac = f32 ? nullptr : ar.take<unsigned short>(ec);
+    r->Ar = f32 ? nullptr : ar.take<unsigned short>(er);
+    r->Aclo = x3 ? ar.take<unsigned short>(ec) : nullptr;
+    r->Arlo = x3 ? ar.take<unsigned short>(er) : nullptr;
     r->colexp = ar.take<int>(n);
     r->gexp = ar.take<int>(1);
     r->Om = need_omega ? ar.take<float>(n * l) : nullptr;
     const int64_t mx = m > n ? m : n;
-    r->X16 = f32 ? nullptr : ar.take<unsigned short>(mx * l);
-    r->X16lo = x3 ? ar.take<unsigned short>(mx * l) : nullptr;
+    r->X16 = f32 ? nullptr : ar.take<unsigned short>(lp_tiled_elems(l, mx));
+    r->X16lo = x3 ? ar.take<unsigned short>(lp_tiled_elems(l, mx)) : nullptr;
     r->Y = ar.take<float>(m * l);
     r->Y2 = ar.take<float>(m * l);
     r->Z = ar.take<float>(n * l);
@@ -547,36 +548,36 @@ int range_and_project_lp(Ctx32& c32, RangeBufsLP& r, SmallBufs& f, int kind, con
     const int* cexp = fp16 ? r.colexp : nullptr;
     const int* gexp = fp16 ? r.gexp : nullptr;
     if (fp16) RQLP_TRY(column_exponents(m, n, A, lda, r.colexp, r.gexp, s));
-    RQLP_TRY(encode_both(kind, m, n, A, lda, r.Ac, r.Aclo, m, r.Ar, r.Arlo, n, cexp, s));
+    RQLP_TRY(encode_tiled(kind, m, n, A, lda, r.Ac, r.Aclo, r.Ar, r.Arlo, cexp, s));
     if (!Om) {
         RQLP_TRY(generate_omega(n, l, seed, kind, r.Om, n, s));
         Om = r.Om;
         ldom = n;
     }
     // Y = A Omega  (FP16: (A D^-1)(2^-g D Omega) 2^g)
-    RQLP_TRY(cast_to_lp(kind, n, l, Om, ldom, r.X16, r.X16lo, n, false, cexp, nullptr, gexp, s));
-    RQLP_TRY(gemm_lp<float>(kind, m, l, n, r.Ar, r.Arlo, n, r.X16, r.X16lo, n, r.Y, m, false, nullptr, gexp, r.lpws,
+    RQLP_TRY(cast_panel(kind, l, n, Om, ldom, r.X16, r.X16lo, cexp, gexp, s));
+    RQLP_TRY(gemm_lp<float>(kind, m, l, n, r.Ar, r.Arlo, r.X16, r.X16lo, r.Y, m, false, nullptr, gexp, r.lpws,
                             r.lpws_elems, s));
     float* V = nullptr;
     RQLP_TRY(ortho_f32(c32, m, l, bs, r.Y, r.Y2, m, &V, q == 0, bc));
     for (int it = 0; it < q; ++it) {
         // Z = A^T V  (FP16: D (A D^-1)^T V)
-        RQLP_TRY(cast_to_lp(kind, m, l, V, m, r.X16, r.X16lo, m, false, nullptr, nullptr, nullptr, s));
-        RQLP_TRY(gemm_lp<float>(kind, n, l, m, r.Ac, r.Aclo, m, r.X16, r.X16lo, m, r.Z, n, false, cexp, nullptr,
+        RQLP_TRY(cast_panel(kind, l, m, V, m, r.X16, r.X16lo, nullptr, nullptr, s));
+        RQLP_TRY(gemm_lp<float>(kind, n, l, m, r.Ac, r.Aclo, r.X16, r.X16lo, r.Z, n, false, cexp, nullptr,
                                 r.lpws, r.lpws_elems, s));
         float* W = nullptr;
         RQLP_TRY(ortho_f32(c32, n, l, bs, r.Z, r.Z2, n, &W, false, bc));
         // Y = A W
-        RQLP_TRY(cast_to_lp(kind, n, l, W, n, r.X16, r.X16lo, n, false, cexp, nullptr, gexp, s));
+        RQLP_TRY(cast_panel(kind, l, n, W, n, r.X16, r.X16lo, cexp, gexp, s));
         float* ydst = (V == r.Y) ? r.Y2 : r.Y;
-        RQLP_TRY(gemm_lp<float>(kind, m, l, n, r.Ar, r.Arlo, n, r.X16, r.X16lo, n, ydst, m, false, nullptr, gexp,
+        RQLP_TRY(gemm_lp<float>(kind, m, l, n, r.Ar, r.Arlo, r.X16, r.X16lo, ydst, m, false, nullptr, gexp,
                                 r.lpws, r.lpws_elems, s));
         float* other = (ydst == r.Y) ? r.Y2 : r.Y;
         RQLP_TRY(ortho_f32(c32, m, l, bs, ydst, other, m, &V, it == q - 1, bc));
     }
     // B = V^T A = (A^T V)^T, FP32 accumulation, stored l x n in FP64
-    RQLP_TRY(cast_to_lp(kind, m, l, V, m, r.X16, r.X16lo, m, false, nullptr, nullptr, nullptr, s));
-    RQLP_TRY(gemm_lp<double>(kind, n, l, m, r.Ac, r.Aclo, m, r.X16, r.X16lo, m, f.B, l, true, cexp, nullptr, r.lpws,
+    RQLP_TRY(cast_panel(kind, l, m, V, m, r.X16, r.X16lo, nullptr, nullptr, s));
+    RQLP_TRY(gemm_lp<double>(kind, n, l, m, r.Ac, r.Aclo, r.X16, r.X16lo, f.B, l, true, cexp, nullptr, r.lpws,
                              r.lpws_elems, s));
     *Vout = V;
     return 0;
@@ -727,10 +728,11 @@ struct LpOp {
 void carve_lp_op(Arena& ar, int64_t m, int64_t n, int64_t c, int precision, LpOp* o) {
     const bool x3 = precision == RQLP_MIXED_BF16X3;
     const int64_t mx = m > n ? m : n;
-    o->Ah = ar.take<unsigned short>(m * n);
-    o->Al = x3 ? ar.take<unsigned short>(m * n) : nullptr;
-    o->Xh = ar.take<unsigned short>(mx * c);
-    o->Xl = x3 ? ar.take<unsigned short>(mx * c) : nullptr;
+    const size_t ea = lp_tiled_elems(m, n) > lp_tiled_elems(n, m) ? lp_tiled_elems(m, n) : lp_tiled_elems(n, m);
+    o->Ah = ar.take<unsigned short>(ea);
+    o->Al = x3 ? ar.take<unsigned short>(ea) : nullptr;
+    o->Xh = ar.take<unsigned short>(lp_tiled_elems(c, mx));
+    o->Xl = x3 ? ar.take<unsigned short>(lp_tiled_elems(c, mx)) : nullptr;
     o->colexp = ar.take<int>(n > 0 ? n : 1);
     o->gexp = ar.take<int>(1);
     o->ws_elems = max_ws(gemm_lp_workspace_elems, {{m, c, n}, {n, c, m}});
@@ -778,11 +780,10 @@ int rqlp_sketch(const void* A, int64_t lda, int64_t m, int64_t n, const void* X,
         const bool fp16 = precision == RQLP_MIXED_FP16;
         const float* Af = (const float*)A;
         if (fp16) RQLP_TRY(column_exponents(m, n, Af, lda, o.colexp, o.gexp, s));
-        RQLP_TRY(cast_to_lp(precision, m, n, Af, lda, o.Ah, o.Al, n, true, nullptr, fp16 ? o.colexp : nullptr,
-                            nullptr, s));
-        RQLP_TRY(cast_to_lp(precision, n, c, (const float*)X, ldx, o.Xh, o.Xl, n, false, fp16 ? o.colexp : nullptr,
-                            nullptr, fp16 ? o.gexp : nullptr, s));
-        return gemm_lp<float>(precision, m, c, n, o.Ah, o.Al, n, o.Xh, o.Xl, n, (float*)Y, ldy, false, nullptr,
+        RQLP_TRY(encode_tiled(precision, m, n, Af, lda, nullptr, nullptr, o.Ah, o.Al, fp16 ? o.colexp : nullptr, s));
+        RQLP_TRY(cast_panel(precision, c, n, (const float*)X, ldx, o.Xh, o.Xl, fp16 ? o.colexp : nullptr,
+                            fp16 ? o.gexp : nullptr, s));
+        return gemm_lp<float>(precision, m, c, n, o.Ah, o.Al, o.Xh, o.Xl, (float*)Y, ldy, false, nullptr,
                               fp16 ? o.gexp : nullptr, o.ws, o.ws_elems, s);
     }
     size_t e = gemm_workspace_elems(m, c, n);
@@ -818,11 +819,9 @@ int rqlp_project(const void* A, int64_t lda, int64_t m, int64_t n, const void* V
         const bool fp16 = precision == RQLP_MIXED_FP16;
         const float* Af = (const float*)A;
         if (fp16) RQLP_TRY(column_exponents(m, n, Af, lda, o.colexp, o.gexp, s));
-        RQLP_TRY(cast_to_lp(precision, m, n, Af, lda, o.Ah, o.Al, m, false, nullptr, fp16 ? o.colexp : nullptr,
-                            nullptr, s));
-        RQLP_TRY(cast_to_lp(precision, m, c, (const float*)V, ldv, o.Xh, o.Xl, m, false, nullptr, nullptr, nullptr,
-                            s));
-        return gemm_lp<float>(precision, n, c, m, o.Ah, o.Al, m, o.Xh, o.Xl, m, (float*)B, ldb, true,
+        RQLP_TRY(encode_tiled(precision, m, n, Af, lda, o.Ah, o.Al, nullptr, nullptr, fp16 ? o.colexp : nullptr, s));
+        RQLP_TRY(cast_panel(precision, c, m, (const float*)V, ldv, o.Xh, o.Xl, nullptr, nullptr, s));
+        return gemm_lp<float>(precision, n, c, m, o.Ah, o.Al, o.Xh, o.Xl, (float*)B, ldb, true,
                               fp16 ? o.colexp : nullptr, nullptr, o.ws, o.ws_elems, s);
     }
     size_t e = gemm_workspace_elems(n, c, m);
@@ -838,53 +837,96 @@ int rqlp_project(const void* A, int64_t lda, int64_t m, int64_t n, const void* V
                        ws, e, s);
 }
 
-int rqlp_encode(const float* A, int64_t lda, int64_t m, int64_t n, int precision, int transpose, uint16_t* Ahi,
-                uint16_t* Alo, int64_t ldh, int32_t* colexp, int32_t* gexp, void* stream) {
+int rqlp_encoded_elems(int64_t m, int64_t n, int form, size_t* elems) {
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (form != RQLP_ENC_COLS && form != RQLP_ENC_ROWS) return -3;
+    if (!elems) return -4;
+    *elems = form == RQLP_ENC_COLS ? lp_tiled_elems(n, m) : lp_tiled_elems(m, n);
+    return 0;
+}
+
+int rqlp_encode(const float* A, int64_t lda, int64_t m, int64_t n, int precision, int form, uint16_t* Ahi,
+                uint16_t* Alo, int32_t* colexp, int32_t* gexp, void* stream) {
     if (m < 0) return -3;
     if (n < 0) return -4;
     if (lda < (m > 1 ? m : 1)) return -2;
     if (!is_mixed(precision)) return -5;
-    const int64_t rows_h = transpose ? n : m;
-    if (ldh < (rows_h > 1 ? rows_h : 1)) return -9;
+    if (form != RQLP_ENC_COLS && form != RQLP_ENC_ROWS) return -6;
     if (m * n == 0) return 0;
     if (!A) return -1;
     if (!Ahi) return -7;
     if ((Alo != nullptr) != (precision == RQLP_MIXED_BF16X3)) return -8;
     const bool fp16 = precision == RQLP_MIXED_FP16;
-    if (fp16 && !colexp) return -10;
-    if (fp16 && !gexp) return -11;
+    if (fp16 && !colexp) return -9;
+    if (fp16 && !gexp) return -10;
     hipStream_t s = (hipStream_t)stream;
     if (fp16) RQLP_TRY(column_exponents(m, n, A, lda, colexp, gexp, s));
-    return cast_to_lp(precision, m, n, A, lda, (unsigned short*)Ahi, (unsigned short*)Alo, ldh, transpose != 0,
-                      nullptr, fp16 ? colexp : nullptr, nullptr, s);
+    unsigned short* hi = (unsigned short*)Ahi;
+    unsigned short* lo = (unsigned short*)Alo;
+    if (form == RQLP_ENC_COLS) return encode_tiled(precision, m, n, A, lda, hi, lo, nullptr, nullptr, fp16 ? colexp : nullptr, s);
+    return encode_tiled(precision, m, n, A, lda, nullptr, nullptr, hi, lo, fp16 ? colexp : nullptr, s);
 }
 
-int rqlp_project_encoded(const uint16_t* Ahi, const uint16_t* Alo, int64_t ldh, const int32_t* colexp, int64_t m,
-                         int64_t n, const float* V, int64_t ldv, int64_t c, float* B, int64_t ldb, int precision,
-                         void* work, size_t work_bytes, void* stream) {
-    if (ldh < (m > 1 ? m : 1)) return -3;
+namespace {
+// Shared argument checks of the two products on an encoded A: the panel P
+// (prow x c, ldp) and the output O (leading dimension ldo >= orow, oelems
+// entries), inner dimension K.
+// Returns 1 when there is nothing to compute (empty output), 0 to proceed.
+int check_encoded_args(const uint16_t* Ahi, const uint16_t* Alo, const int32_t* colexp, const int32_t* gexp,
+                       bool need_gexp, int64_t m, int64_t n, const float* P, int64_t ldp, int64_t prow, int64_t c,
+                       const float* O, int64_t ldo, int64_t orow, int64_t oelems, int64_t K, int precision) {
     if (m < 0) return -5;
     if (n < 0) return -6;
-    if (ldv < (m > 1 ? m : 1)) return -8;
+    if (ldp < (prow > 1 ? prow : 1)) return -8;
     if (c < 0) return -9;
-    if (ldb < (c > 1 ? c : 1)) return -11;
+    if (ldo < (orow > 1 ? orow : 1)) return -11;
     if (!is_mixed(precision)) return -12;
-    if (n * c == 0) return 0;
+    if (oelems == 0) return 1;
+    if (!O) return -10;
+    if (K == 0) return 0;
     if (!Ahi) return -1;
     if ((Alo != nullptr) != (precision == RQLP_MIXED_BF16X3)) return -2;
-    if (precision == RQLP_MIXED_FP16 && !colexp) return -4;
-    if (!V) return -7;
-    if (!B) return -10;
+    if (precision == RQLP_MIXED_FP16 && !colexp) return -3;
+    if (precision == RQLP_MIXED_FP16 && need_gexp && !gexp) return -4;
+    if (!P) return -7;
+    return 0;
+}
+}  // namespace
+
+int rqlp_project_encoded(const uint16_t* Ahi, const uint16_t* Alo, const int32_t* colexp, const int32_t* gexp,
+                         int64_t m, int64_t n, const float* V, int64_t ldv, int64_t c, float* B, int64_t ldb,
+                         int precision, void* work, size_t work_bytes, void* stream) {
+    const int chk = check_encoded_args(Ahi, Alo, colexp, gexp, false, m, n, V, ldv, m, c, B, ldb, c, n * c, m, precision);
+    if (chk != 0) return chk < 0 ? chk : 0;
     Arena ar = arena_for(work, work_bytes);
-    unsigned short* Vh = ar.take<unsigned short>(m * c);
-    unsigned short* Vl = precision == RQLP_MIXED_BF16X3 ? ar.take<unsigned short>(m * c) : nullptr;
+    unsigned short* Vh = ar.take<unsigned short>(lp_tiled_elems(c, m));
+    unsigned short* Vl = precision == RQLP_MIXED_BF16X3 ? ar.take<unsigned short>(lp_tiled_elems(c, m)) : nullptr;
     const size_t e = gemm_lp_workspace_elems(n, c, m);
     float* ws = ar.take<float>(e);
     if (!ar.ok()) return RQLP_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    RQLP_TRY(cast_to_lp(precision, m, c, V, ldv, Vh, Vl, m, false, nullptr, nullptr, nullptr, s));
-    return gemm_lp<float>(precision, n, c, m, (const unsigned short*)Ahi, (const unsigned short*)Alo, ldh, Vh, Vl, m,
-                          B, ldb, true, precision == RQLP_MIXED_FP16 ? colexp : nullptr, nullptr, ws, e, s);
+    RQLP_TRY(cast_panel(precision, c, m, V, ldv, Vh, Vl, nullptr, nullptr, s));
+    return gemm_lp<float>(precision, n, c, m, (const unsigned short*)Ahi, (const unsigned short*)Alo, Vh, Vl, B, ldb,
+                          true, precision == RQLP_MIXED_FP16 ? colexp : nullptr, nullptr, ws, e, s);
+}
+
+int rqlp_sketch_encoded(const uint16_t* Ahi, const uint16_t* Alo, const int32_t* colexp, const int32_t* gexp,
+                        int64_t m, int64_t n, const float* X, int64_t ldx, int64_t c, float* Y, int64_t ldy,
+                        int precision, void* work, size_t work_bytes, void* stream) {
+    const int chk = check_encoded_args(Ahi, Alo, colexp, gexp, true, m, n, X, ldx, n, c, Y, ldy, m, m * c, n, precision);
+    if (chk != 0) return chk < 0 ? chk : 0;
+    Arena ar = arena_for(work, work_bytes);
+    unsigned short* Xh = ar.take<unsigned short>(lp_tiled_elems(c, n));
+    unsigned short* Xl = precision == RQLP_MIXED_BF16X3 ? ar.take<unsigned short>(lp_tiled_elems(c, n)) : nullptr;
+    const size_t e = gemm_lp_workspace_elems(m, c, n);
+    float* ws = ar.take<float>(e);
+    if (!ar.ok()) return RQLP_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const bool fp16 = precision == RQLP_MIXED_FP16;
+    RQLP_TRY(cast_panel(precision, c, n, X, ldx, Xh, Xl, fp16 ? colexp : nullptr, fp16 ? gexp : nullptr, s));
+    return gemm_lp<float>(precision, m, c, n, (const unsigned short*)Ahi, (const unsigned short*)Alo, Xh, Xl, Y, ldy,
+                          false, nullptr, fp16 ? gexp : nullptr, ws, e, s);
 }
 
 int rqlp_orthonormalize_workspace(int64_t m, int64_t c, size_t* bytes) {

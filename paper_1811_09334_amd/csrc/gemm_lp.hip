@@ -3,25 +3,38 @@
 // subspace iterations), with A, W, V rounded to bfloat16 or IEEE half and
 // FP32 accumulation on the gfx950 matrix cores (v_mfma_f32_16x16x32_bf16 /
 // _f16).  The split form ("bf16x3") keeps x = hi + lo in two bfloat16 parts
-// and accumulates hi*hi + hi*lo + lo*hi (Henry, Tang, Heinecke, ARITH 2019).
+// and accumulates lo*hi + hi*lo + hi*hi (Henry, Tang, Heinecke, ARITH 2019).
 //
-// The kernel computes C(i, j) = sum_k P(k + i * ldp) * Q(k + j * ldq): both
-// operands are "k-contiguous", which is what the 16x16x32 MFMA wants (a lane
-// feeds 8 consecutive k of one row or column).  A W uses a row-major 16-bit
-// copy of A, A^T V the column-major one; W and V are column-major.
+// Operand format ("fragment tiles").  Every product here is
+// C(i, j) = sum_k X(i, k) Y(j, k) with both operands k-contiguous, which is
+// what the 16x16x32 MFMA consumes: lane t of a wave feeds row t % 16 and the
+// eight k values 8 (t / 16) .. +7.  The 16-bit copies are therefore stored as
+// 1 KB blocks of 16 rows x 32 k in exactly that lane order (block (rb, kb) at
+// element (rb * nkb + kb) * 512, lane t at + 8 t), zero-padded to whole
+// blocks.  A wave then reads a fragment as one contiguous 1 KB, every block
+// row is one sequential stream through HBM, and ragged edges need no bounds
+// checks (the padding multiplies as zero).  A row-major or column-major
+// 16-bit copy instead makes every 16-byte fragment load touch a different
+// DRAM row, which held these products to about a third of the HBM rate.
 //
-// Tiling: 4 waves, each 32 rows x (16 NB) columns (2 x NB accumulators of
-// 16x16); a workgroup covers 128 rows and all (or a share) of the l columns,
-// so A streams from HBM about once per product.  K advances in stages of 32
-// through two LDS buffers (rows padded to 40 elements so that the 16-byte
-// fragment reads of a wave spread over all banks); split-K partial sums are
-// added in a fixed order by a separate reduce, so results are reproducible.
+// Kernel: 8 waves per workgroup, each 32 rows x (16 NB) columns (2 x NB
+// accumulator tiles); the workgroup covers 256 rows of X and NB column blocks
+// of Y.  X fragments go straight from HBM into registers (each wave owns its
+// rows), NBUF stages ahead; the Y blocks, shared by all waves, are copied
+// into LDS by the load unit itself (global_load_lds_dwordx4, no registers)
+// in the same fragment order, so the MFMA reads them with conflict-free
+// 16-byte LDS loads.  The barrier between stages waits only for the copies of
+// the stage about to be used (explicit vmcnt), keeping NBUF - 1 stages of
+// both operands in flight.  K is split over workgroups (fixed-order
+// reduction in a second kernel, so results are reproducible), and the
+// workgroups sharing one K range of Y are placed on one XCD (blocks are
+// dealt round-robin to the 8 XCDs), so that slice of Y stays in that XCD's L2.
 //
 // IEEE half has too little exponent range for typical matrix entries, so
 // the FP16 form stores A D^{-1} with D = diag(2^e_j) chosen per column
 // (max |A(:, j)| 2^-e_j in [2^14, 2^15)); A W = (A D^{-1}) (D W) with D W
-// stored as 2^-g D W (g = max e_j) and the 2^g put back in the epilogue, and
-// A^T V = D (A D^{-1})^T V with the row scale applied in the epilogue.
+// stored as 2^-g D W (g = max e_j) and the 2^g put back in the reduction, and
+// A^T V = D (A D^{-1})^T V with the row scale applied in the reduction.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -31,10 +44,22 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
 
-constexpr int LP_BM = 128;
-constexpr int LP_BK = 32;
-constexpr int LP_SK = LP_BK + 8;     // LDS row stride in 16-bit elements (80 bytes)
-constexpr int LP_THREADS = 256;
+constexpr int LP_WAVES = 8;
+constexpr int LP_THREADS = 64 * LP_WAVES;
+constexpr int LP_BM = 32 * LP_WAVES;     // rows of X per workgroup
+constexpr int LP_BLK = 512;              // elements of one 16 x 32 fragment block
+
+#define RQLP_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
+// LDS-only barrier: the compiler's __syncthreads also waits for every
+// outstanding global load (vmcnt(0)), which would drain the prefetch queue.
+#define RQLP_LDS_BARRIER() asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory")
+
+// s_waitcnt with only the vector-memory counter constrained (at most n outstanding)
+template <int n>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(n >= 0 && n < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt(0x0F70 | (n & 15) | ((n >> 4) << 14));
+}
 
 template <int KIND>
 __device__ __forceinline__ float4_t mfma_lp(u16x8_t a, u16x8_t b, float4_t c) {
@@ -46,27 +71,40 @@ __device__ __forceinline__ float4_t mfma_lp(u16x8_t a, u16x8_t b, float4_t c) {
                                                        __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
 }
 
-// X3: operands come in (hi, lo) pairs at the same offsets of P / Plo and Q / Qlo.
-// VEC: every 8-element k-chunk is 16-byte aligned and lies wholly inside or
-// outside [0, K) (K, ldp, ldq multiples of 8, aligned bases), so tiles load
-// with plain 16-byte loads; otherwise element loads with bounds checks.
-template <int KIND, int NB, bool X3, bool VEC>
-__global__ __launch_bounds__(LP_THREADS) void gemm_lp_kernel(
-    int64_t M, int64_t N, int64_t K, const unsigned short* __restrict__ P, const unsigned short* __restrict__ Plo,
-    int64_t ldp, const unsigned short* __restrict__ Q, const unsigned short* __restrict__ Qlo, int64_t ldq,
-    float* __restrict__ C, int64_t ldc, int64_t split_stride, int64_t kchunk) {
-    constexpr int NP = X3 ? 2 : 1;                                  // operand parts
-    constexpr int BN = 16 * NB;
-    constexpr int A_CH = LP_BM * LP_BK / 8 / LP_THREADS;            // 16-byte chunks per thread: 2
-    constexpr int B_CH = (BN * LP_BK / 8 + LP_THREADS - 1) / LP_THREADS;
-    __shared__ __attribute__((aligned(16))) unsigned short As[2][NP][LP_BM * LP_SK];
-    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][NP][BN * LP_SK];
+struct LpGrid {
+    int64_t tm, tn, S;      // row tiles, column tiles, K splits
+    int64_t per_xcd, T;     // tiles per XCD, total tiles
+    int64_t kcb;            // K blocks (of 32) per split
+};
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t m0 = (int64_t)blockIdx.x * LP_BM;
-    const int64_t n0 = (int64_t)blockIdx.y * BN;
-    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
-    const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
+// C(i, j) (+ split z * split_stride) = sum over the z-th K range of X(i, k) Y(j, k),
+// for rows i < mstore (all of a 4-row group stored at once) and columns j < N.
+// X: tiled M x K (P, lo part Plo), Y: tiled N x K (Q, Qlo); nkb = ceil(K / 32).
+template <int KIND, int NB, bool X3>
+__global__ __launch_bounds__(LP_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void gemm_lp_kernel(
+    int64_t M, int64_t N, int64_t nkb, const unsigned short* __restrict__ P, const unsigned short* __restrict__ Plo,
+    const unsigned short* __restrict__ Q, const unsigned short* __restrict__ Qlo, float* __restrict__ C, int64_t ldc,
+    int64_t mstore, int64_t split_stride, LpGrid g) {
+    constexpr int NP = X3 ? 2 : 1;                    // operand parts
+    constexpr int NBUF = X3 ? (NB > 9 ? 2 : 3) : 4;   // LDS stages (register budget of the split form)
+    constexpr int NBW = (NB + LP_WAVES - 1) / LP_WAVES;
+    constexpr int OPS = NP * (NBW + 2);               // vector-memory instructions per wave and stage
+    constexpr int STAGE = NP * NB * LP_BLK;
+    __shared__ __attribute__((aligned(16))) unsigned short Ls[NBUF * STAGE + LP_BLK];   // + a sink kilobyte
+
+    // tile of this workgroup: consecutive tiles (same K range first) on one XCD
+    const int64_t L = blockIdx.x, slot = L >> 3;
+    const int64_t t = (L & 7) * g.per_xcd + slot;
+    if (slot >= g.per_xcd || t >= g.T) return;
+    const int64_t bx = t % g.tm, by = (t / g.tm) % g.tn, bz = t / (g.tm * g.tn);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nrb = (M + 15) >> 4, ncb = (N + 15) >> 4;
+    const int64_t kb0 = bz * g.kcb;
+    const int64_t kb1 = (kb0 + g.kcb < nkb) ? kb0 + g.kcb : nkb;
+    const int64_t nst = kb1 > kb0 ? kb1 - kb0 : 0;
+    const u16x8_t* sink = (const u16x8_t*)(Q + lane * 8);
 
     float4_t acc[2][NB];
 #pragma unroll
@@ -74,109 +112,105 @@ __global__ __launch_bounds__(LP_THREADS) void gemm_lp_kernel(
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[a][b] = float4_t{0.f, 0.f, 0.f, 0.f};
 
-    u16x8_t ra[NP][A_CH], rb[NP][B_CH];
-    // 16-byte chunk ch of a tile row: k = 8 (ch % 4) .. +7 of row ch / 4
-    auto load8 = [&](const unsigned short* base, int64_t ld, int64_t row, int64_t rows, int64_t k) {
-        u16x8_t v = {0, 0, 0, 0, 0, 0, 0, 0};
-        if constexpr (VEC) {
-            if (row < rows && k < kend) v = *(const u16x8_t*)(base + k + row * ld);
-        } else if (row < rows) {
-            const unsigned short* p = base + k + row * ld;
+    // Y blocks this wave copies (b = wave, wave + 8, ...); slots past NB copy a
+    // fixed chunk into the sink kilobyte so that every wave issues OPS copies.
+    const unsigned short* qb[NP][NBW];
+    int lofs[NP][NBW];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = (k + e < kend) ? p[e] : (unsigned short)0;
-        }
-        return v;
-    };
-    auto load_tile = [&](int64_t kt) {
-#pragma unroll
-        for (int c = 0; c < A_CH; ++c) {
-            const int ch = tid + LP_THREADS * c;
-            ra[0][c] = load8(P, ldp, m0 + (ch >> 2), M, kt + 8 * (ch & 3));
-            if constexpr (X3) ra[NP - 1][c] = load8(Plo, ldp, m0 + (ch >> 2), M, kt + 8 * (ch & 3));
-        }
-#pragma unroll
-        for (int c = 0; c < B_CH; ++c) {
-            const int ch = tid + LP_THREADS * c;
-            if (ch < BN * 4) {
-                rb[0][c] = load8(Q, ldq, n0 + (ch >> 2), N, kt + 8 * (ch & 3));
-                if constexpr (X3) rb[NP - 1][c] = load8(Qlo, ldq, n0 + (ch >> 2), N, kt + 8 * (ch & 3));
-            }
-        }
-    };
-    auto store_tile = [&](int buf) {
+    for (int i = 0; i < NBW; ++i) {
+        const int b = wave + LP_WAVES * i;
+        int64_t cb = by * NB + b;
+        if (cb > ncb - 1) cb = ncb - 1;
 #pragma unroll
         for (int h = 0; h < NP; ++h) {
-#pragma unroll
-            for (int c = 0; c < A_CH; ++c) {
-                const int ch = tid + LP_THREADS * c;
-                *(u16x8_t*)&As[buf][h][(ch >> 2) * LP_SK + 8 * (ch & 3)] = ra[h][c];
-            }
-#pragma unroll
-            for (int c = 0; c < B_CH; ++c) {
-                const int ch = tid + LP_THREADS * c;
-                if (ch < BN * 4) *(u16x8_t*)&Bs[buf][h][(ch >> 2) * LP_SK + 8 * (ch & 3)] = rb[h][c];
-            }
+            const unsigned short* base = h ? Qlo : Q;
+            qb[h][i] = b < NB ? base + cb * nkb * LP_BLK + lane * 8 : nullptr;
+            lofs[h][i] = b < NB ? (h * NB + b) * LP_BLK : NBUF * STAGE;
         }
-    };
-
-    if (kbeg < kend) {
-        load_tile(kbeg);
-        store_tile(0);
     }
-    __syncthreads();
-    int buf = 0;
-    const int fr = lane & 15, fk = 8 * (lane >> 4);
-    for (int64_t kt = kbeg; kt < kend; kt += LP_BK) {
-        const bool more = kt + LP_BK < kend;
-        if (more) load_tile(kt + LP_BK);
-        u16x8_t af[NP][2];
+    // X block rows of this wave (clamped into the matrix; the extra rows are never stored)
+    const unsigned short* pa[NP][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        int64_t rb = bx * (2 * LP_WAVES) + wave * 2 + a;
+        if (rb > nrb - 1) rb = nrb - 1;
+#pragma unroll
+        for (int h = 0; h < NP; ++h) pa[h][a] = (h ? Plo : P) + rb * nkb * LP_BLK + lane * 8;
+    }
+    u16x8_t ar[NBUF][NP][2];
+
+    auto issue = [&](int s, int64_t kb) {
+        if (kb > nkb - 1) kb = nkb - 1;               // stages past the range re-read the last block
+        const int64_t ko = kb * LP_BLK;
 #pragma unroll
         for (int h = 0; h < NP; ++h)
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
-                af[h][a] = *(const u16x8_t*)&As[buf][h][(wave * 32 + a * 16 + fr) * LP_SK + fk];
+            for (int i = 0; i < NBW; ++i) {
+                const void* src = qb[h][i] ? (const void*)(qb[h][i] + ko) : (const void*)sink;
+                const int lo = lofs[h][i] < NBUF * STAGE ? s * STAGE + lofs[h][i] : NBUF * STAGE;
+                __builtin_amdgcn_global_load_lds(src, RQLP_LDS_PTR(&Ls[lo]), 16, 0, 0);
+            }
+#pragma unroll
+        for (int h = 0; h < NP; ++h)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) ar[s][h][a] = *(const u16x8_t*)(pa[h][a] + ko);
+    };
+    auto step = [&](int u, int64_t j) {
+        wait_vm<(NBUF - 2) * OPS>();                  // this wave's copies of stage j have landed
+        RQLP_LDS_BARRIER();                           // ... and every wave's; stage j - 1 is free
+        issue((u + NBUF - 1) % NBUF, kb0 + j + NBUF - 1);
+        const unsigned short* Ly = &Ls[u * STAGE + lane * 8];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const u16x8_t bf = *(const u16x8_t*)&Bs[buf][0][(b * 16 + fr) * LP_SK + fk];
+            const u16x8_t bf = *(const u16x8_t*)(Ly + b * LP_BLK);
             if constexpr (X3) {
-                const u16x8_t bl = *(const u16x8_t*)&Bs[buf][NP - 1][(b * 16 + fr) * LP_SK + fk];
+                const u16x8_t bl = *(const u16x8_t*)(Ly + (NB + b) * LP_BLK);
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
-                    acc[a][b] = mfma_lp<KIND>(af[NP - 1][a], bf, acc[a][b]);
-                    acc[a][b] = mfma_lp<KIND>(af[0][a], bl, acc[a][b]);
+                    acc[a][b] = mfma_lp<KIND>(ar[u][1][a], bf, acc[a][b]);
+                    acc[a][b] = mfma_lp<KIND>(ar[u][0][a], bl, acc[a][b]);
                 }
             }
 #pragma unroll
-            for (int a = 0; a < 2; ++a) acc[a][b] = mfma_lp<KIND>(af[0][a], bf, acc[a][b]);
+            for (int a = 0; a < 2; ++a) acc[a][b] = mfma_lp<KIND>(ar[u][0][a], bf, acc[a][b]);
         }
-        if (more) store_tile(buf ^ 1);
-        __syncthreads();
-        buf ^= 1;
+    };
+
+#pragma unroll
+    for (int s = 0; s < NBUF - 1; ++s) issue(s, kb0 + s);
+    int64_t j0 = 0;
+    for (; j0 + NBUF <= nst; j0 += NBUF) {
+#pragma unroll
+        for (int u = 0; u < NBUF; ++u) step(u, j0 + u);
     }
-    // accumulator element r of lane l holds C(4 (l / 16) + r, l % 16)
-    float* Cs = C + (int64_t)blockIdx.z * split_stride;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int u = 0; u < NBUF; ++u)
+        if (j0 + u < nst) step(u, j0 + u);
+    wait_vm<0>();                                     // no copy into LDS may outlive the workgroup
+
+    // accumulator element r of lane l holds C(4 (l / 16) + r, l % 16): one 16-byte store per tile
+    float* Cs = C + bz * split_stride;
+    const int64_t m0 = bx * LP_BM + wave * 32 + 4 * (lane >> 4), n0 = by * 16 * NB + (lane & 15);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t i = m0 + wave * 32 + a * 16 + 4 * (lane >> 4) + r;
-            if (i >= M) continue;
+    for (int a = 0; a < 2; ++a) {
+        const int64_t i = m0 + a * 16;
+        if (i >= mstore) continue;
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const int64_t j = n0 + b * 16 + fr;
-                if (j < N) Cs[i + j * ldc] = acc[a][b][r];
-            }
+        for (int b = 0; b < NB; ++b) {
+            const int64_t j = n0 + b * 16;
+            if (j < N) *(float4_t*)&Cs[i + j * ldc] = acc[a][b];
         }
+    }
 }
 
-// C = 2^(gexp + rexp[i]) sum_s W_s (M x N FP32 partials, fixed order; the
-// exponents only for the IEEE half form, else NULL), converted to TO, written
-// as C (M x N) or, transposed, as C^T (N x M) through 32 x 32 LDS tiles.
+// C = 2^(gexp + rexp[i]) sum_s W_s (M x N FP32 partials with leading dimension
+// ldw, fixed order; the exponents only for the IEEE half form, else NULL),
+// converted to TO, written as C (M x N) or, transposed, as C^T (N x M) through
+// 32 x 32 LDS tiles.  S = 0 writes zeros.
 template <typename TO, bool TRANS>
-__global__ __launch_bounds__(256) void lp_reduce_kernel(int64_t M, int64_t N, const float* __restrict__ W,
-                                                        int64_t split_stride, int S, TO* __restrict__ C,
-                                                        int64_t ldc, const int* __restrict__ rexp,
-                                                        const int* __restrict__ gexp) {
+__global__ __launch_bounds__(256) void lp_reduce_kernel(int64_t M, int64_t N, const float* __restrict__ W, int64_t ldw,
+                                                        int64_t split_stride, int S, TO* __restrict__ C, int64_t ldc,
+                                                        const int* __restrict__ rexp, const int* __restrict__ gexp) {
     __shared__ float tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
@@ -185,7 +219,7 @@ __global__ __launch_bounds__(256) void lp_reduce_kernel(int64_t M, int64_t N, co
         const int64_t i = i0 + tx, j = j0 + jj;
         float v0 = 0.f, v1 = 0.f;
         if (i < M && j < N) {
-            const float* w = W + i + j * M;
+            const float* w = W + i + j * ldw;
             int s = 0;
             for (; s + 1 < S; s += 2) {
                 v0 += w[s * split_stride];
@@ -208,113 +242,116 @@ __global__ __launch_bounds__(256) void lp_reduce_kernel(int64_t M, int64_t N, co
 
 // ---------------------------------------------------------------------------
 namespace {
-constexpr int LP_NBS[] = {1, 2, 3, 4, 6, 8, 9, 12, 17, 18};
+constexpr int LP_NBS[] = {1, 2, 4, 6, 9, 12, 17};
 
 struct LpPlan {
     int nb;
-    int64_t tm, tn, S, kchunk;
+    LpGrid g;
 };
 
 LpPlan plan_lp(int64_t M, int64_t N, int64_t K) {
     LpPlan p;
     const int64_t nblk = ceil_div(N, 16);
-    const int64_t ntiles = ceil_div(nblk, 18);
+    const int64_t ntiles = ceil_div(nblk, 17);
     const int64_t want_nb = ceil_div(nblk, ntiles);
-    p.nb = 18;
+    p.nb = 17;
     for (int v : LP_NBS)
         if (v >= want_nb) {
             p.nb = v;
             break;
         }
-    p.tm = ceil_div(M, LP_BM);
-    p.tn = ceil_div(N, 16 * p.nb);
+    LpGrid& g = p.g;
+    g.tm = ceil_div(M, LP_BM);
+    g.tn = ceil_div(N, 16 * p.nb);
+    const int64_t nkb = ceil_div(K, 32);
     const int cus = device_info().num_cus > 0 ? device_info().num_cus : 256;
-    int64_t S = ceil_div(4 * cus, p.tm * p.tn);
-    int64_t smax = ceil_div(K, 512);
-    // keep the partial-sum traffic S M N below a quarter of the operand traffic K (M + N)
+    // about two workgroups per CU (one resident at a time), at least 16 K blocks per split,
+    // and the partial-sum traffic S M N below a quarter of the operand traffic K (M + N)
+    int64_t S = ceil_div(2 * cus, g.tm * g.tn);
+    int64_t smax = ceil_div(nkb, 16);
     const int64_t straffic = (K * (M + N)) / (4 * M * N);
     if (smax > straffic) smax = straffic > 1 ? straffic : 1;
     if (S > smax) S = smax;
     if (S < 1) S = 1;
-    p.kchunk = K <= 0 ? LP_BK : ceil_div(ceil_div(K, S), LP_BK) * LP_BK;
-    p.S = K <= 0 ? 1 : ceil_div(K, p.kchunk);
+    g.kcb = nkb > 0 ? ceil_div(nkb, S) : 1;
+    g.S = nkb > 0 ? ceil_div(nkb, g.kcb) : 1;
+    g.T = g.tm * g.tn * g.S;
+    g.per_xcd = ceil_div(g.T, 8);
     return p;
 }
 
-template <int KIND, int NB, bool X3>
-void launch_lp(const LpPlan& p, int64_t M, int64_t N, int64_t K, const unsigned short* P, const unsigned short* Plo,
-               int64_t ldp, const unsigned short* Q, const unsigned short* Qlo, int64_t ldq, float* C, int64_t ldc,
-               int64_t ss, hipStream_t s) {
-    auto al16 = [](const void* q) { return q == nullptr || (((uintptr_t)q) & 15) == 0; };
-    const bool vec = (K % 8 == 0) && (ldp % 8 == 0) && (ldq % 8 == 0) && al16(P) && al16(Plo) && al16(Q) && al16(Qlo);
-    const dim3 grid((unsigned)p.tm, (unsigned)p.tn, (unsigned)p.S);
-    if (vec)
-        hipLaunchKernelGGL((gemm_lp_kernel<KIND, NB, X3, true>), grid, dim3(LP_THREADS), 0, s, M, N, K, P, Plo, ldp, Q,
-                           Qlo, ldq, C, ldc, ss, p.kchunk);
-    else
-        hipLaunchKernelGGL((gemm_lp_kernel<KIND, NB, X3, false>), grid, dim3(LP_THREADS), 0, s, M, N, K, P, Plo, ldp,
-                           Q, Qlo, ldq, C, ldc, ss, p.kchunk);
-}
-
 template <int KIND, bool X3>
-void dispatch_lp(const LpPlan& p, int64_t M, int64_t N, int64_t K, const unsigned short* P,
-                 const unsigned short* Plo, int64_t ldp, const unsigned short* Q, const unsigned short* Qlo,
-                 int64_t ldq, float* C, int64_t ldc, int64_t ss, hipStream_t s) {
+void dispatch_lp(const LpPlan& p, int64_t M, int64_t N, int64_t nkb, const unsigned short* P,
+                 const unsigned short* Plo, const unsigned short* Q, const unsigned short* Qlo, float* C, int64_t ldc,
+                 int64_t mstore, int64_t ss, hipStream_t s) {
+    const dim3 grid((unsigned)(8 * p.g.per_xcd));
     switch (p.nb) {
-#define RQLP_LP_CASE(X)                                                                                      \
-    case X:                                                                                                  \
-        launch_lp<KIND, X, X3>(p, M, N, K, P, Plo, ldp, Q, Qlo, ldq, C, ldc, ss, s);                        \
+#define RQLP_LP_CASE(X)                                                                                         \
+    case X:                                                                                                     \
+        hipLaunchKernelGGL((gemm_lp_kernel<KIND, X, X3>), grid, dim3(LP_THREADS), 0, s, M, N, nkb, P, Plo, Q, Qlo, \
+                           C, ldc, mstore, ss, p.g);                                                            \
         break;
-        RQLP_LP_CASE(1) RQLP_LP_CASE(2) RQLP_LP_CASE(3) RQLP_LP_CASE(4) RQLP_LP_CASE(6)
-        RQLP_LP_CASE(8) RQLP_LP_CASE(9) RQLP_LP_CASE(12) RQLP_LP_CASE(17) RQLP_LP_CASE(18)
+        RQLP_LP_CASE(1) RQLP_LP_CASE(2) RQLP_LP_CASE(4) RQLP_LP_CASE(6) RQLP_LP_CASE(9) RQLP_LP_CASE(12)
+        RQLP_LP_CASE(17)
 #undef RQLP_LP_CASE
         default: break;
     }
 }
 }  // namespace
 
+size_t lp_tiled_elems(int64_t rows, int64_t K) {
+    if (rows <= 0 || K <= 0) return 0;
+    return (size_t)(ceil_div(rows, 16) * 16) * (size_t)(ceil_div(K, 32) * 32);
+}
+
 size_t gemm_lp_workspace_elems(int64_t M, int64_t N, int64_t K) {
     LpPlan p = plan_lp(M, N, K);
-    return (size_t)(p.S * M * N);
+    return (size_t)(p.g.S * ceil_div(M, 16) * 16 * N);
 }
 
 template <typename TO>
 int gemm_lp(int kind, int64_t M, int64_t N, int64_t K, const unsigned short* P, const unsigned short* Plo,
-            int64_t ldp, const unsigned short* Q, const unsigned short* Qlo, int64_t ldq, TO* C, int64_t ldc,
-            bool trans_out, const int* rexp, const int* gexp, float* ws, size_t ws_elems, hipStream_t s) {
+            const unsigned short* Q, const unsigned short* Qlo, TO* C, int64_t ldc, bool trans_out, const int* rexp,
+            const int* gexp, float* ws, size_t ws_elems, hipStream_t s) {
     if (M <= 0 || N <= 0) return 0;
     const bool x3 = (Plo != nullptr && Qlo != nullptr);
     if (x3 != (kind == RQLP_MIXED_BF16X3)) return RQLP_E_UNSUPPORTED;
+    const dim3 rgrid((unsigned)ceil_div(M, 32), (unsigned)ceil_div(N, 32));
+    auto reduce = [&](const float* W, int64_t ldw, int S) {
+        if (trans_out)
+            hipLaunchKernelGGL((lp_reduce_kernel<TO, true>), rgrid, dim3(256), 0, s, M, N, W, ldw, ldw * N, S, C, ldc,
+                               rexp, gexp);
+        else
+            hipLaunchKernelGGL((lp_reduce_kernel<TO, false>), rgrid, dim3(256), 0, s, M, N, W, ldw, ldw * N, S, C, ldc,
+                               rexp, gexp);
+        return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
+    };
+    if (K <= 0) return reduce(nullptr, M, 0);          // empty sum: zeros
     LpPlan p = plan_lp(M, N, K);
+    const int64_t Mp = ceil_div(M, 16) * 16;
     const bool scaled = rexp != nullptr || gexp != nullptr;
-    const bool direct = (p.S == 1 && !trans_out && !scaled && sizeof(TO) == sizeof(float));
+    const bool direct = p.g.S == 1 && !trans_out && !scaled && sizeof(TO) == sizeof(float) && M % 4 == 0 &&
+                        ldc % 4 == 0 && (((uintptr_t)C) & 15) == 0;
     float* dst = direct ? (float*)C : ws;
-    const int64_t ld = direct ? ldc : M;
-    if (!direct && ((size_t)(p.S * M * N) > ws_elems || ws == nullptr)) return RQLP_E_WORKSPACE;
+    const int64_t ld = direct ? ldc : Mp;
+    if (!direct && ((size_t)(p.g.S * Mp * N) > ws_elems || ws == nullptr)) return RQLP_E_WORKSPACE;
+    const int64_t nkb = ceil_div(K, 32), mstore = direct ? M : Mp;
     if (kind == RQLP_MIXED_FP16)
-        dispatch_lp<RQLP_MIXED_FP16, false>(p, M, N, K, P, Plo, ldp, Q, Qlo, ldq, dst, ld, M * N, s);
+        dispatch_lp<RQLP_MIXED_FP16, false>(p, M, N, nkb, P, Plo, Q, Qlo, dst, ld, mstore, Mp * N, s);
     else if (x3)
-        dispatch_lp<RQLP_MIXED_BF16, true>(p, M, N, K, P, Plo, ldp, Q, Qlo, ldq, dst, ld, M * N, s);
+        dispatch_lp<RQLP_MIXED_BF16, true>(p, M, N, nkb, P, Plo, Q, Qlo, dst, ld, mstore, Mp * N, s);
     else
-        dispatch_lp<RQLP_MIXED_BF16, false>(p, M, N, K, P, Plo, ldp, Q, Qlo, ldq, dst, ld, M * N, s);
+        dispatch_lp<RQLP_MIXED_BF16, false>(p, M, N, nkb, P, Plo, Q, Qlo, dst, ld, mstore, Mp * N, s);
     if (hipGetLastError() != hipSuccess) return RQLP_E_HIP;
-    if (direct) return 0;
-    dim3 grid((unsigned)ceil_div(M, 32), (unsigned)ceil_div(N, 32));
-    if (trans_out)
-        hipLaunchKernelGGL((lp_reduce_kernel<TO, true>), grid, dim3(256), 0, s, M, N, ws, M * N, (int)p.S, C, ldc, rexp,
-                           gexp);
-    else
-        hipLaunchKernelGGL((lp_reduce_kernel<TO, false>), grid, dim3(256), 0, s, M, N, ws, M * N, (int)p.S, C, ldc,
-                           rexp, gexp);
-    return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
+    return direct ? 0 : reduce(ws, Mp, (int)p.g.S);
 }
 
-template int gemm_lp<float>(int, int64_t, int64_t, int64_t, const unsigned short*, const unsigned short*, int64_t,
-                            const unsigned short*, const unsigned short*, int64_t, float*, int64_t, bool, const int*,
+template int gemm_lp<float>(int, int64_t, int64_t, int64_t, const unsigned short*, const unsigned short*,
+                            const unsigned short*, const unsigned short*, float*, int64_t, bool, const int*,
                             const int*, float*, size_t, hipStream_t);
-template int gemm_lp<double>(int, int64_t, int64_t, int64_t, const unsigned short*, const unsigned short*, int64_t,
-                             const unsigned short*, const unsigned short*, int64_t, double*, int64_t, bool,
-                             const int*, const int*, float*, size_t, hipStream_t);
+template int gemm_lp<double>(int, int64_t, int64_t, int64_t, const unsigned short*, const unsigned short*,
+                             const unsigned short*, const unsigned short*, double*, int64_t, bool, const int*,
+                             const int*, float*, size_t, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // FP32 -> 16-bit conversions, round to nearest even.
@@ -328,144 +365,162 @@ __device__ __forceinline__ float bf16_bits_to_f32(unsigned short h) { return __u
 __device__ __forceinline__ unsigned short f32_to_f16_bits(float x) {
     return __builtin_bit_cast(unsigned short, (_Float16)x);
 }
-
-// dst (16-bit) = 2^(rexp[i] - cexp[j] - gexp) src(i, j) for the rows x cols
-// FP32 matrix src (absent exponents count as 0); with transpose the
-// destination holds the cols x rows matrix src^T.  dlo (bf16x3 only) gets
-// the rounded remainder x - hi.  32 x 32 tiles through LDS.
-__global__ __launch_bounds__(256) void cast_lp_kernel(int64_t rows, int64_t cols, const float* __restrict__ src,
-                                                      int64_t lds_, unsigned short* __restrict__ dst,
-                                                      unsigned short* __restrict__ dlo, int64_t ldd, int kind,
-                                                      int transpose, const int* __restrict__ rexp,
-                                                      const int* __restrict__ cexp, const int* __restrict__ gexp) {
-    __shared__ unsigned short t[2][32][34];
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
-    const int g = gexp ? *gexp : 0;
-    for (int jj = ty; jj < 32; jj += 8) {
-        const int64_t i = i0 + tx, j = j0 + jj;
-        unsigned short v = 0, vl = 0;
-        if (i < rows && j < cols) {
-            float x = src[i + j * lds_];
-            const int e = (rexp ? rexp[i] : 0) - (cexp ? cexp[j] : 0) - g;
-            if (e) x = ldexpf(x, e);
-            if (kind == RQLP_MIXED_FP16) {
-                v = f32_to_f16_bits(x);
-            } else {
-                v = f32_to_bf16_bits(x);
-                if (dlo) vl = f32_to_bf16_bits(x - bf16_bits_to_f32(v));
-            }
-            if (!transpose) {
-                dst[i + j * ldd] = v;
-                if (dlo) dlo[i + j * ldd] = vl;
-            }
-        }
-        t[0][jj][tx] = v;
-        t[1][jj][tx] = vl;
-    }
-    if (!transpose) return;
-    __syncthreads();
-    for (int ii = ty; ii < 32; ii += 8) {
-        const int64_t j = j0 + tx, i = i0 + ii;
-        if (i < rows && j < cols) {
-            dst[j + i * ldd] = t[0][tx][ii];
-            if (dlo) dlo[j + i * ldd] = t[1][tx][ii];
-        }
+// x -> (hi, lo) 16-bit patterns for `kind` (lo only for the split form)
+__device__ __forceinline__ void encode16(int kind, bool split, float x, unsigned short& hi, unsigned short& lo) {
+    if (kind == RQLP_MIXED_FP16) {
+        hi = f32_to_f16_bits(x);
+        lo = 0;
+    } else {
+        hi = f32_to_bf16_bits(x);
+        lo = split ? f32_to_bf16_bits(x - bf16_bits_to_f32(hi)) : (unsigned short)0;
     }
 }
 
-// Both 16-bit layouts of the m x n FP32 matrix A in one pass over A:
-// Ac (m x n, column-major, ldc) and Ar (= A^T, n x m, ldr), with the bf16x3
-// remainders (Aclo / Arlo) and the FP16 column exponents (cexp) as in
-// cast_lp_kernel.  64 x 64 tiles: 16-byte reads of A, 8-byte writes of Ac,
-// the transpose through LDS and 16-byte writes of Ar.  Needs m, lda, ldc
-// multiples of 4, ldr a multiple of 8 and 16-byte aligned bases.
-__global__ __launch_bounds__(256) void encode_both_kernel(int64_t m, int64_t n, const float* __restrict__ A,
-                                                          int64_t lda, unsigned short* __restrict__ Ac,
-                                                          unsigned short* __restrict__ Aclo, int64_t ldc,
-                                                          unsigned short* __restrict__ Ar,
-                                                          unsigned short* __restrict__ Arlo, int64_t ldr, int kind,
-                                                          const int* __restrict__ cexp) {
+// Fragment-tiled 16-bit copies of the m x n FP32 matrix A in one pass over A:
+//   Tc: X = A^T (rows = columns of A, k = row index; the operand of A^T V),
+//   Tr: X = A   (rows = rows of A,    k = column index; the operand of A W),
+// each optional, with the split remainders (Tclo / Trlo, bf16x3) and the FP16
+// column scaling 2^-cexp[j].  64 x 64 tiles of A through LDS; vec: 16-byte
+// reads allowed (lda % 4 == 0, A 16-byte aligned).
+__global__ __launch_bounds__(256) void encode_tiled_kernel(int64_t m, int64_t n, const float* __restrict__ A,
+                                                           int64_t lda, int vec, unsigned short* __restrict__ Tc,
+                                                           unsigned short* __restrict__ Tclo,
+                                                           unsigned short* __restrict__ Tr,
+                                                           unsigned short* __restrict__ Trlo, int kind,
+                                                           const int* __restrict__ cexp) {
     typedef unsigned short u16x4_t __attribute__((ext_vector_type(4)));
-    __shared__ __attribute__((aligned(16))) unsigned short t[2][64][64 + 8];   // [part][column][row]
+    __shared__ __attribute__((aligned(16))) unsigned short t[2][64][64 + 8];   // [part][column j][row i]
     const int tid = threadIdx.x;
     const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
-    const bool split = Aclo != nullptr;
+    const bool split = Tclo != nullptr || Trlo != nullptr;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int idx = tid + 256 * e;
         const int cj = idx >> 4, ri = (idx & 15) * 4;
         const int64_t i = i0 + ri, j = j0 + cj;
-        u16x4_t v = {0, 0, 0, 0}, vl = {0, 0, 0, 0};
-        if (j < n && i < m) {
-            const float4_t x = *(const float4_t*)(A + i + j * lda);     // m % 4 == 0: whole chunk inside
-            const int ex = cexp ? -cexp[j] : 0;
+        float x[4] = {0.f, 0.f, 0.f, 0.f};
+        if (j < n) {
+            const float* a = A + i + j * lda;
+            if (vec && i + 3 < m) {
+                const float4_t v = *(const float4_t*)a;
+                x[0] = v[0]; x[1] = v[1]; x[2] = v[2]; x[3] = v[3];
+            } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float y = ex ? ldexpf(x[q], ex) : x[q];
-                if (kind == RQLP_MIXED_FP16) {
-                    v[q] = f32_to_f16_bits(y);
-                } else {
-                    v[q] = f32_to_bf16_bits(y);
-                    if (split) vl[q] = f32_to_bf16_bits(y - bf16_bits_to_f32(v[q]));
-                }
+                for (int q = 0; q < 4; ++q)
+                    if (i + q < m) x[q] = a[q];
             }
-            *(u16x4_t*)(Ac + i + j * ldc) = v;
-            if (split) *(u16x4_t*)(Aclo + i + j * ldc) = vl;
         }
-        *(u16x4_t*)&t[0][cj][ri] = v;
-        *(u16x4_t*)&t[1][cj][ri] = vl;
+        const int ex = (cexp && j < n) ? -cexp[j] : 0;
+        u16x4_t hv, lv;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float y = ex ? ldexpf(x[q], ex) : x[q];
+            unsigned short h, l;
+            encode16(kind, split, y, h, l);
+            hv[q] = h;
+            lv[q] = l;
+        }
+        *(u16x4_t*)&t[0][cj][ri] = hv;
+        *(u16x4_t*)&t[1][cj][ri] = lv;
     }
     __syncthreads();
+    // Tc blocks in this tile: 4 column groups (rows of X) x 2 row groups of 32 (k)
+    if (Tc) {
+        const int64_t nkb = (m + 31) >> 5, nrb = (n + 15) >> 4;
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const int idx = tid + 256 * e;
-        const int ri = idx >> 3, cc = (idx & 7) * 8;
-        const int64_t i = i0 + ri, j = j0 + cc;
-        if (i >= m || j >= n) continue;
+        for (int e = 0; e < 2; ++e) {
+            const int idx = tid + 256 * e, blk = idx >> 6, ln = idx & 63;
+            const int jb = blk & 3, ib = blk >> 2;
+            const int64_t rb = (j0 >> 4) + jb, kb = (i0 >> 5) + ib;
+            if (rb >= nrb || kb >= nkb) continue;
+            const int jl = jb * 16 + (ln & 15), il = ib * 32 + 8 * (ln >> 4);
+            const int64_t o = (rb * nkb + kb) * LP_BLK + ln * 8;
+            *(u16x8_t*)(Tc + o) = *(const u16x8_t*)&t[0][jl][il];
+            if (Tclo) *(u16x8_t*)(Tclo + o) = *(const u16x8_t*)&t[1][jl][il];
+        }
+    }
+    // Tr blocks: 4 row groups of 16 (rows of X) x 2 column groups of 32 (k)
+    if (Tr) {
+        const int64_t nkb = (n + 31) >> 5, nrb = (m + 15) >> 4;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            unsigned short* D = h ? Arlo : Ar;
-            if (!D) continue;
-            u16x8_t v;
+        for (int e = 0; e < 2; ++e) {
+            const int idx = tid + 256 * e, blk = idx >> 6, ln = idx & 63;
+            const int ib = blk & 3, jb = blk >> 2;
+            const int64_t rb = (i0 >> 4) + ib, kb = (j0 >> 5) + jb;
+            if (rb >= nrb || kb >= nkb) continue;
+            const int il = ib * 16 + (ln & 15), jl = jb * 32 + 8 * (ln >> 4);
+            const int64_t o = (rb * nkb + kb) * LP_BLK + ln * 8;
+            u16x8_t v, vl;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) v[q] = t[h][cc + q][ri];
-            if (j + 8 <= n) {
-                *(u16x8_t*)(D + j + i * ldr) = v;
-            } else {
-                for (int q = 0; q < 8; ++q)
-                    if (j + q < n) D[j + q + i * ldr] = v[q];
+            for (int q = 0; q < 8; ++q) {
+                v[q] = t[0][jl + q][il];
+                vl[q] = t[1][jl + q][il];
             }
+            *(u16x8_t*)(Tr + o) = v;
+            if (Trlo) *(u16x8_t*)(Trlo + o) = vl;
         }
     }
 }
 
-int encode_both(int kind, int64_t m, int64_t n, const float* A, int64_t lda, unsigned short* Ac, unsigned short* Aclo,
-                int64_t ldc, unsigned short* Ar, unsigned short* Arlo, int64_t ldr, const int* cexp, hipStream_t s) {
+int encode_tiled(int kind, int64_t m, int64_t n, const float* A, int64_t lda, unsigned short* Tc,
+                 unsigned short* Tclo, unsigned short* Tr, unsigned short* Trlo, const int* cexp, hipStream_t s) {
     if (m <= 0 || n <= 0) return 0;
-    if ((kind == RQLP_MIXED_BF16X3) != (Aclo != nullptr) || (Aclo != nullptr) != (Arlo != nullptr))
-        return RQLP_E_UNSUPPORTED;
-    auto al16 = [](const void* q) { return q == nullptr || (((uintptr_t)q) & 15) == 0; };
-    const bool fast = m % 4 == 0 && lda % 4 == 0 && ldc % 4 == 0 && ldr % 8 == 0 && al16(A) && al16(Ac) &&
-                      al16(Aclo) && al16(Ar) && al16(Arlo);
-    if (!fast) {
-        RQLP_TRY(cast_to_lp(kind, m, n, A, lda, Ac, Aclo, ldc, false, nullptr, cexp, nullptr, s));
-        return cast_to_lp(kind, m, n, A, lda, Ar, Arlo, ldr, true, nullptr, cexp, nullptr, s);
-    }
-    dim3 grid((unsigned)ceil_div(m, 64), (unsigned)ceil_div(n, 64));
-    hipLaunchKernelGGL(encode_both_kernel, grid, dim3(256), 0, s, m, n, A, lda, Ac, Aclo, ldc, Ar, Arlo, ldr, kind,
-                       cexp);
+    const bool x3 = kind == RQLP_MIXED_BF16X3;
+    if ((Tc && x3 != (Tclo != nullptr)) || (Tr && x3 != (Trlo != nullptr))) return RQLP_E_UNSUPPORTED;
+    const int vec = (lda % 4 == 0) && ((((uintptr_t)A) & 15) == 0);
+    const dim3 grid((unsigned)ceil_div(m, 64), (unsigned)ceil_div(n, 64));
+    hipLaunchKernelGGL(encode_tiled_kernel, grid, dim3(256), 0, s, m, n, A, lda, vec, Tc, Tc ? Tclo : nullptr, Tr,
+                       Tr ? Trlo : nullptr, kind, cexp);
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 
-int cast_to_lp(int kind, int64_t rows, int64_t cols, const float* src, int64_t lds_, unsigned short* dst,
-               unsigned short* dlo, int64_t ldd, bool transpose, const int* rexp, const int* cexp, const int* gexp,
-               hipStream_t s) {
-    if (rows <= 0 || cols <= 0) return 0;
+// Fragment-tiled 16-bit copy of a panel operand X (R x K) with
+// X(r, k) = 2^(kexp[k] - gexp) src(k + r ld) (src: column r of a K x R FP32
+// panel; absent exponents count as 0); dlo: split remainders.  One thread per
+// 16-byte chunk (8 consecutive k of one row).
+__global__ __launch_bounds__(256) void cast_panel_kernel(int64_t R, int64_t K, const float* __restrict__ src,
+                                                         int64_t ld, unsigned short* __restrict__ dst,
+                                                         unsigned short* __restrict__ dlo, int kind,
+                                                         const int* __restrict__ kexp,
+                                                         const int* __restrict__ gexp) {
+    const int64_t nkb = (K + 31) >> 5, nrb = (R + 15) >> 4;
+    const int64_t chunks = nrb * nkb * 64;
+    const int g = gexp ? *gexp : 0;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < chunks; idx += (int64_t)gridDim.x * 256) {
+        const int64_t blk = idx >> 6;
+        const int ln = (int)(idx & 63);
+        const int64_t rb = blk / nkb, kb = blk - rb * nkb;
+        const int64_t r = rb * 16 + (ln & 15), k0 = kb * 32 + 8 * (ln >> 4);
+        u16x8_t v = {0, 0, 0, 0, 0, 0, 0, 0}, vl = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (r < R) {
+            const float* p = src + r * ld;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t k = k0 + q;
+                if (k < K) {
+                    float x = p[k];
+                    const int e = (kexp ? kexp[k] : 0) - g;
+                    if (e) x = ldexpf(x, e);
+                    unsigned short h, l;
+                    encode16(kind, dlo != nullptr, x, h, l);
+                    v[q] = h;
+                    vl[q] = l;
+                }
+            }
+        }
+        *(u16x8_t*)(dst + blk * LP_BLK + ln * 8) = v;
+        if (dlo) *(u16x8_t*)(dlo + blk * LP_BLK + ln * 8) = vl;
+    }
+}
+
+int cast_panel(int kind, int64_t R, int64_t K, const float* src, int64_t ld, unsigned short* dst, unsigned short* dlo,
+               const int* kexp, const int* gexp, hipStream_t s) {
+    if (R <= 0 || K <= 0) return 0;
     if ((kind == RQLP_MIXED_BF16X3) != (dlo != nullptr)) return RQLP_E_UNSUPPORTED;
-    dim3 grid((unsigned)ceil_div(rows, 32), (unsigned)ceil_div(cols, 32));
-    hipLaunchKernelGGL(cast_lp_kernel, grid, dim3(256), 0, s, rows, cols, src, lds_, dst, dlo, ldd, kind,
-                       transpose ? 1 : 0, rexp, cexp, gexp);
+    int64_t blocks = ceil_div(ceil_div(R, 16) * ceil_div(K, 32) * 64, 256);
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(cast_panel_kernel, dim3((unsigned)blocks), dim3(256), 0, s, R, K, src, ld, dst, dlo, kind,
+                       kexp, gexp);
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 

@@ -26,24 +26,29 @@ int gemm_f32_acc64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const floa
                    size_t ws_elems, hipStream_t s, const int32_t* gate = nullptr, int gate_mode = 0);
 
 // --- gemm_lp.hip ------------------------------------------------------------
-// C(i, j) = 2^(gexp + rexp[i]) sum_k P(k + i ldp) Q(k + j ldq) with 16-bit
-// operands (bfloat16 or IEEE half per kind) and FP32 accumulation; M x N
-// output C (or its transpose when trans_out) of type TO.  Plo / Qlo: the lo
-// parts of split bfloat16 operands (kind RQLP_MIXED_BF16X3 only, else NULL).
+// 16-bit operands are "fragment tiled": an R x K operand X is stored as
+// ceil(R / 16) x ceil(K / 32) blocks of 512 elements, block (rb, kb) at
+// (rb * ceil(K / 32) + kb) * 512, holding X(16 rb + t % 16, 32 kb + 8 (t / 16) + e)
+// at 8 t + e (t < 64, e < 8); entries outside X are zero.
+size_t lp_tiled_elems(int64_t rows, int64_t K);
+// C(i, j) = 2^(gexp + rexp[i]) sum_k X(i, k) Y(j, k) with X (M x K, tiled P /
+// lo part Plo) and Y (N x K, tiled Q / Qlo) 16-bit (bfloat16 or IEEE half per
+// kind) and FP32 accumulation; M x N output C (or its transpose when
+// trans_out) of type TO.  Plo / Qlo: split bfloat16 only, else NULL.
 // rexp / gexp may be NULL (no scaling).  ws: gemm_lp_workspace_elems floats.
 size_t gemm_lp_workspace_elems(int64_t M, int64_t N, int64_t K);
 template <typename TO>
 int gemm_lp(int kind, int64_t M, int64_t N, int64_t K, const unsigned short* P, const unsigned short* Plo,
-            int64_t ldp, const unsigned short* Q, const unsigned short* Qlo, int64_t ldq, TO* C, int64_t ldc,
-            bool trans_out, const int* rexp, const int* gexp, float* ws, size_t ws_elems, hipStream_t s);
-// dst = 16-bit 2^(rexp[i] - cexp[j] - gexp) src(i, j) (src^T when transpose);
-// dlo: the rounded remainder (bf16x3 only).
-int cast_to_lp(int kind, int64_t rows, int64_t cols, const float* src, int64_t lds, unsigned short* dst,
-               unsigned short* dlo, int64_t ldd, bool transpose, const int* rexp, const int* cexp, const int* gexp,
-               hipStream_t s);
-// both 16-bit layouts of A (column-major Ac and A^T in Ar) in one pass
-int encode_both(int kind, int64_t m, int64_t n, const float* A, int64_t lda, unsigned short* Ac, unsigned short* Aclo,
-                int64_t ldc, unsigned short* Ar, unsigned short* Arlo, int64_t ldr, const int* cexp, hipStream_t s);
+            const unsigned short* Q, const unsigned short* Qlo, TO* C, int64_t ldc, bool trans_out, const int* rexp,
+            const int* gexp, float* ws, size_t ws_elems, hipStream_t s);
+// Tiled 16-bit copies of the FP32 matrix A (m x n) in one pass: Tc = A^T
+// (n x m operand), Tr = A (m x n operand), either may be NULL; lo parts for
+// the split form; FP16 columns scaled by 2^-cexp[j].
+int encode_tiled(int kind, int64_t m, int64_t n, const float* A, int64_t lda, unsigned short* Tc,
+                 unsigned short* Tclo, unsigned short* Tr, unsigned short* Trlo, const int* cexp, hipStream_t s);
+// Tiled 16-bit copy of the panel operand X (R x K), X(r, k) = 2^(kexp[k] - gexp) src[k + r ld].
+int cast_panel(int kind, int64_t R, int64_t K, const float* src, int64_t ld, unsigned short* dst, unsigned short* dlo,
+               const int* kexp, const int* gexp, hipStream_t s);
 // per-column power-of-two exponents of an FP32 matrix for IEEE half storage
 int column_exponents(int64_t rows, int64_t cols, const float* A, int64_t lda, int* colexp, int* gexp,
                      hipStream_t s);

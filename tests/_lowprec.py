@@ -27,6 +27,32 @@ def split_bf16(x):
     return hi, lo
 
 
+def untile(flat, R, K):
+    """Decode a fragment-tiled 16-bit operand (R x K; 16 x 32 blocks of 512
+    entries, block (rb, kb) at (rb * nkb + kb) * 512, lane t = 16 g + r holding
+    X(16 rb + r, 32 kb + 8 g + e) at 8 t + e) into (X, padding)."""
+    nrb, nkb = -(-R // 16), -(-K // 32)
+    b = np.asarray(flat).reshape(nrb, nkb, 4, 16, 8)            # (rb, kb, g, r, e)
+    full = b.transpose(0, 3, 1, 2, 4).reshape(nrb * 16, nkb * 32)
+    pad = np.concatenate([full[R:, :].ravel(), full[:R, K:].ravel()])
+    return full[:R, :K], pad
+
+
+def bits16(x, kind, e=None):
+    """uint16 patterns of the 16-bit encoding of the FP32 matrix x (hi, lo):
+    bf16 / split bf16 round to nearest even, fp16 after the column scaling 2^-e_j."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    if kind == "fp16":
+        y = (x.astype(np.float64) * np.exp2(-np.asarray(e, dtype=np.float64))[None, :]).astype(np.float32)
+        return y.astype(np.float16).view(np.uint16), None
+    hi = (bf16(x).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    if kind != "bf16x3":
+        return hi, None
+    r = (x.astype(np.float64) - bf16(x)).astype(np.float32)
+    lo = (bf16(r).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    return hi, lo
+
+
 def column_exponents(A):
     """e_j with max_i |A(i, j)| 2^-e_j in [2^14, 2^15); 0 for a zero column."""
     mx = np.abs(np.asarray(A, dtype=np.float64)).max(axis=0)

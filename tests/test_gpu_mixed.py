@@ -155,28 +155,39 @@ def test_mixed_library_omega_and_determinism(gpu):
 
 
 @pytest.mark.parametrize("kind", KINDS)
-def test_encoded_projection_equals_one_shot_projection(gpu, kind):
-    """rqlp_encode + rqlp_project_encoded give bitwise the same B as
-    rqlp_project (same encoding, same product, same reduction order); the
-    transposed encoding holds exactly A^T of the column-major one."""
+def test_encoding_layout_and_encoded_products(gpu, kind):
+    """rqlp_encode writes exactly the documented fragment tiles of the rounded
+    A (both forms, zero padding, ragged sizes), and the products on the
+    encoded A give bitwise the same results as rqlp_project / rqlp_sketch."""
     import torch
+    from _lowprec import bits16, column_exponents, untile
     rng = np.random.default_rng(11)
     m, n, c = 3001, 1003, 136
     A = (rng.standard_normal((m, n)) * 1e-3).astype(np.float32)
     V = rng.standard_normal((m, c)).astype(np.float32)
-    Ad, Vd = to_dev(A, torch.float32), to_dev(V, torch.float32)
-    E = gpu.encode(Ad, kind)
-    Et = gpu.encode(Ad, kind, transpose=True)
-    assert np.array_equal(to_np(E.hi), to_np(Et.hi).T)
-    if E.lo is not None:
-        assert np.array_equal(to_np(E.lo), to_np(Et.lo).T)
-    if E.colexp is not None:
-        from _lowprec import column_exponents
-        assert np.array_equal(to_np(E.colexp), column_exponents(A))
-        assert int(to_np(E.gexp)[0]) == int(column_exponents(A).max())
-    B1 = to_np(gpu.project_encoded(E, Vd))
+    X = rng.standard_normal((n, c)).astype(np.float32)
+    Ad, Vd, Xd = to_dev(A, torch.float32), to_dev(V, torch.float32), to_dev(X, torch.float32)
+    Ec = gpu.encode(Ad, kind, form="cols")
+    Er = gpu.encode(Ad, kind, form="rows")
+    e = column_exponents(A) if kind == "fp16" else None
+    if kind == "fp16":
+        assert np.array_equal(to_np(Ec.colexp), e)
+        assert int(to_np(Ec.gexp)[0]) == int(e.max())
+    hi, lo = bits16(A, kind, e)
+    for E, R, K, ref_hi, ref_lo in [(Ec, n, m, hi.T, None if lo is None else lo.T), (Er, m, n, hi, lo)]:
+        got, pad = untile(to_np(E.hi).view(np.uint16), R, K)
+        assert np.array_equal(got, ref_hi)
+        assert not pad.any()
+        if ref_lo is not None:
+            got, pad = untile(to_np(E.lo).view(np.uint16), R, K)
+            assert np.array_equal(got, ref_lo)
+            assert not pad.any()
+    B1 = to_np(gpu.project_encoded(Ec, Vd))
     B2 = to_np(gpu.project(Ad, Vd, precision=kind))
     assert np.array_equal(B1, B2)
+    Y1 = to_np(gpu.sketch_encoded(Er, Xd))
+    Y2 = to_np(gpu.sketch(Ad, Xd, precision=kind))
+    assert np.array_equal(Y1, Y2)
 
 
 @pytest.mark.parametrize("m,n,k,p,q,d", [(1000, 500, 20, 5, 1, 0), (2048, 1024, 100, 12, 2, 2), (777, 333, 40, 8, 0, 1)])

@@ -86,21 +86,41 @@ def test_building_block_argument_checks(lib):
 
 
 def test_encode_argument_checks(lib):
-    # (A, lda, m, n, precision, transpose, Ahi, Alo, ldh, colexp, gexp, stream)
-    assert _lib.rqlp_encode(1, 9, 10, 5, 2, 0, 1, None, 10, None, None, None) == -2
-    assert _lib.rqlp_encode(1, 10, 10, 5, 0, 0, 1, None, 10, None, None, None) == -5     # not a mixed type
-    assert _lib.rqlp_encode(1, 10, 10, 5, 2, 1, 1, None, 4, None, None, None) == -9      # A^T needs ldh >= n
-    assert _lib.rqlp_encode(None, 10, 10, 5, 2, 0, 1, None, 10, None, None, None) == -1
-    assert _lib.rqlp_encode(1, 10, 10, 5, 2, 0, 1, 1, 10, None, None, None) == -8        # lo only for bf16x3
-    assert _lib.rqlp_encode(1, 10, 10, 5, 4, 0, 1, None, 10, None, None, None) == -8
-    assert _lib.rqlp_encode(1, 10, 10, 5, 3, 0, 1, None, 10, None, 1, None) == -10       # fp16 needs colexp
-    assert _lib.rqlp_encode(1, 10, 0, 5, 2, 0, None, None, 10, None, None, None) == 0    # empty: nothing to do
-    # (Ahi, Alo, ldh, colexp, m, n, V, ldv, c, B, ldb, precision, work, bytes, stream)
-    assert _lib.rqlp_project_encoded(1, None, 9, None, 10, 5, 1, 10, 3, 1, 3, 2, None, 0, None) == -3
-    assert _lib.rqlp_project_encoded(1, None, 10, None, 10, 5, 1, 10, 3, 1, 2, 2, None, 0, None) == -11
-    assert _lib.rqlp_project_encoded(1, None, 10, None, 10, 5, 1, 10, 3, 1, 3, 1, None, 0, None) == -12
-    assert _lib.rqlp_project_encoded(1, None, 10, None, 10, 5, 1, 10, 3, 1, 3, 3, None, 0, None) == -4
-    assert _lib.rqlp_project_encoded(1, None, 10, None, 10, 5, 1, 10, 3, 1, 3, 2, None, 0, None) == -1000
+    # (A, lda, m, n, precision, form, Ahi, Alo, colexp, gexp, stream)
+    assert _lib.rqlp_encode(1, 9, 10, 5, 2, 0, 1, None, None, None, None) == -2
+    assert _lib.rqlp_encode(1, 10, 10, 5, 0, 0, 1, None, None, None, None) == -5     # not a mixed type
+    assert _lib.rqlp_encode(1, 10, 10, 5, 2, 2, 1, None, None, None, None) == -6     # unknown form
+    assert _lib.rqlp_encode(None, 10, 10, 5, 2, 0, 1, None, None, None, None) == -1
+    assert _lib.rqlp_encode(1, 10, 10, 5, 2, 0, None, None, None, None, None) == -7
+    assert _lib.rqlp_encode(1, 10, 10, 5, 2, 0, 1, 1, None, None, None) == -8        # lo only for bf16x3
+    assert _lib.rqlp_encode(1, 10, 10, 5, 4, 1, 1, None, None, None, None) == -8
+    assert _lib.rqlp_encode(1, 10, 10, 5, 3, 0, 1, None, None, 1, None) == -9        # fp16 needs colexp
+    assert _lib.rqlp_encode(1, 10, 10, 5, 3, 0, 1, None, 1, None, None) == -10       # ... and gexp
+    assert _lib.rqlp_encode(1, 10, 0, 5, 2, 0, None, None, None, None, None) == 0    # empty: nothing to do
+    # (Ahi, Alo, colexp, gexp, m, n, V, ldv, c, B, ldb, precision, work, bytes, stream)
+    assert _lib.rqlp_project_encoded(1, None, None, None, 10, 5, 1, 9, 3, 1, 3, 2, None, 0, None) == -8
+    assert _lib.rqlp_project_encoded(1, None, None, None, 10, 5, 1, 10, 3, 1, 2, 2, None, 0, None) == -11
+    assert _lib.rqlp_project_encoded(1, None, None, None, 10, 5, 1, 10, 3, 1, 3, 1, None, 0, None) == -12
+    assert _lib.rqlp_project_encoded(1, None, None, None, 10, 5, 1, 10, 3, 1, 3, 3, None, 0, None) == -3
+    assert _lib.rqlp_project_encoded(1, 1, None, None, 10, 5, 1, 10, 3, 1, 3, 2, None, 0, None) == -2
+    assert _lib.rqlp_project_encoded(1, None, None, None, 10, 5, None, 10, 3, 1, 3, 2, None, 0, None) == -7
+    assert _lib.rqlp_project_encoded(1, None, None, None, 10, 5, 1, 10, 3, None, 3, 2, None, 0, None) == -10
+    assert _lib.rqlp_project_encoded(1, None, None, None, 10, 0, 1, 10, 3, None, 3, 2, None, 0, None) == 0
+    assert _lib.rqlp_project_encoded(1, None, None, None, 10, 5, 1, 10, 3, 1, 3, 2, None, 0, None) == -1000
+    # (Ahi, Alo, colexp, gexp, m, n, X, ldx, c, Y, ldy, precision, work, bytes, stream)
+    assert _lib.rqlp_sketch_encoded(1, None, None, None, 10, 5, 1, 4, 3, 1, 10, 2, None, 0, None) == -8
+    assert _lib.rqlp_sketch_encoded(1, None, None, None, 10, 5, 1, 5, 3, 1, 9, 2, None, 0, None) == -11
+    assert _lib.rqlp_sketch_encoded(1, None, 1, None, 10, 5, 1, 5, 3, 1, 10, 3, None, 0, None) == -4
+    assert _lib.rqlp_sketch_encoded(1, None, None, None, 10, 5, 1, 5, 3, 1, 10, 2, None, 0, None) == -1000
+
+
+def test_encoded_sizes(lib):
+    # whole 16 x 32 blocks: rows padded to 16, k to 32
+    assert _lib.rqlp_encoded_elems(100, 40, 0) == 48 * 128          # A^T: 40 rows, k = 100
+    assert _lib.rqlp_encoded_elems(100, 40, 1) == 112 * 64          # A: 100 rows, k = 40
+    assert _lib.rqlp_encoded_elems(0, 40, 1) == 0
+    with pytest.raises(rq.RQLPError):
+        _lib.rqlp_encoded_elems(10, 10, 5)
 
 
 def test_mixed_workspace_holds_the_16bit_copies(lib):
