@@ -132,6 +132,102 @@ __device__ __forceinline__ bool grid_sync_decide(unsigned* bar, int G, unsigned&
     return s_ok != 0;
 }
 
+// Pivot agreement of the register-resident kernel, with fewer dependent
+// round trips to memory than grid_sync_decide: the key maxima are issued
+// together with the candidate column (one completion wait for both), the
+// arrival counters grow monotonically (no resets), a group's last arriver only
+// forwards its arrival, and the very last arriver reads the maxima of all
+// groups (one thread per group slot), decides, and publishes the result with
+// the new generation.  Bounded waits as in grid_sync_decide.
+template <int GRP, typename F>
+__device__ __forceinline__ bool grid_agree(unsigned* bar, int G, unsigned& gen, unsigned& payload, int32_t* info,
+                                           unsigned long long spin_limit, unsigned long long* kslots,
+                                           unsigned long long lk0, unsigned long long lk1, F decide) {
+    __shared__ int s_last, s_ok;
+    __shared__ unsigned s_pay;
+    __shared__ unsigned long long s_m[2][CP_T / 64];
+    const int ng = (G + GRP - 1) / GRP;
+    const int grp = (int)blockIdx.x / GRP;
+    const unsigned gsz = (unsigned)((G - grp * GRP) < GRP ? (G - grp * GRP) : GRP);
+    unsigned* cnt = bar + 32 * grp;
+    unsigned* top = bar + 32 * ng;
+    unsigned long long* gw = (unsigned long long*)(bar + 32 * (ng + 1));
+    const unsigned g = gen;
+    if (threadIdx.x == 0 && kslots && lk0 != 0) {
+        atomicMax(kslots + 16 * grp, lk0);
+        atomicMax(kslots + 16 * grp + 1, lk1);
+    }
+    drain_and_sync();                                    // this workgroup's column stores and maxima are done
+    if (threadIdx.x == 0) {
+        int last = 0;
+        if (__hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gsz * (g + 1u) - 1u &&
+            __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)ng * (g + 1u) - 1u)
+            last = 1;
+        s_last = last;
+    }
+    __syncthreads();
+    if (s_last) {
+        unsigned long long m0 = 0, m1 = 0;
+        if (kslots) {
+            for (int h = threadIdx.x; h < ng; h += CP_T) {
+                const unsigned long long a = __hip_atomic_load(kslots + 16 * h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long c =
+                    __hip_atomic_load(kslots + 16 * h + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                m0 = a > m0 ? a : m0;
+                m1 = c > m1 ? c : m1;
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const unsigned long long a = shfl_xor_u64(m0, off), c = shfl_xor_u64(m1, off);
+                m0 = a > m0 ? a : m0;
+                m1 = c > m1 ? c : m1;
+            }
+            if ((threadIdx.x & 63) == 0) {
+                s_m[0][threadIdx.x >> 6] = m0;
+                s_m[1][threadIdx.x >> 6] = m1;
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (kslots) {
+                m0 = 0;
+                m1 = 0;
+                for (int w = 0; w < CP_T / 64; ++w) {
+                    m0 = s_m[0][w] > m0 ? s_m[0][w] : m0;
+                    m1 = s_m[1][w] > m1 ? s_m[1][w] : m1;
+                }
+            }
+            const unsigned pay = decide(m0, m1);
+            __hip_atomic_store(gw, ((unsigned long long)(g + 1u) << 32) | pay, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            s_pay = pay;
+            s_ok = 1;
+        }
+    } else if (threadIdx.x == 0) {
+        int ok = 1;
+        unsigned pay = 0;
+        unsigned long long spins = 0;
+        while (true) {
+            const unsigned long long w = __hip_atomic_load(gw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((unsigned)(w >> 32) != g) {
+                pay = (unsigned)w;
+                break;
+            }
+            if (++spins > spin_limit) {
+                ok = 0;
+                if (info) atomicOr(info, RQLP_INFO_BARRIER_TIMEOUT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        s_pay = pay;
+        s_ok = ok;
+    }
+    __syncthreads();
+    gen = g + 1u;
+    payload = s_pay;
+    return s_ok != 0;
+}
+
 template <bool SINGLE>
 __global__ __launch_bounds__(CP_T) void cpqr_kernel(
     const double* __restrict__ M, int64_t ldm, int rows, int cols, int cpw, int kmax, int ibits,
@@ -394,6 +490,303 @@ __global__ __launch_bounds__(CP_T) void cpqr_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// The same factorisation with the columns held in registers instead of LDS.
+// 64 columns per workgroup, 16 per wave; lane l of a wave owns the RPT
+// consecutive rows 16-group (l % 16) of the 4 columns 4 t + l / 16 (t < 4)
+// of its wave.  A step reads this lane's slice of the reflector v from LDS
+// once and reuses it for its 4 columns; the dot products and norms reduce
+// over the 16 lanes of a column with shuffles.  Pivot agreement, reflector
+// and bookkeeping are those of cpqr_kernel.
+// lane permutation of a double within DPP rows of 16 lanes
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+constexpr int CPR_RG = 16;                   // row groups (lanes per column)
+constexpr int CPR_CT = 4;                    // columns per lane
+constexpr int CPR_CPW = 64;                  // columns per workgroup
+#ifndef CPR_GROUP
+#define CPR_GROUP 16                         // workgroups per arrival counter
+#endif
+// scratch words of grid_agree<CPR_GROUP> (key slots per step, counters + generation)
+__host__ __device__ constexpr int cpr_key_words(int G) { return 16 * ((G + CPR_GROUP - 1) / CPR_GROUP + 1); }
+__host__ __device__ constexpr int cpr_bar_words(int G) { return 32 * ((G + CPR_GROUP - 1) / CPR_GROUP + 2); }
+
+template <int RPT>
+__global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
+    const double* __restrict__ M, int64_t ldm, int rows, int cols, int kmax, int ibits, unsigned long long* keys,
+    double* candcol, double* partial, unsigned* bar, int64_t* piv, double* Vh, int64_t ldv, double* beta_out,
+    double* Rpiv, int64_t ldr, double* Rt, int64_t ldrt, int32_t* info, unsigned long long spin_limit) {
+    __shared__ double v[CPR_RG * RPT];
+    __shared__ double cst[CPR_RG * RPT];             // staging of the published column
+    __shared__ double s_red[CP_T / 64];
+    __shared__ unsigned long long s_kred[2][CP_T / 64];
+    __shared__ unsigned long long s_key[2];
+    __shared__ double s_beta, s_mu, s_tol2;
+    __shared__ int s_stop, s_rank;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int G = gridDim.x, g = blockIdx.x;
+    const int c0 = g * CPR_CPW;
+    const int qd = lane % CPR_RG, cs = lane / CPR_RG;
+    const int r0 = qd * RPT;                             // first row held by this lane
+    int col[CPR_CT], act[CPR_CT];                        // act: -1 active, >= 0 pivot step, -2 no column
+    unsigned gen = 0;
+
+    double x[CPR_CT][RPT];
+#pragma unroll
+    for (int t = 0; t < CPR_CT; ++t) {
+        col[t] = c0 + 16 * wave + 4 * t + cs;
+        const bool have = col[t] < cols;
+        act[t] = have ? -1 : -2;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+            x[t][r] = (have && r0 + r < rows) ? M[r0 + r + (int64_t)col[t] * ldm] : 0.0;
+    }
+    for (int i = rows + tid; i < CPR_RG * RPT; i += CP_T) v[i] = 0.0;   // rows past the end reflect as zero
+
+    // sum over the 16 lanes of a column (one DPP row): pair sums within quads,
+    // then across the quads of each half row and across the two halves;
+    // every lane ends with the same value (each level adds symmetric pairs)
+    auto colsum = [](double s) {
+        s += dpp_f64<0xB1>(s);     // quad_perm(1, 0, 3, 2)
+        s += dpp_f64<0x4E>(s);     // quad_perm(2, 3, 0, 1)
+        s += dpp_f64<0x141>(s);    // row_half_mirror
+        s += dpp_f64<0x140>(s);    // row_mirror
+        return s;
+    };
+    // exact column norms and ||M||_F^2
+    double nrm2[CPR_CT];
+    double fro = 0.0;
+#pragma unroll
+    for (int t = 0; t < CPR_CT; ++t) {
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) s += x[t][r] * x[t][r];
+        nrm2[t] = colsum(s);
+        fro += (qd == 0 && act[t] == -1) ? nrm2[t] : 0.0;
+    }
+    fro = wave_sum(fro);
+    if (lane == 0) s_red[wave] = fro;
+    __syncthreads();
+    if (tid == 0) {
+        double f = 0.0;
+        for (int w = 0; w < CP_T / 64; ++w) f += s_red[w];
+        st_coherent(partial + g, f);
+    }
+    {
+        unsigned pay;
+        if (!grid_agree<CPR_GROUP>(bar, G, gen, pay, info, spin_limit, nullptr, 0ull, 0ull,
+                        [](unsigned long long, unsigned long long) { return 0u; }))
+            return;
+    }
+    if (tid == 0) {
+        double f = 0.0;
+        for (int h = 0; h < G; ++h) f += ld_coherent(partial + h);
+        const double tol = (double)(rows > cols ? rows : cols) * 2.220446049250313e-16;
+        s_tol2 = tol * tol * f;
+        s_stop = 0;
+        s_rank = kmax;
+    }
+    __syncthreads();
+
+    for (int j = 0; j < kmax; ++j) {
+        const int stopped = s_stop;
+        // ---- 1. local candidates: by norm (k0) and by smallest index (k1) ----
+        unsigned long long k0 = 0, k1 = 0;
+#pragma unroll
+        for (int t = 0; t < CPR_CT; ++t) {
+            if (act[t] == -1) {
+                const unsigned long long a = pivot_key(stopped ? 0.0 : nrm2[t], (unsigned)col[t], ibits);
+                const unsigned long long b = pivot_key(0.0, (unsigned)col[t], ibits);
+                k0 = a > k0 ? a : k0;
+                k1 = b > k1 ? b : k1;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long a = shfl_xor_u64(k0, off), b = shfl_xor_u64(k1, off);
+            k0 = a > k0 ? a : k0;
+            k1 = b > k1 ? b : k1;
+        }
+        if (lane == 0) {
+            s_kred[0][wave] = k0;
+            s_kred[1][wave] = k1;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long a = 0, b = 0;
+            for (int w = 0; w < CP_T / 64; ++w) {
+                a = s_kred[0][w] > a ? s_kred[0][w] : a;
+                b = s_kred[1][w] > b ? s_kred[1][w] : b;
+            }
+            s_key[0] = a;
+            s_key[1] = b;
+        }
+        __syncthreads();
+        // ---- 2. publish the local best column, agree on the pivot ----
+        unsigned pay = 0;
+        {
+            const unsigned long long lk0 = s_key[0], lk1 = s_key[1];
+            const double tol2 = s_tol2;
+            if (lk0 != 0 && !stopped) {
+                // the 16 owner lanes stage the column in LDS, then all threads publish it
+                const int bc = (int)key_index(lk0, ibits);
+#pragma unroll
+                for (int t = 0; t < CPR_CT; ++t) {
+                    if (col[t] == bc) {
+#pragma unroll
+                        for (int r = 0; r < RPT; ++r) cst[r0 + r] = x[t][r];
+                    }
+                }
+                __syncthreads();
+                double* dst = candcol + ((size_t)(j & 1) * G + g) * rows;
+                for (int i = j + tid; i < rows; i += CP_T) st_coherent(dst + i, cst[i]);
+            }
+            auto decide = [&](unsigned long long k0g, unsigned long long k1g) -> unsigned {
+                unsigned stopnow = 0;
+                if (!stopped) {
+                    const double kv = key_value(k0g, ibits);
+                    if (!(kv > tol2) && kv == kv) stopnow = 1;   // NaN norms never trigger the stop
+                }
+                const unsigned win = (stopped || stopnow) ? key_index(k1g, ibits) : key_index(k0g, ibits);
+                return win | (stopnow << 31);
+            };
+            unsigned long long* ks = keys + (size_t)j * cpr_key_words(G);
+            if (!grid_agree<CPR_GROUP>(bar, G, gen, pay, info, spin_limit, ks, lk0, lk1, decide)) return;
+        }
+        const int now_stopped = stopped | (int)(pay >> 31);
+        const int gidx = (int)(pay & 0x7FFFFFFFu);
+        const int owner = gidx / CPR_CPW;
+        // ---- 3. reflector (Parlett's form, R(j, j) = ||x|| >= 0) ----
+        if (!now_stopped) {
+            const double* src = candcol + ((size_t)(j & 1) * G + owner) * rows;
+            double sg = 0.0;
+            for (int i = j + tid; i < rows; i += CP_T) {
+                const double xv = ld_coherent(src + i);
+                v[i] = xv;
+                if (i > j) sg += xv * xv;
+            }
+            sg = wave_sum(sg);
+            if (lane == 0) s_red[wave] = sg;
+            __syncthreads();
+            if (tid == 0) {
+                double sigma = 0.0;
+                for (int w = 0; w < CP_T / 64; ++w) sigma += s_red[w];
+                const double x0 = v[j];
+                const double mu = sqrt(x0 * x0 + sigma);
+                double v0, bb;
+                if (sigma == 0.0) {
+                    v0 = 1.0;
+                    bb = (x0 >= 0.0) ? 0.0 : 2.0;
+                } else {
+                    v0 = (x0 <= 0.0) ? (x0 - mu) : (-sigma / (x0 + mu));
+                    bb = 2.0 * v0 * v0 / (sigma + v0 * v0);
+                }
+                s_beta = bb;
+                s_mu = mu;
+                s_red[0] = (sigma == 0.0) ? 0.0 : 1.0 / v0;
+            }
+            __syncthreads();
+            const double rv0 = s_red[0];
+            for (int i = j + 1 + tid; i < rows; i += CP_T) v[i] *= rv0;
+            if (tid == 0) {
+                v[j] = 1.0;
+                if (j > 0) v[j - 1] = 0.0;               // v(i) = 0 for every i < j
+            }
+        } else if (tid == 0) {
+            s_beta = 0.0;
+            s_mu = 0.0;
+            if (!stopped) {
+                s_stop = 1;
+                s_rank = j;
+            }
+        }
+        __syncthreads();
+        const double b = s_beta;
+        // ---- 4. bookkeeping ----
+        if (g == 0) {
+            if (tid == 0) {
+                if (piv) piv[j] = gidx;
+                if (beta_out) beta_out[j] = b;
+            }
+            if (Vh) {
+                for (int i = tid; i < rows; i += CP_T)
+                    Vh[i + (int64_t)j * ldv] = (i < j || now_stopped) ? ((i == j) ? 1.0 : 0.0) : v[i];
+            }
+        }
+        if (owner == g) {
+            const double mu = s_mu;
+#pragma unroll
+            for (int t = 0; t < CPR_CT; ++t) {
+                if (col[t] != gidx) continue;
+                act[t] = j;
+                if (!now_stopped) {
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        const int i = r0 + r;
+                        if (i >= j) x[t][r] = (i == j) ? mu : 0.0;
+                    }
+                }
+            }
+        }
+        // ---- 5. apply H = I - b v v^T to the active columns, exact norms ----
+        // (v is zero above row j and past the last row, so the sums run over all rows)
+        if (!now_stopped) {
+            double vr[RPT];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) vr[r] = v[r0 + r];
+            double dot[CPR_CT];
+#pragma unroll
+            for (int t = 0; t < CPR_CT; ++t) {
+                double s = 0.0;
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) s += vr[r] * x[t][r];
+                dot[t] = s;
+            }
+#pragma unroll
+            for (int t = 0; t < CPR_CT; ++t) dot[t] = colsum(dot[t]);
+            double sn[CPR_CT];
+#pragma unroll
+            for (int t = 0; t < CPR_CT; ++t) {
+                const double w = (act[t] == -1) ? b * dot[t] : 0.0;
+                double s = 0.0;
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    x[t][r] -= w * vr[r];
+                    s += (r0 + r > j) ? x[t][r] * x[t][r] : 0.0;
+                }
+                sn[t] = s;
+            }
+#pragma unroll
+            for (int t = 0; t < CPR_CT; ++t) {
+                const double s = colsum(sn[t]);
+                if (act[t] == -1) nrm2[t] = s;
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- write back: R^T in original column order, pivoted columns of R ----
+    const int rank = s_rank;
+    if (rank < kmax && g == 0 && tid == 0 && info) atomicOr(info, RQLP_INFO_RANK_DEFICIENT);
+#pragma unroll
+    for (int t = 0; t < CPR_CT; ++t) {
+        if (act[t] == -2) continue;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int i = r0 + r;
+            if (i >= rows) continue;
+            if (Rt) Rt[col[t] + (int64_t)i * ldrt] = (i >= rank) ? 0.0 : x[t][r];
+            if (Rpiv && act[t] >= 0) Rpiv[i + (int64_t)act[t] * ldr] = (i >= rank || i > act[t]) ? 0.0 : x[t][r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 static int index_bits(int64_t cols) {
     int b = 1;
     while ((1ll << b) <= cols) ++b;
@@ -405,10 +798,47 @@ static size_t cpqr_lds(int64_t rows, int cpw) {
     return sizeof(double) * ((size_t)cpw * ldl + cpw + rows) + sizeof(int) * (size_t)cpw;
 }
 
+// rows held per thread by the register-resident kernel (0: rows too large)
+static int cpqr_rpt(int64_t rows) {
+    static const int opts[] = {2, 4, 6, 9, 12, 14, 17, 18, 24};
+    for (int o : opts)
+        if (CPR_RG * (int64_t)o >= rows) return o;
+    return 0;
+}
+
+template <int RPT>
+static int cpqr_reg_capacity() {
+    static int cap = -1;
+    if (cap < 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)cpqr_reg_kernel<RPT>, CP_T, 0) !=
+            hipSuccess)
+            nb = 0;
+        cap = nb * (device_info().num_cus > 0 ? device_info().num_cus : 0);
+    }
+    return cap;
+}
+
+static int cpqr_reg_cap(int rpt) {
+    switch (rpt) {
+        case 2: return cpqr_reg_capacity<2>();
+        case 4: return cpqr_reg_capacity<4>();
+        case 6: return cpqr_reg_capacity<6>();
+        case 9: return cpqr_reg_capacity<9>();
+        case 12: return cpqr_reg_capacity<12>();
+        case 14: return cpqr_reg_capacity<14>();
+        case 17: return cpqr_reg_capacity<17>();
+        case 18: return cpqr_reg_capacity<18>();
+        case 24: return cpqr_reg_capacity<24>();
+        default: return 0;
+    }
+}
+
 int cpqr_plan(int64_t rows, int64_t cols, CpqrPlan* plan) {
     const DeviceInfo& di = device_info();
     const size_t budget = di.max_lds > 0 ? di.max_lds : 65536;
     const int cus = di.num_cus > 0 ? di.num_cus : 1;
+    plan->rpt = 0;
     // single workgroup when everything fits
     if (cpqr_lds(rows, (int)cols) <= budget && cols <= 512) {
         plan->G = 1;
@@ -416,6 +846,19 @@ int cpqr_plan(int64_t rows, int64_t cols, CpqrPlan* plan) {
         plan->lds = cpqr_lds(rows, (int)cols);
         plan->single = true;
         return 0;
+    }
+    // columns in registers, 64 per workgroup, when the rows fit and the grid is co-resident
+    const int rpt = cpqr_rpt(rows);
+    if (rpt > 0) {
+        const int64_t G = ceil_div(cols, CPR_CPW);
+        if (G <= cpqr_reg_cap(rpt)) {
+            plan->G = (int)G;
+            plan->cpw = CPR_CPW;
+            plan->lds = 0;
+            plan->single = false;
+            plan->rpt = rpt;
+            return 0;
+        }
     }
     int cpw = (int)ceil_div(cols, cus);
     if (cpw < 1) cpw = 1;
@@ -438,12 +881,16 @@ size_t cpqr_scratch_bytes(int64_t rows, int64_t cols) {
 }
 
 void cpqr_carve(Arena& ar, int64_t rows, int64_t cols, CpqrScratch* sc) {
-    const int cus = device_info().num_cus > 0 ? device_info().num_cus : 256;
+    // sized for the larger of the two multi-workgroup grids (one per CU, or 64 columns each)
+    int gm = device_info().num_cus > 0 ? device_info().num_cus : 256;
+    if (ceil_div(cols, CPR_CPW) > gm) gm = (int)ceil_div(cols, CPR_CPW);
     const int64_t kmax = rows < cols ? rows : cols;
-    sc->keys = ar.take<unsigned long long>((size_t)kmax * cp_key_words(cus));
-    sc->candcol = ar.take<double>((size_t)2 * cus * rows);
-    sc->partial = ar.take<double>(cus);
-    sc->bar = ar.take<unsigned>(cp_bar_words(cus));
+    const int kw = cp_key_words(gm) > cpr_key_words(gm) ? cp_key_words(gm) : cpr_key_words(gm);
+    const int bw = cp_bar_words(gm) > cpr_bar_words(gm) ? cp_bar_words(gm) : cpr_bar_words(gm);
+    sc->keys = ar.take<unsigned long long>((size_t)kmax * kw);
+    sc->candcol = ar.take<double>((size_t)2 * gm * rows);
+    sc->partial = ar.take<double>(gm);
+    sc->bar = ar.take<unsigned>(bw);
 }
 
 int cpqr(const double* M, int64_t ldm, int64_t rows, int64_t cols, const CpqrScratch& sc, int64_t* piv,
@@ -471,12 +918,10 @@ int cpqr(const double* M, int64_t ldm, int64_t rows, int64_t cols, const CpqrScr
                            ldr, Rt, ldrt, info, spin);
         return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
     }
-    RQLP_TRY(fill_zero_bytes(sc.keys, sizeof(unsigned long long) * (size_t)kmax * cp_key_words(plan.G), s));
-    RQLP_TRY(fill_zero_bytes(sc.bar, sizeof(unsigned) * cp_bar_words(plan.G), s));
-    int nb = 0;
-    RQLP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)cpqr_kernel<false>, CP_T,
-                                                             plan.lds));
-    if ((int64_t)nb * device_info().num_cus < plan.G) return RQLP_E_UNSUPPORTED;
+    const size_t kw = plan.rpt > 0 ? (size_t)cpr_key_words(plan.G) : (size_t)cp_key_words(plan.G);
+    const size_t bw = plan.rpt > 0 ? (size_t)cpr_bar_words(plan.G) : (size_t)cp_bar_words(plan.G);
+    RQLP_TRY(fill_zero_bytes(sc.keys, sizeof(unsigned long long) * (size_t)kmax * kw, s));
+    RQLP_TRY(fill_zero_bytes(sc.bar, sizeof(unsigned) * bw, s));
     const double* Mp = M;
     int64_t ldm_ = ldm, ldv_ = ldv, ldr_ = ldr, ldrt_ = ldrt;
     unsigned long long* keys = sc.keys;
@@ -488,6 +933,30 @@ int cpqr(const double* M, int64_t ldm, int64_t rows, int64_t cols, const CpqrScr
                     (void*)&bar,  (void*)&piv,   (void*)&Vh,    (void*)&ldv_,  (void*)&beta,
                     (void*)&Rpiv, (void*)&ldr_,  (void*)&Rt,    (void*)&ldrt_, (void*)&info,
                     (void*)&spin};
+    if (plan.rpt > 0) {
+        void* rargs[] = {(void*)&Mp,   (void*)&ldm_, (void*)&rows_i, (void*)&cols_i, (void*)&kmax_i,
+                         (void*)&ibits, (void*)&keys, (void*)&cand,  (void*)&part,   (void*)&bar,
+                         (void*)&piv,  (void*)&Vh,   (void*)&ldv_,   (void*)&beta,   (void*)&Rpiv,
+                         (void*)&ldr_, (void*)&Rt,   (void*)&ldrt_,  (void*)&info,   (void*)&spin};
+        const void* fn = nullptr;
+        switch (plan.rpt) {
+            case 2: fn = (const void*)cpqr_reg_kernel<2>; break;
+            case 4: fn = (const void*)cpqr_reg_kernel<4>; break;
+            case 6: fn = (const void*)cpqr_reg_kernel<6>; break;
+            case 9: fn = (const void*)cpqr_reg_kernel<9>; break;
+            case 12: fn = (const void*)cpqr_reg_kernel<12>; break;
+            case 14: fn = (const void*)cpqr_reg_kernel<14>; break;
+            case 17: fn = (const void*)cpqr_reg_kernel<17>; break;
+            case 18: fn = (const void*)cpqr_reg_kernel<18>; break;
+            default: fn = (const void*)cpqr_reg_kernel<24>; break;
+        }
+        RQLP_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(plan.G), dim3(CP_T), rargs, 0, s));
+        return 0;
+    }
+    int nb = 0;
+    RQLP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)cpqr_kernel<false>, CP_T,
+                                                             plan.lds));
+    if ((int64_t)nb * device_info().num_cus < plan.G) return RQLP_E_UNSUPPORTED;
     RQLP_HIP_TRY(hipLaunchCooperativeKernel((const void*)cpqr_kernel<false>, dim3(plan.G), dim3(CP_T), args,
                                             (unsigned)plan.lds, s));
     return 0;

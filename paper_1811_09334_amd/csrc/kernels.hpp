@@ -92,6 +92,7 @@ struct CpqrPlan {
     int cpw;        // columns per workgroup
     size_t lds;     // dynamic LDS bytes
     bool single;    // one workgroup: no grid-wide exchange
+    int rpt;        // > 0: columns held in registers, rpt rows per lane (16 lanes per column)
 };
 int cpqr_plan(int64_t rows, int64_t cols, CpqrPlan* plan);
 size_t cpqr_scratch_bytes(int64_t rows, int64_t cols);
