@@ -69,12 +69,12 @@ int cholqr2(Ctx& cx, int64_t rows, int64_t c, double* buf0, double* buf1, int64_
     for (int pass = 0; pass < 2; ++pass) {
         const int32_t* gate = (!final && pass == 1) ? cx.shifted : nullptr;
         RQLP_TRY(gemm<double>(true, false, c, c, rows, cur, ld, cur, ld, cx.o.G, c, false, 1.0, 0.0, cx.gws,
-                              cx.gws_elems, cx.s, gate, 1));
+                              cx.gws_elems, cx.s, gate, 1, 1));
         double* Lp = pass == 0 ? cx.o.L1 : cx.o.L2;
         RQLP_TRY(chol_inv<double>(c, cx.o.G, c, Lp, cx.o.Li, nullptr, c, shift_scale(rows, c), cx.info, cx.s,
                                   gate, (!final && pass == 0) ? cx.shifted : nullptr, cx.o.sync));
         RQLP_TRY(gemm<double>(false, true, rows, c, c, cur, ld, cx.o.Li, c, nxt, ld, false, 1.0, 0.0, cx.gws,
-                              cx.gws_elems, cx.s, gate, 2));
+                              cx.gws_elems, cx.s, gate, 2, 2));
         double* t = cur;
         cur = nxt;
         nxt = t;
@@ -116,11 +116,11 @@ int cholqr_f32(Ctx32& cx, int64_t rows, int64_t c, float* buf0, float* buf1, int
     for (int pass = 0; pass < 3; ++pass) {
         const int32_t* gate = pass >= always ? cx.shifted : nullptr;
         RQLP_TRY(gemm<float>(true, false, c, c, rows, cur, ld, cur, ld, cx.G, c, false, 1.0f, 0.0f, cx.ws,
-                             cx.ws_elems, cx.s, gate, 1));
+                             cx.ws_elems, cx.s, gate, 1, 1));
         RQLP_TRY(chol_inv<float>(c, cx.G, c, cx.L, cx.Lid, cx.Li, c, shift_scale32(rows, c), cx.info, cx.s,
                                  gate, pass < 2 ? cx.shifted : nullptr, cx.sync, pass == 0 ? 1 : 2));
         RQLP_TRY(gemm<float>(false, true, rows, c, c, cur, ld, cx.Li, c, nxt, ld, false, 1.0f, 0.0f, cx.ws,
-                             cx.ws_elems, cx.s, gate, 2));
+                             cx.ws_elems, cx.s, gate, 2, 2));
         float* t = cur;
         cur = nxt;
         nxt = t;

@@ -61,7 +61,7 @@ template <typename T, bool TA, bool TB, int MB, int NB, int BK, typename TI, typ
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
     int64_t M, int64_t N, int64_t K, const TI* __restrict__ A, int64_t lda,
     const TI* __restrict__ B, int64_t ldb, TC* __restrict__ C, int64_t ldc, int64_t split_stride,
-    int64_t kchunk, const int32_t* __restrict__ gate, int gate_copy) {
+    int64_t kchunk, const int32_t* __restrict__ gate, int gate_copy, int tri) {
     constexpr int BM = 64 * MB;
     constexpr int BN = 16 * NB;
     constexpr int SA = TA ? (BK + 2) : (BM + 16);
@@ -93,8 +93,13 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
             }
         return;
     }
+    // tri 1: only the lower triangle of C is wanted (Gram matrix): tiles wholly
+    // above the diagonal are skipped.  tri 2: op(B)(k, j) = 0 for k > j (B^T of a
+    // lower triangular B), so the K range of a tile ends at its last column.
+    if (tri == 1 && m0 + BM <= n0) return;
     const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
-    const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
+    int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
+    if (tri == 2 && kend > n0 + BN) kend = n0 + BN;
 
     acc_t acc[MB][NB];
 #pragma unroll
@@ -224,11 +229,12 @@ template <typename T, typename TO>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(int64_t M, int64_t N, const T* __restrict__ W,
                                                             int64_t ldw, int64_t split_stride, int S, T alpha,
                                                             T beta, TO* __restrict__ C, int64_t ldc,
-                                                            const int32_t* __restrict__ gate) {
+                                                            const int32_t* __restrict__ gate, int tri) {
     if (gate != nullptr && *gate == 0) return;
     const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= M * N) return;
     const int64_t i = idx % M, j = idx / M;
+    if (tri == 1 && j > i) return;                   // partials of skipped tiles were never written
     const T* w = W + i + j * ldw;
     T v0 = T(0), v1 = T(0);
     int s = 0;
@@ -314,20 +320,20 @@ GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K) {
 template <typename T, typename TI, typename TC, bool TA, bool TB, int NB>
 void launch_nb(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const TI* A, int64_t lda,
                const TI* B, int64_t ldb, TC* C, int64_t ldc, int64_t split_stride, const int32_t* gate, int gate_copy,
-               hipStream_t s) {
+               int tri, hipStream_t s) {
     dim3 grid((unsigned)p.tm, (unsigned)p.tn, (unsigned)p.S);
     hipLaunchKernelGGL((gemm_skinny_kernel<T, TA, TB, 1, NB, GEMM_BK, TI, TC>), grid, dim3(GEMM_THREADS), 0, s, M, N,
-                       K, A, lda, B, ldb, C, ldc, split_stride, p.kchunk, gate, gate_copy);
+                       K, A, lda, B, ldb, C, ldc, split_stride, p.kchunk, gate, gate_copy, tri);
 }
 
 template <typename T, typename TI, typename TC, bool TA, bool TB>
 void launch_dispatch(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const TI* A, int64_t lda,
                      const TI* B, int64_t ldb, TC* C, int64_t ldc, int64_t split_stride, const int32_t* gate,
-                     int gate_copy, hipStream_t s) {
+                     int gate_copy, int tri, hipStream_t s) {
     switch (p.nb) {
 #define RQLP_NB_CASE(X)                                                                                           \
     case X:                                                                                                       \
-        launch_nb<T, TI, TC, TA, TB, X>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, s);    \
+        launch_nb<T, TI, TC, TA, TB, X>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, tri, s); \
         break;
         RQLP_NB_CASE(1) RQLP_NB_CASE(2) RQLP_NB_CASE(3) RQLP_NB_CASE(4)
         RQLP_NB_CASE(5) RQLP_NB_CASE(6) RQLP_NB_CASE(7)
@@ -345,24 +351,27 @@ size_t gemm_workspace_elems(int64_t M, int64_t N, int64_t K) {
 template <typename T, typename TI, typename TC>
 static void launch_any(bool ta, bool tb, const GemmPlan& p, int64_t M, int64_t N, int64_t K, const TI* A,
                        int64_t lda, const TI* B, int64_t ldb, TC* C, int64_t ldc, int64_t split_stride,
-                       const int32_t* gate, int gate_copy, hipStream_t s) {
+                       const int32_t* gate, int gate_copy, int tri, hipStream_t s) {
     if (ta && tb) return;   // not needed by the method
     if (ta)
-        launch_dispatch<T, TI, TC, true, false>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, s);
+        launch_dispatch<T, TI, TC, true, false>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, tri,
+                                                s);
     else if (tb)
-        launch_dispatch<T, TI, TC, false, true>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, s);
+        launch_dispatch<T, TI, TC, false, true>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, tri,
+                                                s);
     else
         launch_dispatch<T, TI, TC, false, false>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy,
-                                                 s);
+                                                 tri, s);
 }
 
 // T: arithmetic and split-K partial type; TI: A, B; TC: C.
 template <typename T, typename TI, typename TC>
 static int gemm_impl(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const TI* A, int64_t lda, const TI* B,
                      int64_t ldb, TC* C, int64_t ldc, bool trans_out, T alpha, T beta, T* ws, size_t ws_elems,
-                     hipStream_t s, const int32_t* gate, int gate_mode) {
+                     hipStream_t s, const int32_t* gate, int gate_mode, int tri = 0) {
     if (ta && tb) return RQLP_E_UNSUPPORTED;
     if (M <= 0 || N <= 0) return 0;
+    if ((tri == 1 && (trans_out || beta != T(0))) || (tri == 2 && !tb)) return RQLP_E_UNSUPPORTED;
     GemmPlan p = plan_gemm(M, N, K);
     const bool direct = (p.S == 1 && !trans_out && alpha == T(1) && beta == T(0));
     // the gated copy (gate_mode 2) writes op(A) straight into C: only for a
@@ -370,18 +379,18 @@ static int gemm_impl(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const TI
     if (gate_mode == 2 && (!direct || ta || K != N)) return RQLP_E_UNSUPPORTED;
     const int gate_copy = gate_mode == 2 ? 1 : 0;
     if (direct) {
-        launch_any<T, TI, TC>(ta, tb, p, M, N, K, A, lda, B, ldb, C, ldc, 0, gate, gate_copy, s);
+        launch_any<T, TI, TC>(ta, tb, p, M, N, K, A, lda, B, ldb, C, ldc, 0, gate, gate_copy, tri, s);
         return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
     }
     if ((size_t)(p.S * M * N) > ws_elems || ws == nullptr) return RQLP_E_WORKSPACE;
-    launch_any<T, TI, T>(ta, tb, p, M, N, K, A, lda, B, ldb, ws, M, M * N, gate, 0, s);
+    launch_any<T, TI, T>(ta, tb, p, M, N, K, A, lda, B, ldb, ws, M, M * N, gate, 0, tri, s);
     if (trans_out) {
         dim3 grid((unsigned)ceil_div(M, 32), (unsigned)ceil_div(N, 32));
         hipLaunchKernelGGL((splitk_reduce_t_kernel<T, TC>), grid, dim3(256), 0, s, M, N, ws, M, M * N, (int)p.S,
                            alpha, beta, C, ldc, gate);
     } else {
         hipLaunchKernelGGL((splitk_reduce_kernel<T, TC>), dim3((unsigned)ceil_div(M * N, 256)), dim3(256), 0, s, M,
-                           N, ws, M, M * N, (int)p.S, alpha, beta, C, ldc, gate);
+                           N, ws, M, M * N, (int)p.S, alpha, beta, C, ldc, gate, tri);
     }
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
@@ -389,9 +398,9 @@ static int gemm_impl(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const TI
 template <typename T>
 int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64_t ldb,
          T* C, int64_t ldc, bool trans_out, T alpha, T beta, T* ws, size_t ws_elems, hipStream_t s,
-         const int32_t* gate, int gate_mode) {
+         const int32_t* gate, int gate_mode, int tri) {
     return gemm_impl<T, T, T>(ta, tb, M, N, K, A, lda, B, ldb, C, ldc, trans_out, alpha, beta, ws, ws_elems, s, gate,
-                              gate_mode);
+                              gate_mode, tri);
 }
 
 int gemm_f32_acc64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
@@ -402,8 +411,9 @@ int gemm_f32_acc64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const floa
 }
 
 template int gemm<double>(bool, bool, int64_t, int64_t, int64_t, const double*, int64_t, const double*, int64_t,
-                          double*, int64_t, bool, double, double, double*, size_t, hipStream_t, const int32_t*, int);
+                          double*, int64_t, bool, double, double, double*, size_t, hipStream_t, const int32_t*, int,
+                          int);
 template int gemm<float>(bool, bool, int64_t, int64_t, int64_t, const float*, int64_t, const float*, int64_t,
-                         float*, int64_t, bool, float, float, float*, size_t, hipStream_t, const int32_t*, int);
+                         float*, int64_t, bool, float, float, float*, size_t, hipStream_t, const int32_t*, int, int);
 
 }  // namespace rqlp

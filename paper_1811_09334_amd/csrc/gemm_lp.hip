@@ -482,7 +482,7 @@ __global__ __launch_bounds__(256) void cast_panel_kernel(int64_t R, int64_t K, c
                                                          int64_t ld, unsigned short* __restrict__ dst,
                                                          unsigned short* __restrict__ dlo, int kind,
                                                          const int* __restrict__ kexp,
-                                                         const int* __restrict__ gexp) {
+                                                         const int* __restrict__ gexp, int vec) {
     const int64_t nkb = (K + 31) >> 5, nrb = (R + 15) >> 4;
     const int64_t chunks = nrb * nkb * 64;
     const int g = gexp ? *gexp : 0;
@@ -494,11 +494,20 @@ __global__ __launch_bounds__(256) void cast_panel_kernel(int64_t R, int64_t K, c
         u16x8_t v = {0, 0, 0, 0, 0, 0, 0, 0}, vl = {0, 0, 0, 0, 0, 0, 0, 0};
         if (r < R) {
             const float* p = src + r * ld;
+            float xs[8];
+            if (vec && k0 + 8 <= K) {                    // two 16-byte loads
+                const float4_t a = *(const float4_t*)(p + k0), b = *(const float4_t*)(p + k0 + 4);
+                xs[0] = a[0]; xs[1] = a[1]; xs[2] = a[2]; xs[3] = a[3];
+                xs[4] = b[0]; xs[5] = b[1]; xs[6] = b[2]; xs[7] = b[3];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) xs[q] = (k0 + q < K) ? p[k0 + q] : 0.f;
+            }
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int64_t k = k0 + q;
                 if (k < K) {
-                    float x = p[k];
+                    float x = xs[q];
                     const int e = (kexp ? kexp[k] : 0) - g;
                     if (e) x = ldexpf(x, e);
                     unsigned short h, l;
@@ -519,8 +528,9 @@ int cast_panel(int kind, int64_t R, int64_t K, const float* src, int64_t ld, uns
     if ((kind == RQLP_MIXED_BF16X3) != (dlo != nullptr)) return RQLP_E_UNSUPPORTED;
     int64_t blocks = ceil_div(ceil_div(R, 16) * ceil_div(K, 32) * 64, 256);
     if (blocks > 16384) blocks = 16384;
+    const int vec = (ld % 4 == 0) && ((((uintptr_t)src) & 15) == 0);
     hipLaunchKernelGGL(cast_panel_kernel, dim3((unsigned)blocks), dim3(256), 0, s, R, K, src, ld, dst, dlo, kind,
-                       kexp, gexp);
+                       kexp, gexp, vec);
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 

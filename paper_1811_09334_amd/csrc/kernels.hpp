@@ -18,7 +18,11 @@ size_t gemm_workspace_elems(int64_t M, int64_t N, int64_t K);
 template <typename T>
 int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A, int64_t lda, const T* B, int64_t ldb,
          T* C, int64_t ldc, bool trans_out, T alpha, T beta, T* ws, size_t ws_elems, hipStream_t s,
-         const int32_t* gate = nullptr, int gate_mode = 0);
+         const int32_t* gate = nullptr, int gate_mode = 0, int tri = 0);
+// tri = 1: only the lower triangle of C is computed and written (the Gram
+// matrix op(A) op(B) = X^T X of CholeskyQR; no transposed output, beta 0);
+// tri = 2: op(B) = B^T with B lower triangular (its strict upper part is not
+// read), e.g. X L^{-T}.
 // The same product with FP32 operands and result but FP64 MFMA arithmetic
 // (exact products, FP64 sums; split-K partials in ws are FP64).
 int gemm_f32_acc64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
