@@ -396,6 +396,7 @@ int chol_mw(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float*
         attr_set = true;
     }
     const int NB = (int)((c + 15) / 16);
+    if (device_info().num_cus > 0 && NB > device_info().num_cus) return RQLP_E_UNSUPPORTED;
     const size_t lds = chol_mw_lds_bytes(c);
     // epochs: odd and distinct per launch (a zeroed flag word never matches)
     const unsigned e0 = 2u * epoch_counter.fetch_add(2) + 1u;
@@ -411,10 +412,13 @@ int chol_mw(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float*
         int gate_mode = attempt ? 2 : (run_flag ? 1 : 0);
         int32_t* shout = shifted_out;
         int smode = shifted_mode;
-        void* args[] = {&cc, (void*)&G, &ldg, &shift_scale, &a, &L, &Linv, &Linv32, &ld, &info, &fl, &ep, &retry,
-                        (void*)&gate, &gate_mode, &shout, &smode};
-        RQLP_HIP_TRY(hipLaunchCooperativeKernel((const void*)chol_mw_kernel<TG>, dim3(NB), dim3(MW_T), args,
-                                                (unsigned)lds, s));
+        // A plain launch: the NB <= 32 workgroups (one per block column, at most
+        // one per CU by their LDS) all fit on the device at once, and every
+        // wait is bounded.  (A cooperative launch gave the same residency but
+        // cost ~15 us of idle device time before and ~10 us after each launch.)
+        hipLaunchKernelGGL((chol_mw_kernel<TG>), dim3(NB), dim3(MW_T), (unsigned)lds, s, cc, G, ldg, shift_scale, a, L,
+                           Linv, Linv32, ld, info, fl, ep, retry, gate, gate_mode, shout, smode);
+        RQLP_HIP_TRY(hipGetLastError());
     }
     return 0;
 }
