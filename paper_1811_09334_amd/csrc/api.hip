@@ -106,13 +106,18 @@ struct Ctx32 {
 // final basis: CholeskyQR2; 1 for an intermediate basis of the subspace
 // iteration, which only has to span range(X) and be well conditioned) and
 // the rest only when a Cholesky of an earlier pass needed the shifted retry
-// (device word cx.shifted, set by any such pass).  A skipped pass forms no
-// Gram and its update copies X through, so the result is always in buf1.
+// (device word cx.shifted, set by any such pass and never cleared by a later
+// one).  A skipped pass forms no Gram; the result is always in buf1: for the
+// final basis the skipped third pass copies X through, and for an
+// intermediate basis the two conditional passes run or are skipped together
+// (the second runs only when the word is set, and then the third does too),
+// so their updates are simply left out when skipped.
 int cholqr_f32(Ctx32& cx, int64_t rows, int64_t c, float* buf0, float* buf1, int64_t ld, float** out,
                bool final = true) {
     float* cur = buf0;
     float* nxt = buf1;
     const int always = final ? 2 : 1;
+    const int skip_mode = final ? 2 : 1;          // gemm gate modes: 2 copy op(A), 1 skip
     for (int pass = 0; pass < 3; ++pass) {
         const int32_t* gate = pass >= always ? cx.shifted : nullptr;
         RQLP_TRY(gemm<float>(true, false, c, c, rows, cur, ld, cur, ld, cx.G, c, false, 1.0f, 0.0f, cx.ws,
@@ -120,7 +125,7 @@ int cholqr_f32(Ctx32& cx, int64_t rows, int64_t c, float* buf0, float* buf1, int
         RQLP_TRY(chol_inv<float>(c, cx.G, c, cx.L, cx.Lid, cx.Li, c, shift_scale32(rows, c), cx.info, cx.s,
                                  gate, pass < 2 ? cx.shifted : nullptr, cx.sync, pass == 0 ? 1 : 2));
         RQLP_TRY(gemm<float>(false, true, rows, c, c, cur, ld, cx.Li, c, nxt, ld, false, 1.0f, 0.0f, cx.ws,
-                             cx.ws_elems, cx.s, gate, 2, 2));
+                             cx.ws_elems, cx.s, gate, skip_mode, 2));
         float* t = cur;
         cur = nxt;
         nxt = t;

@@ -152,4 +152,18 @@ __device__ __forceinline__ void drain_and_sync() {
     __syncthreads();
 }
 
+// Copies from global memory straight into LDS (global_load_lds_dwordx4): the
+// LDS operand is the wave's base address, lane l's 16 bytes land at base + 16 l.
+#define RQLP_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
+// LDS-only barrier: the compiler's __syncthreads also waits for every
+// outstanding global load (vmcnt(0)), which would drain a prefetch queue.
+#define RQLP_LDS_BARRIER() asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory")
+
+// s_waitcnt with only the vector-memory counter constrained (at most n outstanding)
+template <int n>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(n >= 0 && n < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt(0x0F70 | (n & 15) | ((n >> 4) << 14));
+}
+
 }  // namespace rqlp

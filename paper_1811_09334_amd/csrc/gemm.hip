@@ -22,6 +22,8 @@
 //   A, op(A) = A   : [k][i], row stride BM + 16   (global loads run along i)
 //   A, op(A) = A^T : [i][k], row stride BK + 2    (global loads run along k)
 //   B              : [j][k], row stride BK + 2    (global loads run along k)
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -345,7 +347,12 @@ void launch_dispatch(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const T
 
 size_t gemm_workspace_elems(int64_t M, int64_t N, int64_t K) {
     GemmPlan p = plan_gemm(M, N, K);
-    return (size_t)(p.S * M * N);
+    size_t e = (size_t)(p.S * M * N);
+    if (M == N) {                                    // a Gram matrix may take the CholeskyQR kernel
+        const size_t g = gram_workspace_elems(K, M);
+        if (g > e) e = g;
+    }
+    return e;
 }
 
 template <typename T, typename TI, typename TC>
@@ -372,6 +379,16 @@ static int gemm_impl(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const TI
     if (ta && tb) return RQLP_E_UNSUPPORTED;
     if (M <= 0 || N <= 0) return 0;
     if ((tri == 1 && (trans_out || beta != T(0))) || (tri == 2 && !tb)) return RQLP_E_UNSUPPORTED;
+    if constexpr (std::is_same<T, TI>::value && std::is_same<T, TC>::value) {
+        // the two products of a CholeskyQR pass have kernels of their own
+        if (alpha == T(1) && beta == T(0) && !trans_out) {
+            if (tri == 1 && ta && M == N && (const void*)A == (const void*)B && lda == ldb && gate_mode != 2 &&
+                gram_fits<T>(K, M, A, lda, ws, ws_elems))
+                return gram<T>(K, M, A, lda, C, ldc, ws, ws_elems, s, gate);
+            if (tri == 2 && !ta && N == K && ldb >= N && ldb <= (1 << 20) && trmm_fits<T>(M, N, A, lda, C, ldc))
+                return trmm_lt<T>(M, N, A, lda, B, ldb, C, ldc, s, gate, gate_mode);
+        }
+    }
     GemmPlan p = plan_gemm(M, N, K);
     const bool direct = (p.S == 1 && !trans_out && alpha == T(1) && beta == T(0));
     // the gated copy (gate_mode 2) writes op(A) straight into C: only for a

@@ -49,18 +49,6 @@ constexpr int LP_THREADS = 64 * LP_WAVES;
 constexpr int LP_BM = 32 * LP_WAVES;     // rows of X per workgroup
 constexpr int LP_BLK = 512;              // elements of one 16 x 32 fragment block
 
-#define RQLP_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
-// LDS-only barrier: the compiler's __syncthreads also waits for every
-// outstanding global load (vmcnt(0)), which would drain the prefetch queue.
-#define RQLP_LDS_BARRIER() asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory")
-
-// s_waitcnt with only the vector-memory counter constrained (at most n outstanding)
-template <int n>
-__device__ __forceinline__ void wait_vm() {
-    static_assert(n >= 0 && n < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt(0x0F70 | (n & 15) | ((n >> 4) << 14));
-}
-
 template <int KIND>
 __device__ __forceinline__ float4_t mfma_lp(u16x8_t a, u16x8_t b, float4_t c) {
     if constexpr (KIND == RQLP_MIXED_FP16)

@@ -23,6 +23,21 @@ int gemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const T* A, int64_t 
 // matrix op(A) op(B) = X^T X of CholeskyQR; no transposed output, beta 0);
 // tri = 2: op(B) = B^T with B lower triangular (its strict upper part is not
 // read), e.g. X L^{-T}.
+// --- cholqr_mm.hip: the products of a CholeskyQR pass on a tall panel ------
+// G = X^T X (lower triangle; X: R x c, c <= 512) and Y = X Li^T (Li lower
+// triangular c x c, strict upper part not read), used by gemm for tri = 1 / 2
+// when the operands qualify (*_fits); ws: gram_workspace_elems(R, c).
+size_t gram_workspace_elems(int64_t R, int64_t c);
+template <typename T>
+bool gram_fits(int64_t R, int64_t c, const T* X, int64_t ldx, const T* ws, size_t ws_elems);
+template <typename T>
+int gram(int64_t R, int64_t c, const T* X, int64_t ldx, T* G, int64_t ldg, T* ws, size_t ws_elems, hipStream_t s,
+         const int32_t* gate);
+template <typename T>
+bool trmm_fits(int64_t R, int64_t c, const T* X, int64_t ldx, const T* Y, int64_t ldy);
+template <typename T>
+int trmm_lt(int64_t R, int64_t c, const T* X, int64_t ldx, const T* Li, int64_t ldl, T* Y, int64_t ldy,
+            hipStream_t s, const int32_t* gate, int gate_mode);
 // The same product with FP32 operands and result but FP64 MFMA arithmetic
 // (exact products, FP64 sums; split-K partials in ws are FP64).
 int gemm_f32_acc64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,

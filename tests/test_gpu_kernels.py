@@ -140,3 +140,19 @@ def test_cholqr2_panel_widths(gpu, c):
     assert np.abs(V.T @ V - np.eye(c)).max() < 1e-12 * max(10, c)
     assert np.linalg.norm(Y - V @ R) < 1e-13 * np.linalg.norm(Y) * max(10, c)
     assert np.allclose(np.tril(R, -1), 0.0) and np.all(np.diag(R) > 0)
+
+
+@pytest.mark.parametrize("m,c", [(7, 5), (13, 13), (1001, 33), (4099, 272), (4100, 272), (2052, 130)])
+def test_cholqr2_row_counts(gpu, m, c):
+    """Row counts that leave a tail past the last whole fragment of the Gram
+    product, or are odd (the update then takes the general product)."""
+    rng = np.random.default_rng(m + c)
+    Y = rng.standard_normal((m, c)) * np.logspace(0, -3, c)[None, :]
+    V, R, info = gpu.orthonormalize(to_dev(Y), want_r=True)
+    V, R = to_np(V), to_np(R)
+    assert int(to_np(info)[0]) == 0
+    assert np.abs(V.T @ V - np.eye(c)).max() < 1e-12 * max(10, c)
+    assert np.linalg.norm(Y - V @ R) < 1e-13 * np.linalg.norm(Y) * max(10, c)
+    q, r = np.linalg.qr(Y)
+    s = np.sign(np.diag(r))
+    assert np.allclose(R, s[:, None] * r, atol=1e-10 * np.abs(r).max())
