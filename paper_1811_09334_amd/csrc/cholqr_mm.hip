@@ -123,14 +123,15 @@ __global__ __launch_bounds__(GR_THREADS) void gram_kernel(int c, const T* __rest
         src[i] = (const char*)(X + (int64_t)col * ldx + VEC * (lane >> 4));
         lofs[i] = b < nbl ? b * GR_FRAG : GR_NBUF * STAGE;
     }
-    // LDS byte offsets of the two operand fragments of each pair (-1: no pair)
+    // LDS byte offsets of the two operand fragments of each pair; slots past
+    // the last pair compute block (0, 0) again and are not stored
     int oa[GR_BPW], ob[GR_BPW];
 #pragma unroll
     for (int s = 0; s < GR_BPW; ++s) {
         const int p = pw0 + s;
         int bi = 0, bj = 0;
         if (p < P) cq_pair(p, bi, bj);
-        oa[s] = p < P ? bi * GR_FRAG : -1;
+        oa[s] = bi * GR_FRAG;
         ob[s] = bj * GR_FRAG;
     }
     acc_t acc[GR_BPW];
@@ -151,14 +152,17 @@ __global__ __launch_bounds__(GR_THREADS) void gram_kernel(int c, const T* __rest
         RQLP_LDS_BARRIER();                                  // ... and every wave's; stage j - 1 is free
         issue((u + GR_NBUF - 1) % GR_NBUF, f0 + j + GR_NBUF - 1);
         const char* Lb = Ls + u * STAGE + 16 * lane;
+        vec_t a[GR_BPW], b[GR_BPW];
 #pragma unroll
         for (int s = 0; s < GR_BPW; ++s) {
-            if (oa[s] < 0) continue;
-            const vec_t a = *(const vec_t*)(Lb + oa[s]);
-            const vec_t b = *(const vec_t*)(Lb + ob[s]);
-#pragma unroll
-            for (int t = 0; t < VEC; ++t) acc[s] = Mm::op(a[t], b[t], acc[s]);
+            a[s] = *(const vec_t*)(Lb + oa[s]);
+            b[s] = *(const vec_t*)(Lb + ob[s]);
         }
+        // t outer: consecutive MFMAs update different accumulators
+#pragma unroll
+        for (int t = 0; t < VEC; ++t)
+#pragma unroll
+            for (int s = 0; s < GR_BPW; ++s) acc[s] = Mm::op(a[s][t], b[s][t], acc[s]);
     };
 
 #pragma unroll
@@ -176,18 +180,36 @@ __global__ __launch_bounds__(GR_THREADS) void gram_kernel(int c, const T* __rest
     T* W = ws + (int64_t)blockIdx.x * P * 256 + 4 * lane;
 #pragma unroll
     for (int s = 0; s < GR_BPW; ++s)
-        if (oa[s] >= 0) *(acc_t*)(W + (int64_t)(pw0 + s) * 256) = acc[s];
+        if (pw0 + s < P) *(acc_t*)(W + (int64_t)(pw0 + s) * 256) = acc[s];
 }
 
-// G(i, j) for i >= j: the S partial sums of its pair in the fixed order s =
-// 0, 1, ..., plus the rows R0 .. R-1 that fill no whole fragment.
+// G(i, j) for i >= j: the S partial sums of its pair, plus the rows R0 .. R-1
+// that fill no whole fragment.  A workgroup takes 64 entries of one pair;
+// wave h adds the splits s = h mod 4 in four interleaved chains, and the
+// four wave sums are combined in a fixed order (reproducible results).
 template <typename T>
 __global__ __launch_bounds__(256) void gram_reduce_kernel(int c, int P, int S, const T* __restrict__ ws, int64_t R0,
                                                           int64_t R, const T* __restrict__ X, int64_t ldx,
                                                           T* __restrict__ G, int64_t ldg,
                                                           const int32_t* __restrict__ gate) {
     if (gate != nullptr && *gate == 0) return;
-    const int p = blockIdx.x, e = threadIdx.x;
+    __shared__ T part[4][64];
+    const int p = blockIdx.x >> 2, el = threadIdx.x & 63, h = threadIdx.x >> 6;
+    const int e = (blockIdx.x & 3) * 64 + el;
+    const T* w = ws + (int64_t)p * 256 + e;
+    const int64_t stride = (int64_t)P * 256;
+    T v0 = T(0), v1 = T(0), v2 = T(0), v3 = T(0);
+    int s = h;
+    for (; s + 12 < S; s += 16) {
+        v0 += w[s * stride];
+        v1 += w[(s + 4) * stride];
+        v2 += w[(s + 8) * stride];
+        v3 += w[(s + 12) * stride];
+    }
+    for (; s < S; s += 4) v0 += w[s * stride];
+    part[h][el] = (v0 + v1) + (v2 + v3);
+    __syncthreads();
+    if (h != 0) return;
     int bi, bj;
     cq_pair(p, bi, bj);
     const int lane = e >> 2, r = e & 3;
@@ -195,16 +217,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int c, int P, int S, c
     if (bi == bj && jj > ii) return;
     const int i = 16 * bi + ii, j = 16 * bj + jj;
     if (i >= c) return;                                      // j <= i
-    const T* w = ws + (int64_t)p * 256 + e;
-    const int64_t stride = (int64_t)P * 256;
-    T v0 = T(0), v1 = T(0);
-    int s = 0;
-    for (; s + 1 < S; s += 2) {
-        v0 += w[s * stride];
-        v1 += w[(s + 1) * stride];
-    }
-    if (s < S) v0 += w[s * stride];
-    T v = v0 + v1;
+    T v = (part[0][el] + part[1][el]) + (part[2][el] + part[3][el]);
     const T* xi = X + (int64_t)i * ldx;
     const T* xj = X + (int64_t)j * ldx;
     for (int64_t k = R0; k < R; ++k) v += xi[k] * xj[k];
@@ -266,9 +279,10 @@ __global__ __launch_bounds__(TR_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
         for (int t = 0; t < VEC; ++t) acc[q][t] = acc_t{0, 0, 0, 0};
     T b0[MAXB][4], b1[MAXB][4];
-    // L^{-1}(j, k) for k = 16 g + 4 (lane / 16) + s, j = 16 b_q + lane % 16:
-    // loads from clamped addresses (32-bit offsets: c <= 512), zero where
-    // k > j or j >= c
+    // L^{-1}(j, k) for k = 16 g + 4 (lane / 16) + s, j = 16 b_q + lane % 16,
+    // loaded raw from clamped addresses (32-bit offsets: c <= 512) so that the
+    // loads stay in flight; the diagonal group masks k > j at use (k >= c only
+    // occurs there), and columns j >= c are computed but never stored
     const int ldl32 = (int)ldl;
     auto load_b = [&](T (&bq)[MAXB][4], int g) {
 #pragma unroll
@@ -280,21 +294,26 @@ __global__ __launch_bounds__(TR_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
             for (int s = 0; s < 4; ++s) {
                 const int k = 16 * g + 4 * (lane >> 4) + s;
                 const int kc = k < c ? k : c - 1;
-                const T v = Li[jc + kc * ldl32];
-                bq[q][s] = (b >= g && j < c && k <= j) ? v : T(0);
+                bq[q][s] = Li[jc + kc * ldl32];
             }
         }
     };
     auto step = [&](const T (&bq)[MAXB][4], int g) {
+        vec_t a[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int k = 16 * g + 4 * (lane >> 4) + s;
-            const vec_t a = *(const vec_t*)(Xs + k * 256 + 16 * (lane & 15));
+        for (int s = 0; s < 4; ++s)
+            a[s] = *(const vec_t*)(Xs + (16 * g + 4 * (lane >> 4) + s) * 256 + 16 * (lane & 15));
 #pragma unroll
-            for (int q = 0; q < MAXB; ++q) {
-                if (bmax - 4 * q < g) continue;              // block done: k past its last column
+        for (int q = 0; q < MAXB; ++q) {
+            const int b = bmax - 4 * q;
+            if (b < g) continue;                             // block done: k past its last column
+            const bool diag = b == g;
 #pragma unroll
-                for (int t = 0; t < VEC; ++t) acc[q][t] = Mm::op(a[t], bq[q][s], acc[q][t]);
+            for (int s = 0; s < 4; ++s) {
+                const int k = 16 * g + 4 * (lane >> 4) + s;
+                const T bv = (!diag || k <= 16 * b + (lane & 15)) ? bq[q][s] : T(0);
+#pragma unroll
+                for (int t = 0; t < VEC; ++t) acc[q][t] = Mm::op(a[s][t], bv, acc[q][t]);
             }
         }
     };
@@ -408,7 +427,7 @@ int gram(int64_t R, int64_t c, const T* X, int64_t ldx, T* G, int64_t ldg, T* ws
             default: launch_gram<T, 4>(p, c, X, ldx, ws, gate, s); break;
         }
     }
-    hipLaunchKernelGGL((gram_reduce_kernel<T>), dim3((unsigned)p.P), dim3(256), 0, s, (int)c, p.P, (int)p.S, ws,
+    hipLaunchKernelGGL((gram_reduce_kernel<T>), dim3((unsigned)(4 * p.P)), dim3(256), 0, s, (int)c, p.P, (int)p.S, ws,
                        p.nfrag * KF, R, X, ldx, G, ldg, gate);
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
@@ -418,7 +437,8 @@ bool trmm_fits(int64_t R, int64_t c, const T* X, int64_t ldx, const T* Y, int64_
     constexpr int VEC = CqMfma<T>::VEC;
     // FP64 beyond 28 column blocks would spill (eight blocks per wave)
     const int64_t cmax = sizeof(T) == 8 ? 448 : CQ_MAXC;
-    return c >= 1 && c <= cmax && R >= VEC && R % VEC == 0 && ldx % VEC == 0 && ldy % VEC == 0 &&
+    // a workgroup per 16 VEC rows: below 16 workgroups the general product is faster
+    return c >= 1 && c <= cmax && R >= 16 * 16 * VEC && R % VEC == 0 && ldx % VEC == 0 && ldy % VEC == 0 &&
            aligned16(X) && aligned16(Y) && (const void*)X != (const void*)Y;
 }
 
