@@ -38,6 +38,7 @@ constexpr int MW_T = 256;
 constexpr int MW_NW = MW_T / 64;
 constexpr int MW_S = 17;                               // LDS row stride in doubles
 constexpr unsigned long long MW_SPIN_LIMIT = 1ull << 22;
+constexpr unsigned MW_EARLY = 0x80000000u;               // early-flag marker (epochs are odd, < 2^31 apart)
 constexpr int MW_MAXT = CHOL_MW_MAXC / 16 / MW_NW;       // row tiles per wave (at most)
 
 __device__ __forceinline__ double mw_readlane(double v, int l) {
@@ -167,21 +168,58 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
     }
     __syncthreads();
 
+    // The diagonal block, factored by wave 0: D = L_JJ^{-1} into Dv, L_JJ into
+    // tile 0 of Wc, breakdown into s_bad.
+    auto factor_diag = [&]() {
+        if (wave == 0) {
+            const int i = lane & 15, g = lane >> 4;
+            double d[4], x[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) d[e] = Wc[i * MW_S + 4 * g + e];
+            const bool bad = mw_factor_diag(d, x, lane);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                Wc[i * MW_S + 4 * g + e] = d[e];
+                Dv[i * MW_S + 4 * g + e] = x[e];
+            }
+            if (lane == 0) s_bad = bad ? 1 : 0;
+        }
+    };
+    // W(r0.., J) -= A B^T for one 16-row tile: a = L(rows, K), b = L(J, K)^T
+    auto update_tile = [&](int r0, const double (&a)[4], const double (&b)[4]) {
+        const bool in = j0 + r0 + fr < c;
+        double4_t acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = Wc[(r0 + fk + 4 * r) * MW_S + fr];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? -a[ks] : 0.0, b[ks], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Wc[(r0 + fk + 4 * r) * MW_S + fr] = acc[r];
+    };
+    // Flag words: owner K first stores MW_EARLY ^ epoch once the rows of block
+    // K + 1 of L(:, K) are published (all that owner K + 1 needs to update and
+    // factor its diagonal block), then epoch once all of L(:, K) and D_K are.
+    auto wait_flag = [&](int K, bool early_ok) {
+        if (tid == 0) {
+            unsigned long long spins = 0;
+            for (;;) {
+                const unsigned f = ld_coherent_u32(flags + K);
+                if (f == epoch || (early_ok && f == (epoch ^ MW_EARLY))) break;
+                if (++spins > MW_SPIN_LIMIT) {
+                    if (info) atomicOr(info, RQLP_INFO_BARRIER_TIMEOUT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __syncthreads();
+    };
+
     for (int K = 0; K < NB; ++K) {
         const int64_t kc = 16 * (int64_t)K;
-        if (K != J) {
-            if (tid == 0) {
-                unsigned long long spins = 0;
-                while (ld_coherent_u32(flags + K) != epoch) {
-                    if (++spins > MW_SPIN_LIMIT) {
-                        if (info) atomicOr(info, RQLP_INFO_BARRIER_TIMEOUT);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-            __syncthreads();
-        }
+        const bool ahead = K == J - 1;                  // the panel just before this workgroup's own step
+        if (K != J) wait_flag(K, ahead);
         if (K < J) {
             // W(:, J) -= L(:, K) L(J, K)^T over the rows j0.. of this block column
             // b = L(J, K)^T is the same for every tile of this workgroup
@@ -194,11 +232,22 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
 #pragma unroll
                 for (int ks = 0; ks < 4; ++ks) b[ks] = jt < c ? b[ks] : 0.0;
             }
+            int tfirst = 0;
+            if (ahead) {
+                // look-ahead: the diagonal tile (its panel rows are b) is updated and
+                // factored as soon as the rows of block J of L(:, K) are out; the
+                // other tiles wait for the whole panel
+                if (wave == 0) update_tile(0, b, b);
+                __syncthreads();
+                factor_diag();
+                wait_flag(K, false);                    // (its barrier also orders the factor)
+                tfirst = 1;
+            }
             // all panel loads of this wave's tiles are issued before the first use
             double a[MW_MAXT][4];
 #pragma unroll
             for (int q = 0; q < MW_MAXT; ++q) {
-                const int tile = wave + MW_NW * q;
+                const int tile = tfirst + wave + MW_NW * q;
                 const int i = j0 + 16 * tile + fr;
                 const int ic = (tile < nrt && i < c) ? i : c - 1;
 #pragma unroll
@@ -206,36 +255,17 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
             }
 #pragma unroll
             for (int q = 0; q < MW_MAXT; ++q) {
-                const int tile = wave + MW_NW * q;
+                const int tile = tfirst + wave + MW_NW * q;
                 if (tile >= nrt) break;
-                const int r0 = 16 * tile;
-                const bool in = j0 + r0 + fr < c;
-                double4_t acc;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r] = Wc[(r0 + fk + 4 * r) * MW_S + fr];
-#pragma unroll
-                for (int ks = 0; ks < 4; ++ks)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(in ? -a[q][ks] : 0.0, b[ks], acc, 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) Wc[(r0 + fk + 4 * r) * MW_S + fr] = acc[r];
+                update_tile(16 * tile, a[q], b);
             }
             __syncthreads();
         } else if (K == J) {
-            // ---- own step: diagonal factor, panel, publication ----
-            if (wave == 0) {
-                const int i = lane & 15, g = lane >> 4;
-                double d[4], x[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) d[e] = Wc[i * MW_S + 4 * g + e];
-                const bool bad = mw_factor_diag(d, x, lane);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    Wc[i * MW_S + 4 * g + e] = d[e];
-                    Dv[i * MW_S + 4 * g + e] = x[e];
-                }
-                if (lane == 0) s_bad = bad ? 1 : 0;
+            // ---- own step: diagonal factor (unless done ahead), panel, publication ----
+            if (J == 0) {
+                factor_diag();
+                __syncthreads();
             }
-            __syncthreads();
             if (s_bad && tid == 0) {
                 if (attempt == 0) {
                     if (info) atomicOr(info, RQLP_INFO_CHOLQR_SHIFTED);
@@ -244,7 +274,8 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
                     atomicOr(info, RQLP_INFO_CHOL_FAILED);
                 }
             }
-            // panel rows below the diagonal block: L(i, J) = W(i, J) D^T
+            // panel rows below the diagonal block: L(i, J) = W(i, J) D^T.  Tile 1
+            // (the rows of block J + 1) first, by wave 0, published at once
             for (int tile = 1 + wave; tile < nrt; tile += MW_NW) {
                 const int r0 = 16 * tile;
                 double a[4], b[4];
@@ -259,6 +290,18 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
                 for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], b[ks], acc, 0, 0, 0);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) Wc[(r0 + fk + 4 * r) * MW_S + fr] = acc[r];
+                if (tile == 1) {
+                    // accumulator r holds L(j0 + 16 + fk + 4 r, j0 + fr)
+                    if (fr < kb) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int i = j0 + 16 + fk + 4 * r;
+                            if (i < c) st_coherent(Lo + i + (int64_t)(j0 + fr) * ld, acc[r]);
+                        }
+                    }
+                    __builtin_amdgcn_s_waitcnt(0);
+                    if (lane == 0) st_coherent_u32(flags + J, epoch ^ MW_EARLY);
+                }
             }
             // X(J, J) = D
             for (int idx = tid; idx < 256; idx += MW_T) {
@@ -266,11 +309,11 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
                 Xc[r * MW_S + t] = (r >= t) ? Dv[r * MW_S + t] : 0.0;
             }
             __syncthreads();
-            // publish L(j0.., J) and D into the outputs, then raise flag J
+            // publish the rest of L(j0.., J) and D into the outputs, then raise flag J
             for (int idx = tid; idx < nrt * 16 * 16; idx += MW_T) {
                 const int r = idx >> 4, t = idx & 15;
                 const int i = j0 + r;
-                if (i >= c || t >= kb) continue;
+                if (i >= c || t >= kb || (r >= 16 && r < 32)) continue;
                 const int64_t col = j0 + t;
                 st_coherent(Lo + i + col * ld, r >= t ? Wc[r * MW_S + t] : 0.0);
                 if (r < 16) st_coherent(Xo + i + col * ld, r >= t ? Dv[r * MW_S + t] : 0.0);
