@@ -243,34 +243,67 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
     #pragma unroll
                     for (int ks = 0; ks < 4; ++ks) b[ks] = jt < c ? b[ks] : 0.0;
                 }
-                int tfirst = 0;
                 if (ahead) {
-                    // look-ahead: the diagonal tile (its panel rows are b) is updated and
-                    // factored as soon as the rows of block J of L(:, K) are out; the
-                    // other tiles wait for the whole panel
-                    if (wave == 0) update_tile(0, b, b);
+                    // look-ahead: wave 0 updates the diagonal tile (its panel rows are
+                    // b, out with the early flag) and factors it, while the other waves
+                    // wait for the whole panel and update the remaining tiles
+                    if (wave == 0) {
+                        update_tile(0, b, b);
+                        __builtin_amdgcn_wave_barrier();
+                        factor_diag();
+                    } else {
+                        if (lane == 0) {
+                            unsigned long long spins = 0;
+                            while (ld_coherent_u32(flags + K) != epoch) {
+                                if (++spins > MW_SPIN_LIMIT) {
+                                    if (info) atomicOr(info, RQLP_INFO_BARRIER_TIMEOUT);
+                                    break;
+                                }
+                                __builtin_amdgcn_s_sleep(1);
+                            }
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        constexpr int NW1 = MW_NW - 1;
+                        for (int q0 = 0; 1 + (wave - 1) + NW1 * q0 < nrt; q0 += MW_MAXT) {
+                            double a[MW_MAXT][4];
+    #pragma unroll
+                            for (int q = 0; q < MW_MAXT; ++q) {
+                                const int tile = 1 + (wave - 1) + NW1 * (q0 + q);
+                                const int i = j0 + 16 * tile + fr;
+                                const int ic = (tile < nrt && i < c) ? i : c - 1;
+    #pragma unroll
+                                for (int ks = 0; ks < 4; ++ks)
+                                    a[q][ks] = ld_coherent(Lo + ic + (kc + 4 * ks + fk) * ld);
+                            }
+    #pragma unroll
+                            for (int q = 0; q < MW_MAXT; ++q) {
+                                const int tile = 1 + (wave - 1) + NW1 * (q0 + q);
+                                if (tile >= nrt) break;
+                                update_tile(16 * tile, a[q], b);
+                            }
+                        }
+                    }
                     __syncthreads();
-                    factor_diag();
-                    wait_flag(K, false);                    // (its barrier also orders the factor)
-                    tfirst = 1;
-                }
-                // all panel loads of this wave's tiles are issued before the first use
-                double a[MW_MAXT][4];
+                } else {
+                    // all panel loads of this wave's tiles are issued before the first use
+                    double a[MW_MAXT][4];
     #pragma unroll
-                for (int q = 0; q < MW_MAXT; ++q) {
-                    const int tile = tfirst + wave + MW_NW * q;
-                    const int i = j0 + 16 * tile + fr;
-                    const int ic = (tile < nrt && i < c) ? i : c - 1;
+                    for (int q = 0; q < MW_MAXT; ++q) {
+                        const int tile = wave + MW_NW * q;
+                        const int i = j0 + 16 * tile + fr;
+                        const int ic = (tile < nrt && i < c) ? i : c - 1;
     #pragma unroll
-                    for (int ks = 0; ks < 4; ++ks) a[q][ks] = ld_coherent(Lo + ic + (kc + 4 * ks + fk) * ld);
-                }
+                        for (int ks = 0; ks < 4; ++ks) a[q][ks] = ld_coherent(Lo + ic + (kc + 4 * ks + fk) * ld);
+                    }
     #pragma unroll
-                for (int q = 0; q < MW_MAXT; ++q) {
-                    const int tile = tfirst + wave + MW_NW * q;
-                    if (tile >= nrt) break;
-                    update_tile(16 * tile, a[q], b);
+                    for (int q = 0; q < MW_MAXT; ++q) {
+                        const int tile = wave + MW_NW * q;
+                        if (tile >= nrt) break;
+                        update_tile(16 * tile, a[q], b);
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
             } else if (K == J) {
                 // ---- own step: diagonal factor (unless done ahead), panel, publication ----
                 if (J == 0) {
