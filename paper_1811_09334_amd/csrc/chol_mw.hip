@@ -54,11 +54,14 @@ __device__ __forceinline__ double mw_readlane(double v, int l) {
 // inverse X = L^{-1} (zero above the diagonal).  Returns true when a pivot
 // was non-positive or not finite (it is then replaced by 1).  Each column
 // step broadcasts the pivot with a read-lane and gathers L(i, j), L(k, j)
-// with lane shuffles; the inverse is the row sweep of L X = I.
+// with lane shuffles.  The row sweep of L X = I runs in the same loop: its
+// step j needs only L(i, j) and 1 / L(j, j) from the factor's step j, so the
+// two dependency chains overlap.
 __device__ bool mw_factor_diag(double d[4], double x[4], int lane) {
     const int i = lane & 15, g = lane >> 4;
     bool bad = false;
-    double rdiag[16];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) x[e] = (i == 4 * g + e) ? 1.0 : 0.0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int gj = j >> 2, ej = j & 3;
@@ -71,30 +74,26 @@ __device__ bool mw_factor_diag(double d[4], double x[4], int lane) {
         double rinv = __builtin_amdgcn_rsq(p);
         rinv = rinv * (1.5 - 0.5 * p * rinv * rinv);
         const double lj = p * rinv;
-        rdiag[j] = rinv;
         if (g == gj) d[ej] = (i == j) ? lj : (i > j ? d[ej] * rinv : 0.0);
-        const double lij = __shfl(d[ej], i + 16 * gj, 64);
+        // column j is read from the lanes of group gj, which the update below
+        // leaves alone; a copy keeps the shuffles independent of that update
+        const double colj = d[ej];
+        const double lij = __shfl(colj, i + 16 * gj, 64);          // L(i, j)
+        double lkj[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const double lkj = __shfl(d[ej], 4 * g + e + 16 * gj, 64);
-            if (4 * g + e > j) d[e] -= lij * lkj;
-        }
-    }
-    double lrow[16];                       // L(i, t) of this lane's row
+        for (int e = 0; e < 4; ++e) lkj[e] = __shfl(colj, 4 * g + e + 16 * gj, 64);
 #pragma unroll
-    for (int t = 0; t < 16; ++t) lrow[t] = __shfl(d[t & 3], i + 16 * (t >> 2), 64);
+        for (int e = 0; e < 4; ++e)
+            if (4 * g + e > j) d[e] -= lij * lkj[e];
+        // row sweep of L X = I: X(j, :) /= L(j, j), then X(i, :) -= L(i, j) X(j, :) below
+        if (i == j) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) x[e] = (i == 4 * g + e) ? 1.0 : 0.0;
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        if (i == t) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) x[e] *= rdiag[t];
+            for (int e = 0; e < 4; ++e) x[e] *= rinv;
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const double xt = __shfl(x[e], t + 16 * g, 64);
-            if (i > t) x[e] -= lrow[t] * xt;
+            const double xt = __shfl(x[e], j + 16 * g, 64);
+            if (i > j) x[e] -= lij * xt;
         }
     }
     return bad;
