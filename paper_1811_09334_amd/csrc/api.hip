@@ -357,10 +357,15 @@ struct BcgsScratch {
 // step 5 of Algorithm 4.1) over the rows x l panel V whose bs-column blocks
 // are already orthonormal: for every block j > 0, twice,
 // V_j <- V_j - V_{<j} (V_{<j}^T V_j), V_j <- qr(V_j).
+// Block Gram-Schmidt twice (BCGS2) of the blocks of bs columns after the
+// first (already orthonormal): each block is projected against the earlier
+// blocks and orthonormalised in place, twice; the first QR is one CholeskyQR
+// pass (with the conditional passes after a shifted retry), the second the
+// full form when `final` (CholeskyQR2), again one pass otherwise.
 template <typename T, typename CtxT>
-int bcgs2(CtxT& cx, int64_t rows, int64_t l, int64_t bs, T* V, int64_t ld, BcgsScratch& sc, hipStream_t s) {
+int bcgs2(CtxT& cx, int64_t rows, int64_t l, int64_t bs, T* V, int64_t ld, BcgsScratch& sc, bool final,
+          hipStream_t s) {
     T* C = (T*)sc.C;
-    T* p0 = (T*)sc.p0;
     T* p1 = (T*)sc.p1;
     T* ws = (T*)sc.ws;
     for (int64_t s0 = bs; s0 < l; s0 += bs) {
@@ -369,15 +374,15 @@ int bcgs2(CtxT& cx, int64_t rows, int64_t l, int64_t bs, T* V, int64_t ld, BcgsS
         for (int pass = 0; pass < 2; ++pass) {
             RQLP_TRY(gemm<T>(true, false, s0, bj, rows, V, ld, Vj, ld, C, s0, false, T(1), T(0), ws, sc.ws_elems, s));
             RQLP_TRY(gemm<T>(false, false, rows, bj, s0, V, ld, C, s0, Vj, ld, false, T(-1), T(1), ws, sc.ws_elems, s));
+            const bool full = pass == 1 && final;
             T* o = nullptr;
             if constexpr (sizeof(T) == sizeof(double)) {
-                RQLP_TRY(copy_matrix(rows, bj, (const double*)Vj, ld, (double*)p0, rows, s));
-                RQLP_TRY(cholqr2(cx, rows, bj, (double*)p0, (double*)p1, rows, nullptr, (double**)&o, true));
-                RQLP_TRY(copy_matrix(rows, bj, (const double*)o, rows, (double*)Vj, ld, s));
+                RQLP_TRY(cholqr2(cx, rows, bj, (double*)Vj, (double*)p1, ld, nullptr, (double**)&o, full));
+                if ((void*)o != (void*)Vj) RQLP_TRY(copy_matrix(rows, bj, (const double*)o, ld, (double*)Vj, ld, s));
             } else {
-                RQLP_TRY((cast_matrix<float, float>(rows, bj, (const float*)Vj, ld, (float*)p0, rows, s)));
-                RQLP_TRY(cholqr_f32(cx, rows, bj, (float*)p0, (float*)p1, rows, (float**)&o, true));
-                RQLP_TRY((cast_matrix<float, float>(rows, bj, (const float*)o, rows, (float*)Vj, ld, s)));
+                RQLP_TRY(cholqr_f32(cx, rows, bj, (float*)Vj, (float*)p1, ld, (float**)&o, full));
+                if ((void*)o != (void*)Vj)
+                    RQLP_TRY((cast_matrix<float, float>(rows, bj, (const float*)o, ld, (float*)Vj, ld, s)));
             }
         }
     }
@@ -385,39 +390,31 @@ int bcgs2(CtxT& cx, int64_t rows, int64_t l, int64_t bs, T* V, int64_t ld, BcgsS
 }
 
 // Orthonormalisation of a rows x l panel: as a whole (bs == 0, CholeskyQR),
-// or by blocks of bs columns (the last one ragged): a QR of every block,
-// then block Gram-Schmidt twice against the earlier blocks.  Both forms are
-// triangular (column j of the result lies in the span of columns 0..j of
-// the input), so the leading blocks of the range finder's basis span the
-// images of the leading blocks of Omega: the blocks of Algorithm 4.1.  The
-// result is in *out (buf0 or buf1).
+// or by blocks of bs columns (the last one ragged): a QR of the first block,
+// then block Gram-Schmidt twice for the others.  Both forms are triangular
+// (column j of the result lies in the span of columns 0..j of the input), so
+// the leading blocks of the range finder's basis span the images of the
+// leading blocks of Omega: the blocks of Algorithm 4.1.  The result is in
+// *out (buf0 or buf1).
 int ortho_f64(Ctx& cx, int64_t rows, int64_t l, int64_t bs, double* buf0, double* buf1, int64_t ld, double** out,
               bool final, BcgsScratch& bc) {
     if (bs <= 0 || bs >= l) return cholqr2(cx, rows, l, buf0, buf1, ld, nullptr, out, final);
-    double* res = buf0;
-    for (int64_t s0 = 0; s0 < l; s0 += bs) {
-        const int64_t bj = (l - s0) < bs ? (l - s0) : bs;
-        double* o = nullptr;
-        RQLP_TRY(cholqr2(cx, rows, bj, buf0 + s0 * ld, buf1 + s0 * ld, ld, nullptr, &o, final));
-        res = (o == buf0 + s0 * ld) ? buf0 : buf1;
-    }
-    RQLP_TRY((bcgs2<double, Ctx>(cx, rows, l, bs, res, ld, bc, cx.s)));
-    *out = res;
+    double* o = nullptr;
+    RQLP_TRY(cholqr2(cx, rows, bs, buf0, buf1, ld, nullptr, &o, final));
+    if (o != buf0) RQLP_TRY(copy_matrix(rows, bs, o, ld, buf0, ld, cx.s));
+    RQLP_TRY((bcgs2<double, Ctx>(cx, rows, l, bs, buf0, ld, bc, final, cx.s)));
+    *out = buf0;
     return 0;
 }
 
 int ortho_f32(Ctx32& cx, int64_t rows, int64_t l, int64_t bs, float* buf0, float* buf1, int64_t ld, float** out,
               bool final, BcgsScratch& bc) {
     if (bs <= 0 || bs >= l) return cholqr_f32(cx, rows, l, buf0, buf1, ld, out, final);
-    float* res = buf0;
-    for (int64_t s0 = 0; s0 < l; s0 += bs) {
-        const int64_t bj = (l - s0) < bs ? (l - s0) : bs;
-        float* o = nullptr;
-        RQLP_TRY(cholqr_f32(cx, rows, bj, buf0 + s0 * ld, buf1 + s0 * ld, ld, &o, final));
-        res = (o == buf0 + s0 * ld) ? buf0 : buf1;
-    }
-    RQLP_TRY((bcgs2<float, Ctx32>(cx, rows, l, bs, res, ld, bc, cx.s)));
-    *out = res;
+    float* o = nullptr;
+    RQLP_TRY(cholqr_f32(cx, rows, bs, buf0, buf1, ld, &o, final));
+    if (o != buf0) RQLP_TRY((cast_matrix<float, float>(rows, bs, o, ld, buf0, ld, cx.s)));
+    RQLP_TRY((bcgs2<float, Ctx32>(cx, rows, l, bs, buf0, ld, bc, final, cx.s)));
+    *out = buf0;
     return 0;
 }
 
