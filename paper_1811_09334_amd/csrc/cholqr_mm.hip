@@ -108,9 +108,9 @@ __global__ __launch_bounds__(GR_THREADS) void gram_kernel(int c, const T* __rest
     // column blocks this workgroup needs: 0 .. block row of its last pair
     int plast = pg0 + GR_WAVES * GR_BPW - 1;
     if (plast > P - 1) plast = P - 1;
-    int nbl, tmp;
-    cq_pair(plast, nbl, tmp);
-    nbl += 1;
+    int bil = 0, bjl = 0;
+    cq_pair(plast, bil, bjl);
+    const int nbl = bil + 1;                                // column blocks 0 .. bil (bjl <= bil)
 
     // copy slots: block b = wave + 8 i; slots past nbl copy into the sink
     const char* src[OPS];
