@@ -228,6 +228,111 @@ __device__ __forceinline__ bool grid_agree(unsigned* bar, int G, unsigned& gen, 
     return s_ok != 0;
 }
 
+// Pivot agreement of the register-resident kernel through one key slot per
+// workgroup and step instead of arrival counters (atomics on one address are
+// serialised, about 20 ns each): once its column stores are complete, every
+// workgroup stores its two keys, tagged with bit 63, into its own slot of the
+// step (the slots are zero-filled before the launch); the last workgroup polls
+// all slots with one wave, decides, and publishes the result with the new
+// generation in the 64-bit word gw, which the others poll.  Keys of finite
+// norms never have bit 63 set (norms are >= 0, the index key has only index
+// bits), so the tag changes no comparison (a NaN norm loses its sign bit and
+// still ranks above every finite one).  Bounded waits as in grid_sync_decide.
+template <typename F>
+__device__ __forceinline__ bool slot_agree(unsigned long long* slots, unsigned long long* gw, int G, unsigned& gen,
+                                           unsigned& payload, int32_t* info, unsigned long long spin_limit,
+                                           unsigned long long lk0, unsigned long long lk1, F decide) {
+    constexpr unsigned long long TAG = 1ull << 63;
+    __shared__ int s_ok;
+    __shared__ unsigned s_pay;
+    const unsigned g = gen;
+    drain_and_sync();                                    // this workgroup's column stores are complete
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(slots + 2 * blockIdx.x, lk0 | TAG, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(slots + 2 * blockIdx.x + 1, lk1 | TAG, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if ((int)blockIdx.x == G - 1) {
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            unsigned long long m0 = 0, m1 = 0;
+            int ok = 1;
+            // slots h0 + lane + 64 u, all loads of a poll in flight together
+            for (int h0 = 0; h0 < G && ok; h0 += 256) {
+                unsigned long long spins = 0;
+                while (true) {
+                    unsigned long long a[4], c[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int h = h0 + lane + 64 * u;
+                        a[u] = TAG;
+                        c[u] = TAG;
+                        if (h < G) {
+                            a[u] = __hip_atomic_load(slots + 2 * h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            c[u] = __hip_atomic_load(slots + 2 * h + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                    int here = 1;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) here &= (int)((a[u] & c[u]) >> 63);
+                    if (__all(here)) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const unsigned long long ka = a[u] & ~TAG, kc = c[u] & ~TAG;
+                            m0 = ka > m0 ? ka : m0;
+                            m1 = kc > m1 ? kc : m1;
+                        }
+                        break;
+                    }
+                    if (++spins > spin_limit) {
+                        ok = 0;
+                        if (lane == 0 && info) atomicOr(info, RQLP_INFO_BARRIER_TIMEOUT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const unsigned long long a = shfl_xor_u64(m0, off), c = shfl_xor_u64(m1, off);
+                m0 = a > m0 ? a : m0;
+                m1 = c > m1 ? c : m1;
+            }
+            if (lane == 0) {
+                unsigned pay = 0;
+                if (ok) {
+                    pay = decide(m0, m1);
+                    __hip_atomic_store(gw, ((unsigned long long)(g + 1u) << 32) | pay, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                }
+                s_pay = pay;
+                s_ok = ok;
+            }
+        }
+    } else if (threadIdx.x == 0) {
+        int ok = 1;
+        unsigned pay = 0;
+        unsigned long long spins = 0;
+        while (true) {
+            const unsigned long long w = __hip_atomic_load(gw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((unsigned)(w >> 32) != g) {
+                pay = (unsigned)w;
+                break;
+            }
+            if (++spins > spin_limit) {
+                ok = 0;
+                if (info) atomicOr(info, RQLP_INFO_BARRIER_TIMEOUT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        s_pay = pay;
+        s_ok = ok;
+    }
+    __syncthreads();
+    gen = g + 1u;
+    payload = s_pay;
+    return s_ok != 0;
+}
+
 template <bool SINGLE>
 __global__ __launch_bounds__(CP_T) void cpqr_kernel(
     const double* __restrict__ M, int64_t ldm, int rows, int cols, int cpw, int kmax, int ibits,
@@ -512,8 +617,8 @@ constexpr int CPR_CPW = 64;                  // columns per workgroup
 #ifndef CPR_GROUP
 #define CPR_GROUP 16                         // workgroups per arrival counter
 #endif
-// scratch words of grid_agree<CPR_GROUP> (key slots per step, counters + generation)
-__host__ __device__ constexpr int cpr_key_words(int G) { return 16 * ((G + CPR_GROUP - 1) / CPR_GROUP + 1); }
+// scratch words: key slots of one step (slot_agree), counters + generation word (grid_agree<CPR_GROUP>)
+__host__ __device__ constexpr int cpr_key_words(int G) { return 2 * G; }
 __host__ __device__ constexpr int cpr_bar_words(int G) { return 32 * ((G + CPR_GROUP - 1) / CPR_GROUP + 2); }
 
 template <int RPT>
@@ -536,6 +641,8 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
     const int r0 = qd * RPT;                             // first row held by this lane
     int col[CPR_CT], act[CPR_CT];                        // act: -1 active, >= 0 pivot step, -2 no column
     unsigned gen = 0;
+    // generation word of grid_agree<CPR_GROUP>, also the result word of slot_agree
+    unsigned long long* gw = (unsigned long long*)(bar + 32 * ((G + CPR_GROUP - 1) / CPR_GROUP + 1));
 
     double x[CPR_CT][RPT];
 #pragma unroll
@@ -656,7 +763,7 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
                 return win | (stopnow << 31);
             };
             unsigned long long* ks = keys + (size_t)j * cpr_key_words(G);
-            if (!grid_agree<CPR_GROUP>(bar, G, gen, pay, info, spin_limit, ks, lk0, lk1, decide)) return;
+            if (!slot_agree(ks, gw, G, gen, pay, info, spin_limit, lk0, lk1, decide)) return;
         }
         const int now_stopped = stopped | (int)(pay >> 31);
         const int gidx = (int)(pay & 0x7FFFFFFFu);
