@@ -542,7 +542,7 @@ __global__ __launch_bounds__(256) void colexp_kernel(int64_t rows, const float* 
 // *gexp = max_j colexp[j]; one workgroup.
 __global__ __launch_bounds__(256) void gexp_kernel(int64_t n, const int* __restrict__ colexp, int* __restrict__ gexp) {
     __shared__ int red[4];
-    int mx = -1 << 30;
+    int mx = -(1 << 30);
     for (int64_t j = threadIdx.x; j < n; j += 256) mx = max(mx, colexp[j]);
     for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
