@@ -25,7 +25,9 @@
 // Numerical-rank stop: when the largest residual norm is <= max(rows, cols)
 // * eps * ||M||_F, the remaining steps take the smallest-index active columns,
 // apply no reflection, and the trailing rows of R are zero.
-// With G = 1 the exchange goes through LDS only.
+// With G = 1 the exchange goes through LDS only.  The register-resident
+// kernel (cpqr_reg_kernel, below) agrees through per-workgroup key slots
+// instead of the counters of step 2 (slot_agree).
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -600,8 +602,8 @@ __global__ __launch_bounds__(CP_T) void cpqr_kernel(
 // consecutive rows 16-group (l % 16) of the 4 columns 4 t + l / 16 (t < 4)
 // of its wave.  A step reads this lane's slice of the reflector v from LDS
 // once and reuses it for its 4 columns; the dot products and norms reduce
-// over the 16 lanes of a column with shuffles.  Pivot agreement, reflector
-// and bookkeeping are those of cpqr_kernel.
+// over the 16 lanes of a column with shuffles.  The reflector and the
+// bookkeeping are those of cpqr_kernel; the pivot agreement is slot_agree.
 // lane permutation of a double within DPP rows of 16 lanes
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
