@@ -134,99 +134,43 @@ __device__ __forceinline__ bool grid_sync_decide(unsigned* bar, int G, unsigned&
     return s_ok != 0;
 }
 
-// Pivot agreement of the register-resident kernel, with fewer dependent
-// round trips to memory than grid_sync_decide: the key maxima are issued
-// together with the candidate column (one completion wait for both), the
-// arrival counters grow monotonically (no resets), a group's last arriver only
-// forwards its arrival, and the very last arriver reads the maxima of all
-// groups (one thread per group slot), decides, and publishes the result with
-// the new generation.  Bounded waits as in grid_sync_decide.
-template <int GRP, typename F>
-__device__ __forceinline__ bool grid_agree(unsigned* bar, int G, unsigned& gen, unsigned& payload, int32_t* info,
-                                           unsigned long long spin_limit, unsigned long long* kslots,
-                                           unsigned long long lk0, unsigned long long lk1, F decide) {
-    __shared__ int s_last, s_ok;
-    __shared__ unsigned s_pay;
-    __shared__ unsigned long long s_m[2][CP_T / 64];
+// Grid barrier of the register-resident kernel (once per factorisation, for
+// the Frobenius norm): arrival counters of groups of GRP workgroups that grow
+// monotonically (no resets); a group's last arriver forwards its arrival to
+// the top counter, and the very last arriver publishes the new generation in
+// the 64-bit word gw (the result word of slot_agree), which the others poll.
+// Bounded waits as in grid_sync_decide.
+template <int GRP>
+__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned long long* gw, int G, unsigned& gen,
+                                             int32_t* info, unsigned long long spin_limit) {
+    __shared__ int s_ok;
     const int ng = (G + GRP - 1) / GRP;
     const int grp = (int)blockIdx.x / GRP;
     const unsigned gsz = (unsigned)((G - grp * GRP) < GRP ? (G - grp * GRP) : GRP);
     unsigned* cnt = bar + 32 * grp;
     unsigned* top = bar + 32 * ng;
-    unsigned long long* gw = (unsigned long long*)(bar + 32 * (ng + 1));
     const unsigned g = gen;
-    if (threadIdx.x == 0 && kslots && lk0 != 0) {
-        atomicMax(kslots + 16 * grp, lk0);
-        atomicMax(kslots + 16 * grp + 1, lk1);
-    }
-    drain_and_sync();                                    // this workgroup's column stores and maxima are done
+    drain_and_sync();                                    // this workgroup's stores are done
     if (threadIdx.x == 0) {
-        int last = 0;
-        if (__hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gsz * (g + 1u) - 1u &&
-            __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)ng * (g + 1u) - 1u)
-            last = 1;
-        s_last = last;
-    }
-    __syncthreads();
-    if (s_last) {
-        unsigned long long m0 = 0, m1 = 0;
-        if (kslots) {
-            for (int h = threadIdx.x; h < ng; h += CP_T) {
-                const unsigned long long a = __hip_atomic_load(kslots + 16 * h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned long long c =
-                    __hip_atomic_load(kslots + 16 * h + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                m0 = a > m0 ? a : m0;
-                m1 = c > m1 ? c : m1;
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                const unsigned long long a = shfl_xor_u64(m0, off), c = shfl_xor_u64(m1, off);
-                m0 = a > m0 ? a : m0;
-                m1 = c > m1 ? c : m1;
-            }
-            if ((threadIdx.x & 63) == 0) {
-                s_m[0][threadIdx.x >> 6] = m0;
-                s_m[1][threadIdx.x >> 6] = m1;
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            if (kslots) {
-                m0 = 0;
-                m1 = 0;
-                for (int w = 0; w < CP_T / 64; ++w) {
-                    m0 = s_m[0][w] > m0 ? s_m[0][w] : m0;
-                    m1 = s_m[1][w] > m1 ? s_m[1][w] : m1;
-                }
-            }
-            const unsigned pay = decide(m0, m1);
-            __hip_atomic_store(gw, ((unsigned long long)(g + 1u) << 32) | pay, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            s_pay = pay;
-            s_ok = 1;
-        }
-    } else if (threadIdx.x == 0) {
         int ok = 1;
-        unsigned pay = 0;
-        unsigned long long spins = 0;
-        while (true) {
-            const unsigned long long w = __hip_atomic_load(gw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((unsigned)(w >> 32) != g) {
-                pay = (unsigned)w;
-                break;
+        if (__hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gsz * (g + 1u) - 1u &&
+            __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (unsigned)ng * (g + 1u) - 1u) {
+            __hip_atomic_store(gw, (unsigned long long)(g + 1u) << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned long long spins = 0;
+            while ((unsigned)(__hip_atomic_load(gw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32) == g) {
+                if (++spins > spin_limit) {
+                    ok = 0;
+                    if (info) atomicOr(info, RQLP_INFO_BARRIER_TIMEOUT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
             }
-            if (++spins > spin_limit) {
-                ok = 0;
-                if (info) atomicOr(info, RQLP_INFO_BARRIER_TIMEOUT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
         }
-        s_pay = pay;
         s_ok = ok;
     }
     __syncthreads();
     gen = g + 1u;
-    payload = s_pay;
     return s_ok != 0;
 }
 
@@ -619,7 +563,7 @@ constexpr int CPR_CPW = 64;                  // columns per workgroup
 #ifndef CPR_GROUP
 #define CPR_GROUP 16                         // workgroups per arrival counter
 #endif
-// scratch words: key slots of one step (slot_agree), counters + generation word (grid_agree<CPR_GROUP>)
+// scratch words: key slots of one step (slot_agree), counters + generation word (grid_barrier<CPR_GROUP>)
 __host__ __device__ constexpr int cpr_key_words(int G) { return 2 * G; }
 __host__ __device__ constexpr int cpr_bar_words(int G) { return 32 * ((G + CPR_GROUP - 1) / CPR_GROUP + 2); }
 
@@ -643,7 +587,7 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
     const int r0 = qd * RPT;                             // first row held by this lane
     int col[CPR_CT], act[CPR_CT];                        // act: -1 active, >= 0 pivot step, -2 no column
     unsigned gen = 0;
-    // generation word of grid_agree<CPR_GROUP>, also the result word of slot_agree
+    // generation word of grid_barrier<CPR_GROUP>, also the result word of slot_agree
     unsigned long long* gw = (unsigned long long*)(bar + 32 * ((G + CPR_GROUP - 1) / CPR_GROUP + 1));
 
     double x[CPR_CT][RPT];
@@ -687,12 +631,7 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
         for (int w = 0; w < CP_T / 64; ++w) f += s_red[w];
         st_coherent(partial + g, f);
     }
-    {
-        unsigned pay;
-        if (!grid_agree<CPR_GROUP>(bar, G, gen, pay, info, spin_limit, nullptr, 0ull, 0ull,
-                        [](unsigned long long, unsigned long long) { return 0u; }))
-            return;
-    }
+    if (!grid_barrier<CPR_GROUP>(bar, gw, G, gen, info, spin_limit)) return;
     if (tid == 0) {
         double f = 0.0;
         for (int h = 0; h < G; ++h) f += ld_coherent(partial + h);
