@@ -576,7 +576,6 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
     __shared__ double cst[CPR_RG * RPT];             // staging of the published column
     __shared__ double s_red[CP_T / 64];
     __shared__ unsigned long long s_kred[2][CP_T / 64];
-    __shared__ unsigned long long s_key[2];
     __shared__ double s_beta, s_mu, s_tol2;
     __shared__ int s_stop, s_rank;
 
@@ -665,20 +664,17 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
             s_kred[1][wave] = k1;
         }
         __syncthreads();
-        if (tid == 0) {
-            unsigned long long a = 0, b = 0;
-            for (int w = 0; w < CP_T / 64; ++w) {
-                a = s_kred[0][w] > a ? s_kred[0][w] : a;
-                b = s_kred[1][w] > b ? s_kred[1][w] : b;
-            }
-            s_key[0] = a;
-            s_key[1] = b;
-        }
-        __syncthreads();
         // ---- 2. publish the local best column, agree on the pivot ----
+        // (every thread combines the wave maxima itself; s_kred is written
+        // again only after the barriers of this step's agreement)
         unsigned pay = 0;
         {
-            const unsigned long long lk0 = s_key[0], lk1 = s_key[1];
+            unsigned long long lk0 = 0, lk1 = 0;
+#pragma unroll
+            for (int w = 0; w < CP_T / 64; ++w) {
+                lk0 = s_kred[0][w] > lk0 ? s_kred[0][w] : lk0;
+                lk1 = s_kred[1][w] > lk1 ? s_kred[1][w] : lk1;
+            }
             const double tol2 = s_tol2;
             if (lk0 != 0 && !stopped) {
                 // the 16 owner lanes stage the column in LDS, then all threads publish it
