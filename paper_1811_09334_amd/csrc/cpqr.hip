@@ -1008,7 +1008,7 @@ int cpqr(const double* M, int64_t ldm, int64_t rows, int64_t cols, const CpqrScr
 
 // ---------------------------------------------------------------------------
 // Y = H_0 H_1 ... H_{k-1} X, one wave per column, the column held in registers
-// (RPL rows per lane), the next reflector prefetched while the current one is
+// (RPL rows per lane), the next reflectors prefetched while the current one is
 // applied.
 template <int RPL>
 __global__ __launch_bounds__(256) void apply_householder_kernel(int rows, int k, const double* __restrict__ Vh,
@@ -1026,39 +1026,54 @@ __global__ __launch_bounds__(256) void apply_householder_kernel(int rows, int k,
         const int i = lane + 64 * r;
         x[r] = (i < rows) ? (X ? X[i + (int64_t)col * ldx] : (i == u ? 1.0 : 0.0)) : 0.0;
     }
-    double vn[RPL];
     if (k > 0) {
+        // D reflectors in flight in a ring of registers (the loop is unrolled
+        // by D, so no register is copied while its load is outstanding); the
+        // loads are unconditional from clamped rows (no branches that would
+        // make the compiler wait for all of them), rows past the end are
+        // masked where they are used
+        constexpr int D = 4;
+        int ic[RPL];
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int i = lane + 64 * r;
-            vn[r] = (i < rows) ? Vh[i + (int64_t)(k - 1) * ldv] : 0.0;
+            ic[r] = i < rows ? i : rows - 1;
         }
-    }
-    for (int j = k - 1; j >= 0; --j) {
-        double vc[RPL];
+        double vb[D][RPL];
+        auto load = [&](double (&v)[RPL], int j) {
+            const double* p = Vh + (int64_t)(j > 0 ? j : 0) * ldv;
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) vc[r] = vn[r];
-        const double bj = beta[j];
-        if (j > 0) {
+            for (int r = 0; r < RPL; ++r) v[r] = p[ic[r]];
+        };
+        auto apply = [&](const double (&v)[RPL], int j) {
+            const double bj = beta[j];
+            double dot = 0.0;
 #pragma unroll
             for (int r = 0; r < RPL; ++r) {
                 const int i = lane + 64 * r;
-                vn[r] = (i < rows) ? Vh[i + (int64_t)(j - 1) * ldv] : 0.0;
+                dot += (i >= j && i < rows) ? v[r] * x[r] : 0.0;
+            }
+            dot = wave_sum(dot);
+            const double w = bj * dot;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = lane + 64 * r;
+                if (i >= j && i < rows) x[r] -= w * v[r];
+            }
+        };
+#pragma unroll
+        for (int d = 0; d < D; ++d) load(vb[d], k - 1 - d);
+        int j = k - 1;
+        for (; j >= D - 1; j -= D) {                  // vb[d] holds reflector j - d
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                apply(vb[d], j - d);
+                load(vb[d], j - d - D);
             }
         }
-        double dot = 0.0;
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            const int i = lane + 64 * r;
-            dot += (i >= j) ? vc[r] * x[r] : 0.0;
-        }
-        dot = wave_sum(dot);
-        const double w = bj * dot;
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            const int i = lane + 64 * r;
-            if (i >= j) x[r] -= w * vc[r];
-        }
+        for (int d = 0; d < D - 1; ++d)
+            if (d <= j) apply(vb[d], j - d);          // the last j + 1 reflectors
     }
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
