@@ -205,3 +205,79 @@ def test_paper_table_orderings(example):
     e_q = lvalue_abs_err(np.diag(L), sig, k)
     assert e_4 < e_r
     assert 0.3 < e_r / e_q < 3.0
+
+
+# ---------------------------------------------------------------------------
+# the q > 0 subspace iteration of the range finder, pinned by closed forms
+# ---------------------------------------------------------------------------
+def _two_level(m, n, r, rho, seed):
+    """A = U diag(1 (r times), rho (n - r times)) V^T with U, V Haar; returns (A, U, V)."""
+    rng = np.random.default_rng(seed)
+    U = inputs.haar_columns(rng, m, n)
+    Vr = inputs.haar_columns(rng, n, n)
+    s = np.r_[np.ones(r), np.full(n - r, rho)]
+    return (U * s) @ Vr.T, U, Vr
+
+
+def _tan_max(U1, V):
+    """Largest principal angle tangent between span(U1) and span(V) (equal dimensions)."""
+    c = np.linalg.svd(U1.T @ V, compute_uv=False)
+    cmin = c.min()
+    return np.sqrt(max(0.0, 1.0 - cmin * cmin)) / cmin
+
+
+@pytest.mark.parametrize("q", [0, 1, 2, 3])
+def test_range_finder_angles_follow_closed_form(q):
+    """For s = (1, ..., 1, rho, ..., rho) with r = l ones, (A A^T)^q A Omega =
+    U [Om1; rho^(2q+1) Om2] with Om1 = V1^T Omega (l x l), Om2 = V2^T Omega, so
+    the principal-angle tangents between range(V) and U_l are exactly the
+    singular values of rho^(2q+1) Om2 Om1^-1 (subspace iteration has the range
+    of the power iteration in exact arithmetic)."""
+    m, n, k, p, rho = 60, 40, 6, 3, 0.3
+    l = k + p
+    A, U, Vr = _two_level(m, n, l, rho, 31)
+    Om = inputs.gaussian(n, l, 32)
+    Om1, Om2 = Vr[:, :l].T @ Om, Vr[:, l:].T @ Om
+    expect = rho ** (2 * q + 1) * np.linalg.norm(Om2 @ np.linalg.inv(Om1), 2)
+    V = range_finder(A, Om, q)
+    assert np.abs(V.T @ V - np.eye(l)).max() < 1e-13
+    got = _tan_max(U[:, :l], V)
+    assert abs(got - expect) <= 1e-9 * expect + 1e-14, (got, expect)
+    # the whole pipeline runs the same range finder: B = V^T A has the same row space
+    r = rqlp(A, Om, k, p, q=q)
+    assert abs(_tan_max(U[:, :l], r.Q) - expect) <= 1e-9 * expect + 1e-14
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_range_finder_spans_power_iterate(q):
+    """range(V) = range((A A^T)^q A Omega) on a small well-conditioned case
+    (the unstabilised power iterate is formed directly; projectors agree)."""
+    m, n, k, p = 30, 20, 3, 2
+    A = _mat(m, n, np.linspace(1.0, 0.5, n), seed=33)
+    Om = inputs.gaussian(n, k + p, 34)
+    Y = A @ Om
+    for _ in range(q):
+        Y = A @ (A.T @ Y)
+    Qd, _ = np.linalg.qr(Y)
+    V = range_finder(A, Om, q)
+    assert np.linalg.norm(V @ V.T - Qd @ Qd.T, 2) < 1e-12
+    # and it is a different subspace from the q = 0 sketch (the iteration matters)
+    V0 = range_finder(A, Om, 0)
+    assert np.linalg.norm(V @ V.T - V0 @ V0.T, 2) > 1e-3
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_block_range_finder_spans_power_iterate_of_leading_blocks(q):
+    """Block RQLP: the first j blocks of V span (A A^T)^q A Omega_{<=j} (each
+    block's power iterate, reorthogonalised against the earlier ones)."""
+    m, n, k, p, b = 40, 24, 6, 3, 4          # l = 9 = 4 + 4 + 1
+    A = _mat(m, n, np.linspace(1.0, 0.4, n), seed=35)
+    Om = inputs.gaussian(n, k + p, 36)
+    rb = brqlp(A, Om, k, p, b, q=q, deflate=False)
+    for s1 in (4, 8, 9):
+        Y = A @ Om[:, :s1]
+        for _ in range(q):
+            Y = A @ (A.T @ Y)
+        Qd, _ = np.linalg.qr(Y)
+        Vj = rb.V[:, :s1]
+        assert np.linalg.norm(Vj @ Vj.T - Qd @ Qd.T, 2) < 1e-11
