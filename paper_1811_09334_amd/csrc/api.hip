@@ -53,35 +53,75 @@ struct Ctx {
     int32_t* shifted;   // device word: the first pass used the shifted retry
 };
 
-// CholeskyQR2 of the rows x c panel held in buf0 (leading dimension ld):
-// two passes of G = X^T X, G = L L^T, X <- X L^{-T}.  Returns the buffer
-// holding the orthonormal result (buf0 or buf1; buf0 is overwritten).  RT
-// (c x c, optional) receives R^T = L1 L2 (lower triangular), where
-// X_in = V R is the QR factorisation with diag(R) > 0.
-// With final == false (an intermediate basis of the subspace iteration,
-// which only has to span range(X) and be well conditioned) the second pass
-// runs only when the first Cholesky needed the shifted retry; it is then
-// gated on the device word cx.shifted and a skipped pass copies X through.
+// Relative pivot below which the plain attempt of an FP64 CholeskyQR pass
+// counts as a breakdown: a column whose component outside the span of the
+// earlier columns is below ~1e-6 of its norm (pivot ratio 1e-12) is
+// numerically dependent, and the pass takes the shifted retry instead.
+constexpr double kPivotRel = 1e-12;
+// Squared column norm below which a column is numerically zero after a
+// shifted first pass (its healthy columns have norm ~1): it is replaced by a
+// random vector (orthonormal completion).
+constexpr double kZeroCol2 = 1e-12;
+
+// CholeskyQR of the rows x c panel held in buf0 (leading dimension ld):
+// passes of G = X^T X, G = L L^T, X <- X L^{-T}.  Returns the buffer holding
+// the orthonormal result (buf0 or buf1; buf0 is overwritten).  RT (c x c,
+// optional) receives R^T = L1 L2 ... (lower triangular), where X_in = V R
+// with diag(R) >= 0.
+// final == true (a basis that is returned): CholeskyQR2, plus two more passes
+// when any pass needed the shifted retry (device word cx.shifted, sticky
+// over the call).  A shifted first pass also marks input that is
+// numerically rank deficient (kPivotRel): its dependent directions are
+// then still tiny, and each shifted pass scales them up by about
+// 1 / sqrt(shift), so a shifted CholeskyQR3 does not always reach an
+// orthonormal basis, while four passes do; columns that are exactly zero
+// (R0^T after a rank stop) never grow and are replaced by random vectors
+// after the first pass (complete_columns), which also zeroes their rows of
+// R.  The conditional passes 3 and 4 run or are skipped together, so the
+// result buffer does not depend on the gate.
+// final == false (an intermediate basis of the subspace iteration, which
+// only has to span range(X) and be well conditioned): one pass, and the
+// second only when the first needed the shifted retry.
 int cholqr2(Ctx& cx, int64_t rows, int64_t c, double* buf0, double* buf1, int64_t ld, double* RT,
             double** out, bool final = true) {
     double* cur = buf0;
     double* nxt = buf1;
-    for (int pass = 0; pass < 2; ++pass) {
-        const int32_t* gate = (!final && pass == 1) ? cx.shifted : nullptr;
+    const int npass = final ? 4 : 2;
+    double* Ls[4] = {cx.o.L1, cx.o.L2, cx.o.L1, cx.o.L2};
+    for (int pass = 0; pass < npass; ++pass) {
+        // gate: pass 2 of an intermediate basis, passes 3 and 4 of a final one
+        const int32_t* gate = (pass >= (final ? 2 : 1)) ? cx.shifted : nullptr;
+        if (final && pass == 2 && RT) {
+            // R^T of the first two passes, before their factors are reused
+            RQLP_TRY(gemm<double>(false, false, c, c, c, cx.o.L1, c, cx.o.L2, c, RT, c, false, 1.0, 0.0, cx.gws,
+                                  cx.gws_elems, cx.s));
+        }
         RQLP_TRY(gemm<double>(true, false, c, c, rows, cur, ld, cur, ld, cx.o.G, c, false, 1.0, 0.0, cx.gws,
                               cx.gws_elems, cx.s, gate, 1, 1));
-        double* Lp = pass == 0 ? cx.o.L1 : cx.o.L2;
+        double* Lp = Ls[pass];
+        // shifted word: written by the first pass, only ever set by the later ones
         RQLP_TRY(chol_inv<double>(c, cx.o.G, c, Lp, cx.o.Li, nullptr, c, shift_scale(rows, c), cx.info, cx.s,
-                                  gate, (!final && pass == 0) ? cx.shifted : nullptr, cx.o.sync));
+                                  gate, cx.shifted, cx.o.sync, pass == 0 ? 1 : 2, pass == 0 ? kPivotRel : 0.0));
+        // a skipped second pass of an intermediate basis copies X through (static result buffer)
         RQLP_TRY(gemm<double>(false, true, rows, c, c, cur, ld, cx.o.Li, c, nxt, ld, false, 1.0, 0.0, cx.gws,
-                              cx.gws_elems, cx.s, gate, 2, 2));
+                              cx.gws_elems, cx.s, gate, final ? 1 : 2, 2));
+        if (pass == 0) RQLP_TRY(complete_columns(rows, c, nxt, ld, cx.o.L1, c, kZeroCol2, cx.shifted, cx.s));
         double* t = cur;
         cur = nxt;
         nxt = t;
     }
-    if (RT)
-        RQLP_TRY(gemm<double>(false, false, c, c, c, cx.o.L1, c, cx.o.L2, c, RT, c, false, 1.0, 0.0, cx.gws,
-                              cx.gws_elems, cx.s));
+    if (RT) {
+        if (!final) {
+            RQLP_TRY(gemm<double>(false, false, c, c, c, cx.o.L1, c, cx.o.L2, c, RT, c, false, 1.0, 0.0, cx.gws,
+                                  cx.gws_elems, cx.s));
+        } else {
+            // RT <- RT L3 L4 when the extra passes ran (else copied through)
+            RQLP_TRY(gemm<double>(false, false, c, c, c, RT, c, cx.o.L1, c, cx.o.G, c, false, 1.0, 0.0, cx.gws,
+                                  cx.gws_elems, cx.s, cx.shifted, 2));
+            RQLP_TRY(gemm<double>(false, false, c, c, c, cx.o.G, c, cx.o.L2, c, RT, c, false, 1.0, 0.0, cx.gws,
+                                  cx.gws_elems, cx.s, cx.shifted, 2));
+        }
+    }
     *out = cur;
     return 0;
 }

@@ -55,7 +55,8 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const TG* __restr
                                                         double* __restrict__ X, float* __restrict__ Xf,
                                                         int64_t ldw, int32_t* info, int prows, int xcols,
                                                         const int32_t* __restrict__ run_flag,
-                                                        int32_t* __restrict__ shifted_out, int shifted_mode) {
+                                                        int32_t* __restrict__ shifted_out, int shifted_mode,
+                                                        double pivot_rel) {
     extern __shared__ double lds[];
     double* D = lds;                           // [NB][NB+1] factored diagonal block
     double* Dinv = D + CH_NB * CH_PS;          // [NB][NB+1] its inverse
@@ -98,7 +99,8 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const TG* __restr
 
     int attempt = 0;
     for (; attempt < 2; ++attempt) {
-        const double shift = attempt == 0 ? 0.0 : shift_scale * s_trace;
+        // a zero Gram matrix (X = 0) gets a unit shift: its factor is then I
+        const double shift = attempt == 0 ? 0.0 : (s_trace == 0.0 ? 1.0 : shift_scale * s_trace);
         for (int j = wave; j < c; j += NWAVE) {
             for (int i = lane; i < c; i += 64) {
                 if (i >= j) W[i + (int64_t)j * ldw] = (double)G[i + (int64_t)j * ldg] + (i == j ? shift : 0.0);
@@ -123,7 +125,10 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const TG* __restr
                 int bad = 0;
                 for (int j = 0; j < kb; ++j) {
                     const double pj = D[j * CH_PS + j];
-                    const bool ok = (pj > 0.0) && (pj < 1.0e308);
+                    // plain attempt: a pivot below pivot_rel times the column's
+                    // squared norm marks a numerically dependent column
+                    const double thr = attempt == 0 ? pivot_rel * (double)G[(K0 + j) + (int64_t)(K0 + j) * ldg] : 0.0;
+                    const bool ok = (pj > thr) && (pj > 0.0) && (pj < 1.0e308);
                     bad |= !ok;
                     const double sj = ok ? sqrt(pj) : 1.0;
                     wave_sync();
@@ -306,11 +311,11 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const TG* __restr
 template <typename TG>
 int chol_inv(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
              double shift_scale, int32_t* info, hipStream_t s, const int32_t* run_flag, int32_t* shifted_out,
-             unsigned* sync, int shifted_mode) {
+             unsigned* sync, int shifted_mode, double pivot_rel) {
     if (c <= 0) return 0;
     if (sync && c <= CHOL_MW_MAXC)
         return chol_mw<TG>(c, G, ldg, L, Linv, Linv32, ld, shift_scale, info, sync, s, run_flag, shifted_out,
-                           shifted_mode);
+                           shifted_mode, pivot_rel);
     const size_t lds = chol_inv_lds_bytes(c);
     static bool attr_set = false;
     if (!attr_set) {
@@ -320,12 +325,12 @@ int chol_inv(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float
         attr_set = true;
     }
     hipLaunchKernelGGL((chol_inv_kernel<TG>), dim3(1), dim3(CH_T), lds, s, (int)c, G, ldg, shift_scale, L, Linv,
-                       Linv32, ld, info, ch_prows(c), ch_xcols(c), run_flag, shifted_out, shifted_mode);
+                       Linv32, ld, info, ch_prows(c), ch_xcols(c), run_flag, shifted_out, shifted_mode, pivot_rel);
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 template int chol_inv<double>(int64_t, const double*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
-                              hipStream_t, const int32_t*, int32_t*, unsigned*, int);
+                              hipStream_t, const int32_t*, int32_t*, unsigned*, int, double);
 template int chol_inv<float>(int64_t, const float*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
-                             hipStream_t, const int32_t*, int32_t*, unsigned*, int);
+                             hipStream_t, const int32_t*, int32_t*, unsigned*, int, double);
 
 }  // namespace rqlp

@@ -57,7 +57,7 @@ __device__ __forceinline__ double mw_readlane(double v, int l) {
 // with lane shuffles.  The row sweep of L X = I runs in the same loop: its
 // step j needs only L(i, j) and 1 / L(j, j) from the factor's step j, so the
 // two dependency chains overlap.
-__device__ bool mw_factor_diag(double d[4], double x[4], int lane) {
+__device__ bool mw_factor_diag(double d[4], double x[4], double thr, int lane) {
     const int i = lane & 15, g = lane >> 4;
     bool bad = false;
 #pragma unroll
@@ -66,7 +66,7 @@ __device__ bool mw_factor_diag(double d[4], double x[4], int lane) {
     for (int j = 0; j < 16; ++j) {
         const int gj = j >> 2, ej = j & 3;
         const double piv = mw_readlane(d[ej], j + 16 * gj);
-        const bool ok = (piv > 0.0) && (piv < 1.0e308);
+        const bool ok = (piv > mw_readlane(thr, j)) && (piv > 0.0) && (piv < 1.0e308);
         bad |= !ok;
         // 1 / sqrt(piv) from the hardware estimate and one Newton step
         // (relative error ~1e-16), then sqrt(piv) = piv / sqrt(piv)
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
                                                        double* __restrict__ Xo, float* __restrict__ Xf, int64_t ld,
                                                        int32_t* info, unsigned* flags0, unsigned epoch0,
                                                        int32_t* retry, const int32_t* gate, int gate_mode,
-                                                       int32_t* shifted_out, int shifted_mode) {
+                                                       int32_t* shifted_out, int shifted_mode, double pivot_rel) {
     extern __shared__ double lds[];
     const int J = blockIdx.x, NB = gridDim.x;
     const int j0 = 16 * J;
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
             __syncthreads();
             double tr = 0.0;
             for (int w = 0; w < MW_NW; ++w) tr += s_red[w];
-            shift = shift_scale * tr;
+            shift = tr == 0.0 ? 1.0 : shift_scale * tr;     // a zero Gram matrix: factor I
         }
         for (int idx = tid; idx < nrt * 16 * 16; idx += MW_T) {
             const int r = idx >> 4, t = idx & 15;
@@ -186,7 +186,11 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
                 double d[4], x[4];
     #pragma unroll
                 for (int e = 0; e < 4; ++e) d[e] = Wc[i * MW_S + 4 * g + e];
-                const bool bad = mw_factor_diag(d, x, lane);
+                // plain attempt: a pivot below pivot_rel times the column's squared
+                // norm marks a numerically dependent column (lane i: column j0 + i)
+                const double thr = (attempt == 0 && j0 + i < c)
+                                       ? pivot_rel * (double)G[(j0 + i) + (int64_t)(j0 + i) * ldg] : 0.0;
+                const bool bad = mw_factor_diag(d, x, thr, lane);
     #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     Wc[i * MW_S + 4 * g + e] = d[e];
@@ -478,7 +482,7 @@ size_t chol_mw_lds_bytes(int64_t c) {
 template <typename TG>
 int chol_mw(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
             double shift_scale, int32_t* info, unsigned* sync, hipStream_t s, const int32_t* run_flag,
-            int32_t* shifted_out, int shifted_mode) {
+            int32_t* shifted_out, int shifted_mode, double pivot_rel) {
     // per-process start value, so that flag words left in reused memory by
     // another process are unlikely to match
     static std::atomic<unsigned> epoch_counter{(unsigned)(getpid() * 2654435761u) ^ (unsigned)time(nullptr)};
@@ -500,14 +504,14 @@ int chol_mw(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float*
     // ~15 us of idle device time before and ~10 us after each launch.)
     hipLaunchKernelGGL((chol_mw_kernel<TG>), dim3(NB), dim3(MW_T), (unsigned)lds, s, (int)c, G, ldg, shift_scale, L,
                        Linv, Linv32, ld, info, sync, e0, retry, run_flag, run_flag ? 1 : 0, shifted_out,
-                       shifted_mode);
+                       shifted_mode, pivot_rel);
     RQLP_HIP_TRY(hipGetLastError());
     return 0;
 }
 
 template int chol_mw<double>(int64_t, const double*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
-                             unsigned*, hipStream_t, const int32_t*, int32_t*, int);
+                             unsigned*, hipStream_t, const int32_t*, int32_t*, int, double);
 template int chol_mw<float>(int64_t, const float*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
-                            unsigned*, hipStream_t, const int32_t*, int32_t*, int);
+                            unsigned*, hipStream_t, const int32_t*, int32_t*, int, double);
 
 }  // namespace rqlp

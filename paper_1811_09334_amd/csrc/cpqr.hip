@@ -3,7 +3,7 @@
 // factor of the second stage (Algorithm 2.1 step 6).
 //
 // Design: the matrix is distributed by columns over G co-resident workgroups
-// (cooperative launch), each holding its columns in LDS for the whole
+// (a grid no larger than the device holds at once), each holding its columns in LDS for the whole
 // factorisation, so the matrix never returns to HBM until the end.  Every
 // pivot step needs one grid-wide agreement on the winning column:
 //   1. each workgroup finds its best active column (largest residual norm,
@@ -966,44 +966,38 @@ int cpqr(const double* M, int64_t ldm, int64_t rows, int64_t cols, const CpqrScr
     const size_t bw = plan.rpt > 0 ? (size_t)cpr_bar_words(plan.G) : (size_t)cp_bar_words(plan.G);
     RQLP_TRY(fill_zero_bytes(sc.keys, sizeof(unsigned long long) * (size_t)kmax * kw, s));
     RQLP_TRY(fill_zero_bytes(sc.bar, sizeof(unsigned) * bw, s));
-    const double* Mp = M;
-    int64_t ldm_ = ldm, ldv_ = ldv, ldr_ = ldr, ldrt_ = ldrt;
-    unsigned long long* keys = sc.keys;
-    double* cand = sc.candcol;
-    double* part = sc.partial;
-    unsigned* bar = sc.bar;
-    void* args[] = {(void*)&Mp,   (void*)&ldm_,  (void*)&rows_i, (void*)&cols_i, (void*)&cpw,
-                    (void*)&kmax_i, (void*)&ibits, (void*)&keys, (void*)&cand,  (void*)&part,
-                    (void*)&bar,  (void*)&piv,   (void*)&Vh,    (void*)&ldv_,  (void*)&beta,
-                    (void*)&Rpiv, (void*)&ldr_,  (void*)&Rt,    (void*)&ldrt_, (void*)&info,
-                    (void*)&spin};
+    // Plain launches: the grid is at most the number of workgroups the device
+    // holds at once (checked against the occupancy), so every workgroup is
+    // resident once the previous kernel of the stream has drained, and every
+    // wait inside is bounded (RQLP_INFO_BARRIER_TIMEOUT).  A cooperative
+    // launch gives the same residency at the cost of idle device time around
+    // the launch.
     if (plan.rpt > 0) {
-        void* rargs[] = {(void*)&Mp,   (void*)&ldm_, (void*)&rows_i, (void*)&cols_i, (void*)&kmax_i,
-                         (void*)&ibits, (void*)&keys, (void*)&cand,  (void*)&part,   (void*)&bar,
-                         (void*)&piv,  (void*)&Vh,   (void*)&ldv_,   (void*)&beta,   (void*)&Rpiv,
-                         (void*)&ldr_, (void*)&Rt,   (void*)&ldrt_,  (void*)&info,   (void*)&spin};
-        const void* fn = nullptr;
+#define RQLP_CPR(R)                                                                                             \
+    hipLaunchKernelGGL(cpqr_reg_kernel<R>, dim3(plan.G), dim3(CP_T), 0, s, M, ldm, rows_i, cols_i, kmax_i, ibits, \
+                       sc.keys, sc.candcol, sc.partial, sc.bar, piv, Vh, ldv, beta, Rpiv, ldr, Rt, ldrt, info, spin)
         switch (plan.rpt) {
-            case 2: fn = (const void*)cpqr_reg_kernel<2>; break;
-            case 4: fn = (const void*)cpqr_reg_kernel<4>; break;
-            case 6: fn = (const void*)cpqr_reg_kernel<6>; break;
-            case 9: fn = (const void*)cpqr_reg_kernel<9>; break;
-            case 12: fn = (const void*)cpqr_reg_kernel<12>; break;
-            case 14: fn = (const void*)cpqr_reg_kernel<14>; break;
-            case 17: fn = (const void*)cpqr_reg_kernel<17>; break;
-            case 18: fn = (const void*)cpqr_reg_kernel<18>; break;
-            default: fn = (const void*)cpqr_reg_kernel<24>; break;
+            case 2: RQLP_CPR(2); break;
+            case 4: RQLP_CPR(4); break;
+            case 6: RQLP_CPR(6); break;
+            case 9: RQLP_CPR(9); break;
+            case 12: RQLP_CPR(12); break;
+            case 14: RQLP_CPR(14); break;
+            case 17: RQLP_CPR(17); break;
+            case 18: RQLP_CPR(18); break;
+            default: RQLP_CPR(24); break;
         }
-        RQLP_HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(plan.G), dim3(CP_T), rargs, 0, s));
-        return 0;
+#undef RQLP_CPR
+        return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
     }
     int nb = 0;
     RQLP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)cpqr_kernel<false>, CP_T,
                                                              plan.lds));
     if ((int64_t)nb * device_info().num_cus < plan.G) return RQLP_E_UNSUPPORTED;
-    RQLP_HIP_TRY(hipLaunchCooperativeKernel((const void*)cpqr_kernel<false>, dim3(plan.G), dim3(CP_T), args,
-                                            (unsigned)plan.lds, s));
-    return 0;
+    hipLaunchKernelGGL(cpqr_kernel<false>, dim3(plan.G), dim3(CP_T), plan.lds, s, M, ldm, rows_i, cols_i, cpw,
+                       kmax_i, ibits, sc.keys, sc.candcol, sc.partial, sc.bar, piv, Vh, ldv, beta, Rpiv, ldr, Rt,
+                       ldrt, info, spin);
+    return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 
 // ---------------------------------------------------------------------------

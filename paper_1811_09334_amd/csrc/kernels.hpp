@@ -85,6 +85,8 @@ int cast_matrix(int64_t rows, int64_t cols, const S* src, int64_t lds, D* dst, i
 // identities (a conditional extra pass); shifted_out (optional): with
 // shifted_mode 1 it receives 1 when the shifted retry was used, else 0; with
 // shifted_mode 2 it is only ever set to 1 (accumulates over passes).
+// pivot_rel: in the plain attempt a pivot <= pivot_rel * G(j, j) counts as a
+// breakdown (column j numerically dependent on the earlier ones).
 // sync: CHOL_SYNC_WORDS words of device scratch (flags of the multi-workgroup
 // kernel used for c <= CHOL_MW_MAXC); NULL selects the one-workgroup kernel.
 constexpr int CHOL_MW_MAXC = 512;
@@ -93,11 +95,12 @@ size_t chol_inv_lds_bytes(int64_t c);
 template <typename TG>
 int chol_inv(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
              double shift_scale, int32_t* info, hipStream_t s, const int32_t* run_flag = nullptr,
-             int32_t* shifted_out = nullptr, unsigned* sync = nullptr, int shifted_mode = 1);
+             int32_t* shifted_out = nullptr, unsigned* sync = nullptr, int shifted_mode = 1,
+             double pivot_rel = 0.0);
 template <typename TG>
 int chol_mw(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
             double shift_scale, int32_t* info, unsigned* sync, hipStream_t s, const int32_t* run_flag,
-            int32_t* shifted_out, int shifted_mode);
+            int32_t* shifted_out, int shifted_mode, double pivot_rel);
 
 // --- cpqr.hip ---------------------------------------------------------------
 struct CpqrScratch {
@@ -132,6 +135,12 @@ int apply_householder(int64_t rows, int64_t k, const double* Vh, int64_t ldv, co
                       int64_t ldy, hipStream_t s);
 
 // --- misc.hip ---------------------------------------------------------------
+// Columns of X (rows x c) whose squared norm is <= tau2 are replaced by
+// N(0, 1/rows) vectors (Philox4x32-10 counter (i, j, 1, 0), fixed key), and the
+// diagonal entry L(j, j) of the optional c x c factor is zeroed.  Runs only
+// when the device word *gate is non-zero.
+int complete_columns(int64_t rows, int64_t c, double* X, int64_t ldx, double* L, int64_t ldl, double tau2,
+                     const int32_t* gate, hipStream_t s);
 int fill_zero_bytes(void* p, size_t bytes, hipStream_t s);
 int copy_matrix(int64_t rows, int64_t cols, const double* X, int64_t ldx, double* Y, int64_t ldy,
                 hipStream_t s);

@@ -196,4 +196,48 @@ int generate_omega(int64_t n, int64_t l, uint64_t seed, int precision, void* Ome
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 
+
+// Orthonormal completion of a basis whose input columns were numerically zero
+// (exactly zero columns of R0^T after a rank stop of the first CPQR, or a
+// sketch of a zero matrix): after a shifted CholeskyQR pass such a column is
+// still (close to) zero and no later pass can normalise it, so it is replaced
+// by a Gaussian vector, which the following passes orthonormalise against the
+// earlier columns.  Zeroing L(j, j) of the pass's factor keeps X_in = X L^T
+// exact for a zero input column (its row and column of L are zero apart from
+// the diagonal), so the triangular factor R of the whole CholeskyQR gets a zero
+// row j.  One workgroup per column.
+__global__ __launch_bounds__(256) void complete_columns_kernel(int64_t rows, int64_t c, double* X, int64_t ldx,
+                                                               double* L, int64_t ldl, double tau2,
+                                                               const int32_t* gate) {
+    if (*gate == 0) return;
+    __shared__ double s_red[4];
+    const int64_t j = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* x = X + j * ldx;
+    double ss = 0.0;
+    for (int64_t i = tid; i < rows; i += 256) ss += x[i] * x[i];
+    ss = wave_sum(ss);
+    if (lane == 0) s_red[wave] = ss;
+    __syncthreads();
+    const double nrm2 = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+    if (!(nrm2 <= tau2)) return;                      // also keeps NaN columns as they are
+    const double scale = 1.0 / sqrt((double)rows);
+    for (int64_t i = tid; i < rows; i += 256) {
+        uint32_t ctr[4] = {(uint32_t)i, (uint32_t)j, 1u, 0u};
+        philox4x32_10(ctr, 0x5EED1234u, 0x0C0FFEE5u);
+        const double u1 = ((double)ctr[0] + 1.0) * 2.3283064365386963e-10;
+        const double u2 = (double)ctr[1] * 2.3283064365386963e-10;
+        x[i] = scale * sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    }
+    if (L && tid == 0) L[j + j * ldl] = 0.0;
+}
+
+int complete_columns(int64_t rows, int64_t c, double* X, int64_t ldx, double* L, int64_t ldl, double tau2,
+                     const int32_t* gate, hipStream_t s) {
+    if (rows <= 0 || c <= 0) return 0;
+    hipLaunchKernelGGL(complete_columns_kernel, dim3((unsigned)c), dim3(256), 0, s, rows, c, X, ldx, L, ldl, tau2,
+                       gate);
+    return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
+}
+
 }  // namespace rqlp

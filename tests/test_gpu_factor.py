@@ -100,3 +100,60 @@ def test_repeat_calls_are_bitwise_identical(gpu):
     f2 = gpu.factor(A, w.k, w.p, q=1, d=2, Omega=Om)
     for a, b in [(f1.Q, f2.Q), (f1.T, f2.T), (f1.P, f2.P), (f1.piv0, f2.piv0)]:
         assert np.array_equal(to_np(a), to_np(b))
+
+
+@pytest.mark.parametrize("q,d", [(0, 0), (0, 2), (1, 0), (1, 1), (2, 2)])
+def test_rank_deficient_input_exact_reconstruction(gpu, q, d):
+    """rank(A) = 10 < l = 12 (Section 2: exact reconstruction when the sketch
+    holds range(A)): the first CPQR stops at the rank, the trailing L-values are
+    exactly zero, Q and P stay orthonormal and Q T P^T reproduces A; the
+    CholeskyQR of the rank-deficient sketch and of R0^T takes the shifted
+    retry (flag 0x1, not 0x10)."""
+    m, n, k, p, rank = 60, 40, 8, 4, 10
+    l = k + p
+    A = inputs.svd_matrix(m, n, inputs.spectrum_poly(rank, 1.0), 5)
+    Om = inputs.gaussian(n, l, 6)
+    f = gpu.factor(to_dev(A), k, p, q=q, d=d, Omega=to_dev(Om))
+    Q, T, P = to_np(f.Q), to_np(f.T), to_np(f.P)
+    lv, info = to_np(f.lvals), int(to_np(f.info)[0])
+    ref = oracle_rqlp(A, Om, k, p, q=q, d=d)
+    assert ref.rank0 == rank
+    assert info & 0x2 and info & 0x1 and not info & (0x4 | 0x8 | 0x10 | 0x20), f"info {info:#x}"
+    assert np.all(lv[rank:] == 0.0)
+    assert np.max(np.abs(lv[:rank] - ref.lvals[:rank]) / ref.lvals[:rank]) < LVAL_TOL
+    nA = np.linalg.norm(A)
+    assert np.linalg.norm(A - Q @ T @ P.T) < 1e-13 * nA * 10
+    assert np.abs(Q.T @ Q - np.eye(l)).max() < 1e-12
+    assert np.abs(P.T @ P - np.eye(l)).max() < 1e-12
+    assert np.array_equal(to_np(f.piv0)[:rank], ref.piv0[:rank])
+
+
+def test_zero_matrix(gpu):
+    """A = 0: every L-value is 0, Q and P are orthonormal completions, the
+    first CPQR reports rank 0."""
+    m, n, k, p = 50, 30, 4, 3
+    A = np.zeros((m, n))
+    Om = inputs.gaussian(n, k + p, 1)
+    for d in (0, 2):
+        f = gpu.factor(to_dev(A), k, p, q=1, d=d, Omega=to_dev(Om))
+        Q, T, P, info = to_np(f.Q), to_np(f.T), to_np(f.P), int(to_np(f.info)[0])
+        assert np.all(T == 0.0) and np.all(to_np(f.lvals) == 0.0)
+        assert info & 0x2 and not info & (0x4 | 0x10)
+        assert np.abs(Q.T @ Q - np.eye(k + p)).max() < 1e-12
+        assert np.abs(P.T @ P - np.eye(k + p)).max() < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16"])
+def test_nonfinite_input_is_flagged(gpu, precision):
+    """A NaN (or Inf) entry in A sets RQLP_INFO_NONFINITE; every wait inside
+    the call still ends (bounded spins)."""
+    import torch
+    m, n, k, p = 300, 200, 10, 5
+    dt = torch.float64 if precision == "f64" else torch.float32
+    for bad in (np.nan, np.inf):
+        A = inputs.gaussian(m, n, 3)
+        A[17, 33] = bad
+        f = gpu.factor(to_dev(A, dt), k, p, q=1, d=2, precision=precision, seed=5)
+        info = int(to_np(f.info)[0])
+        assert info & 0x4, f"{precision} {bad}: info {info:#x}"
+        assert not info & 0x8

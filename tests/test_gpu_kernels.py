@@ -76,7 +76,11 @@ def test_cholqr2_orthonormalizes(gpu, m, c, cond):
 
 
 @pytest.mark.parametrize("rows,cols,seed", [(25, 500, 0), (210, 2000, 1), (47, 333, 2), (64, 64, 3),
-                                            (136, 136, 4), (200, 200, 5), (272, 4000, 6), (30, 12, 7)])
+                                            (136, 136, 4), (200, 200, 5), (272, 4000, 6), (30, 12, 7),
+                                            # the reduced-matrix shapes of the benchmark workloads: 157, 256
+                                            # and 128 workgroups of 64 columns (pivot agreement over more
+                                            # than 64 key slots, i.e. several slots per polling lane)
+                                            (210, 10000, 8), (272, 16384, 9), (64, 8192, 10), (17, 4097, 12)])
 def test_cpqr_matches_oracle(gpu, rows, cols, seed):
     rng = np.random.default_rng(seed)
     M = rng.standard_normal((rows, cols)) * np.exp(rng.uniform(-6, 0, cols))[None, :]

@@ -29,7 +29,9 @@ KINDS = ["bf16", "fp16", "bf16x3"]
 
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("m,n,c", [(1000, 500, 25), (777, 333, 47), (4096, 2048, 272), (64, 16, 16),
-                                   (130, 70, 3), (1500, 3000, 120), (5000, 700, 288), (300, 200, 300)])
+                                   (130, 70, 3), (1500, 3000, 120), (5000, 700, 288), (300, 200, 300),
+                                   # the block workload's panel width l = 1056 (four column tiles)
+                                   (2048, 4096, 1056)])
 def test_lowprec_products_match_encoded_reference(gpu, kind, m, n, c):
     import torch
     rng = np.random.default_rng(m * 3 + n + c)
@@ -210,3 +212,29 @@ def test_f32_path_matches_oracle(gpu, m, n, k, p, q, d):
     Q, P = g["Q"].astype(np.float64), g["P"].astype(np.float64)
     l = k + p
     assert np.abs(Q.T @ Q - np.eye(l)).max() < 2e-5 and np.abs(P.T @ P - np.eye(l)).max() < 2e-5
+
+
+@pytest.mark.parametrize("kind", ["bf16", "bf16x3"])
+def test_mixed_rank_deficient_input(gpu, kind):
+    """rank(A) = 40 < l = 72 with 16-bit products: the sketch's null
+    directions sit at the products' rounding level instead of zero, so the
+    leading L-values meet the frozen-pivot gate while the trailing ones and the
+    residual are at the 16-bit rounding level (not exactly zero as in FP64)."""
+    import torch
+    m, n, k, p, rank = 2048, 1024, 64, 8, 40
+    l = k + p
+    A = inputs.svd_matrix(m, n, inputs.spectrum_poly(rank, 1.0), 77).astype(np.float32)
+    Om = inputs.round_to_bf16(inputs.gaussian(n, l, 78))
+    f, g = _mixed_factor(gpu, A, Om, k, p, 1, 2, kind)
+    lv, piv0 = g["lvals"], g["piv0"]
+    assert int(g["info"][0]) & ~0x3 == 0, f"info {int(g['info'][0]):#x}"
+    frozen = oracle_rqlp(A.astype(np.float64), Om, k, p, q=1, d=2, piv0=piv0)
+    rel = np.abs(lv[:rank] - frozen.lvals[:rank]) / frozen.lvals[:rank]
+    tail = lv[rank:].max() / lv[0]
+    Q, T, P = g["Q"].astype(np.float64), g["T"], g["P"].astype(np.float64)
+    res = np.linalg.norm(A - Q @ T @ P.T) / np.linalg.norm(A)
+    print(f"[{kind} rank {rank} < l {l}] leading frozen {rel.max():.2e}, trailing/L11 {tail:.2e}, residual {res:.2e}")
+    assert rel.max() <= LVAL_GATE
+    bound = 1e-2 if kind == "bf16" else 1e-4
+    assert tail < bound and res < bound
+    assert np.abs(Q.T @ Q - np.eye(l)).max() < 2e-5
