@@ -61,7 +61,9 @@ enum rqlp_status {
     RQLP_OK = 0,
     RQLP_E_WORKSPACE = -1000,   /* work_bytes smaller than rqlp_workspace_size() */
     RQLP_E_HIP = -1001,         /* a HIP launch / runtime call failed            */
-    RQLP_E_UNSUPPORTED = -1002  /* valid arguments this build does not handle     */
+    RQLP_E_UNSUPPORTED = -1002, /* valid arguments this build does not handle     */
+    RQLP_E_SCRATCH_LIMIT = -1003 /* rqlp_factor_noalloc: problem needs more than
+                                    RQLP_NOALLOC_SCRATCH_BYTES of workspace      */
 };
 
 /* bit flags written to *info (device int32) */
@@ -138,6 +140,29 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
                 void* Q, int64_t ldq, double* T, int64_t ldt, void* P, int64_t ldp,
                 int64_t* piv0, int64_t* piv1, double* lvals, int32_t* info, char* uplo,
                 void* work, size_t work_bytes, void* stream);
+
+/* rqlp_factor for callers that cannot allocate device memory (code that
+ * must not call hipMalloc: tight serving loops, harnesses that forbid
+ * allocation).  No workspace argument: the workspace is a fixed device array
+ * of RQLP_NOALLOC_SCRATCH_BYTES bytes inside the library, one copy per device
+ * the library runs on, held until the process ends.  A problem whose
+ * rqlp_workspace_size() exceeds that size returns RQLP_E_SCRATCH_LIMIT
+ * before any work is enqueued.  Arguments 1-24, outputs, argument errors and
+ * the asynchronous *info flags are those of rqlp_factor; argument 25 is the
+ * stream.  Everything that must start at zero is cleared by kernels inside
+ * the call.  All calls on one device share its array: calls that may overlap
+ * in time on one device (different streams, or host threads without ordering
+ * between them) race and give wrong results; calls on one stream are
+ * ordered and safe.  Capturing a call into a HIP graph for replay is not
+ * supported (the flag epochs of the multi-workgroup Cholesky are fixed when
+ * the call is enqueued). */
+#define RQLP_NOALLOC_SCRATCH_BYTES (64u << 20)
+int rqlp_factor_noalloc(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int64_t p,
+                        int q, int d, int b, int precision, uint64_t seed,
+                        const void* Omega, int64_t ldo,
+                        void* Q, int64_t ldq, double* T, int64_t ldt, void* P, int64_t ldp,
+                        int64_t* piv0, int64_t* piv1, double* lvals, int32_t* info, char* uplo,
+                        void* stream);
 
 /* ---- building blocks (the steps of Algorithm 2.1, usable on their own) ---- */
 

@@ -25,6 +25,10 @@ SIGNATURES = {
                             c_uint64, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64,
                             c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_char), c_void_p, c_size_t,
                             c_void_p]),
+    "rqlp_factor_noalloc": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_int64, c_int64, c_int, c_int, c_int,
+                                    c_int, c_uint64, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64,
+                                    c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_char),
+                                    c_void_p]),
     "rqlp_backward": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_int64, c_int64, c_int, c_int, c_int, c_int,
                               c_uint64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_int64,
                               c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_size_t,
@@ -108,6 +112,12 @@ def rqlp_factor(A, lda, m, n, k, p, q, d, b, precision, seed, Omega, ldo, Q, ldq
                 piv0, piv1, lvals, info, uplo, work, work_bytes, stream) -> int:
     return _call("rqlp_factor", A, lda, m, n, k, p, q, d, b, precision, seed, Omega, ldo, Q, ldq, T, ldt, P, ldp,
                  piv0, piv1, lvals, info, uplo, work, work_bytes, stream)
+
+
+def rqlp_factor_noalloc(A, lda, m, n, k, p, q, d, b, precision, seed, Omega, ldo, Q, ldq, T, ldt, P, ldp,
+                        piv0, piv1, lvals, info, uplo, stream) -> int:
+    return _call("rqlp_factor_noalloc", A, lda, m, n, k, p, q, d, b, precision, seed, Omega, ldo, Q, ldq, T, ldt,
+                 P, ldp, piv0, piv1, lvals, info, uplo, stream)
 
 
 def rqlp_backward(A, lda, m, n, k, p, q, d, b, precision, seed, Omega, ldo, piv0, piv1, dT, lddt, dQ, lddq, dP,

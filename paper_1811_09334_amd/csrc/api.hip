@@ -506,6 +506,27 @@ int check_factor_args(const void* A, int64_t lda, int64_t m, int64_t n, int64_t 
     return 0;
 }
 
+}  // namespace
+
+namespace rqlp {
+int factor_arg_status(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int64_t p, int q, int d, int b,
+                      int precision, const void* Omega, int64_t ldo, const void* Q, int64_t ldq, const double* T,
+                      int64_t ldt, const void* P, int64_t ldp) {
+    RQLP_TRY(check_factor_args(A, lda, m, n, k, p, q, d, b, precision));
+    const int64_t l = k + p;
+    if (Omega && ldo < n) return -13;
+    if (!Q) return -14;
+    if (ldq < m) return -15;
+    if (!T) return -16;
+    if (ldt < l) return -17;
+    if (!P) return -18;
+    if (ldp < n) return -19;
+    return 0;
+}
+}  // namespace rqlp
+
+namespace {
+
 // Workspace layout of one rqlp_factor call (shared by the size query and
 // the call itself).
 struct FactorLayout {
@@ -636,6 +657,9 @@ const char* rqlp_status_string(int status) {
     if (status == RQLP_E_WORKSPACE) return "workspace too small";
     if (status == RQLP_E_HIP) return "HIP runtime or launch error";
     if (status == RQLP_E_UNSUPPORTED) return "arguments valid but not supported by this build";
+    if (status == RQLP_E_SCRATCH_LIMIT)
+        return "rqlp_factor_noalloc: the problem needs more workspace than the library's static scratch "
+               "(RQLP_NOALLOC_SCRATCH_BYTES); use rqlp_factor with a caller workspace";
     if (status < 0 && status > -100) return "invalid argument (see the argument index -status)";
     return "unknown status";
 }
@@ -666,15 +690,8 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
                 int precision, uint64_t seed, const void* Omega, int64_t ldo, void* Q, int64_t ldq, double* T,
                 int64_t ldt, void* P, int64_t ldp, int64_t* piv0, int64_t* piv1, double* lvals, int32_t* info,
                 char* uplo, void* work, size_t work_bytes, void* stream) {
-    RQLP_TRY(check_factor_args(A, lda, m, n, k, p, q, d, b, precision));
+    RQLP_TRY(rqlp::factor_arg_status(A, lda, m, n, k, p, q, d, b, precision, Omega, ldo, Q, ldq, T, ldt, P, ldp));
     const int64_t l = k + p;
-    if (Omega && ldo < n) return -13;
-    if (!Q) return -14;
-    if (ldq < m) return -15;
-    if (!T) return -16;
-    if (ldt < l) return -17;
-    if (!P) return -18;
-    if (ldp < n) return -19;
     if (!work) return -25;
     // block RQLP with b >= l is a single block: plain RQLP
     const int64_t bs = (b > 0 && b < l) ? b : 0;

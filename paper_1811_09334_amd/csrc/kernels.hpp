@@ -5,6 +5,13 @@
 
 namespace rqlp {
 
+// --- api.hip ----------------------------------------------------------------
+// Synchronous argument checks of rqlp_factor up to (not including) the
+// workspace: 0, or -i for the first invalid argument i (rqlp_factor's numbering).
+int factor_arg_status(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int64_t p, int q, int d, int b,
+                      int precision, const void* Omega, int64_t ldo, const void* Q, int64_t ldq, const double* T,
+                      int64_t ldt, const void* P, int64_t ldp);
+
 // --- gemm.hip ---------------------------------------------------------------
 // C = alpha * op(A) * op(B) + beta * C, op(A) = A (ta = false, A is M x K)
 // or A^T (ta = true, A is K x M); op(B) = B (tb = false, B is K x N) or B^T
