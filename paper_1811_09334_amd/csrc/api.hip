@@ -77,13 +77,15 @@ constexpr double kZeroCol2 = 1e-12;
 // orthonormal basis, while four passes do; columns that are exactly zero
 // (R0^T after a rank stop) never grow and are replaced by random vectors
 // after the first pass (complete_columns), which also zeroes their rows of
-// R.  The conditional passes 3 and 4 run or are skipped together, so the
-// result buffer does not depend on the gate.
+// R (col0: the panel's first column in a wider basis, which keeps the
+// completions of different blocks of one basis apart).  The conditional
+// passes 3 and 4 run or are skipped together, so the result buffer does not
+// depend on the gate.
 // final == false (an intermediate basis of the subspace iteration, which
 // only has to span range(X) and be well conditioned): one pass, and the
 // second only when the first needed the shifted retry.
 int cholqr2(Ctx& cx, int64_t rows, int64_t c, double* buf0, double* buf1, int64_t ld, double* RT,
-            double** out, bool final = true) {
+            double** out, bool final = true, int64_t col0 = 0) {
     double* cur = buf0;
     double* nxt = buf1;
     const int npass = final ? 4 : 2;
@@ -105,7 +107,7 @@ int cholqr2(Ctx& cx, int64_t rows, int64_t c, double* buf0, double* buf1, int64_
         // a skipped second pass of an intermediate basis copies X through (static result buffer)
         RQLP_TRY(gemm<double>(false, true, rows, c, c, cur, ld, cx.o.Li, c, nxt, ld, false, 1.0, 0.0, cx.gws,
                               cx.gws_elems, cx.s, gate, final ? 1 : 2, 2));
-        if (pass == 0) RQLP_TRY(complete_columns(rows, c, nxt, ld, cx.o.L1, c, kZeroCol2, cx.shifted, cx.s));
+        if (pass == 0) RQLP_TRY(complete_columns(rows, c, nxt, ld, cx.o.L1, c, kZeroCol2, cx.shifted, cx.s, col0));
         double* t = cur;
         cur = nxt;
         nxt = t;
@@ -417,7 +419,7 @@ int bcgs2(CtxT& cx, int64_t rows, int64_t l, int64_t bs, T* V, int64_t ld, BcgsS
             const bool full = pass == 1 && final;
             T* o = nullptr;
             if constexpr (sizeof(T) == sizeof(double)) {
-                RQLP_TRY(cholqr2(cx, rows, bj, (double*)Vj, (double*)p1, ld, nullptr, (double**)&o, full));
+                RQLP_TRY(cholqr2(cx, rows, bj, (double*)Vj, (double*)p1, ld, nullptr, (double**)&o, full, s0));
                 if ((void*)o != (void*)Vj) RQLP_TRY(copy_matrix(rows, bj, (const double*)o, ld, (double*)Vj, ld, s));
             } else {
                 RQLP_TRY(cholqr_f32(cx, rows, bj, (float*)Vj, (float*)p1, ld, (float**)&o, full));
@@ -535,6 +537,7 @@ struct FactorLayout {
     SmallBufs sm;
     BcgsScratch bc;     // block RQLP only
     double* Bj;         // block RQLP: one block row of B (bs x n)
+    BqlpScratch bq;     // block RQLP with blocks of <= 64 rows: batched per-block QLP
 };
 
 // bs: block size of block RQLP (0: unblocked).
@@ -558,6 +561,7 @@ void carve_factor(Arena& ar, int64_t m, int64_t n, int64_t l, int precision, boo
         L->bc.ws_elems = max_ws(gemm_workspace_elems, {{l, bs, m}, {m, bs, l}, {l, bs, n}, {n, bs, l}});
         L->bc.ws = ar.take<char>(L->bc.ws_elems * es);
         L->Bj = ar.take<double>(bs * n);
+        if (bs <= 64) bqlp_carve(ar, n, l, bs, &L->bq);
     }
 }
 
@@ -742,6 +746,16 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
         }
         if (piv0) RQLP_TRY(copy_i64(l, f.piv0, piv0, s));
         if (piv1) RQLP_TRY(copy_i64(l, d == 0 ? f.piv1 : nullptr, piv1, s));
+    } else if (bqlp_supported(n, l, bs)) {
+        // Algorithm 4.1 steps 6-7 for all blocks at once (batched kernels)
+        if (f64)
+            RQLP_TRY(bqlp<double>(f.B, l, n, l, bs, Lay.bq, f.Z, V64, m, m, (double*)Q, ldq, Pd, ldpd, T, ldt, f.piv0,
+                                  f.piv1, inf, s));
+        else
+            RQLP_TRY(bqlp<float>(f.B, l, n, l, bs, Lay.bq, f.Z, V32, m, m, (float*)Q, ldq, Pd, ldpd, T, ldt, f.piv0,
+                                 f.piv1, inf, s));
+        if (piv0) RQLP_TRY(copy_i64(l, f.piv0, piv0, s));
+        if (piv1) RQLP_TRY(copy_i64(l, f.piv1, piv1, s));
     } else {
         // Algorithm 4.1 steps 6-7, block by block: B_j = V_j^T A is block row j
         // of B; pivoted QLP of B_j; Q_j = V_j Q_B(j), P_j = P_B(j); T = blkdiag(L_j)

@@ -152,6 +152,34 @@ __device__ __forceinline__ void drain_and_sync() {
     __syncthreads();
 }
 
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+// 4 x 32-bit counter-based generator on c with key (k0, k1).
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+// N(0, 1) by Box-Muller from the first two words of Philox4x32-10 at counter
+// (c0, c1, c2, 0) with key (k0, k1).
+__device__ __forceinline__ double philox_normal(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t k0, uint32_t k1) {
+    uint32_t c[4] = {c0, c1, c2, 0u};
+    philox4x32_10(c, k0, k1);
+    const double u1 = ((double)c[0] + 1.0) * 2.3283064365386963e-10;
+    const double u2 = (double)c[1] * 2.3283064365386963e-10;
+    return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
 // Copies from global memory straight into LDS (global_load_lds_dwordx4): the
 // LDS operand is the wave's base address, lane l's 16 bytes land at base + 16 l.
 #define RQLP_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))

@@ -141,13 +141,45 @@ int apply_householder(int64_t rows, int64_t k, const double* Vh, int64_t ldv, co
                       const double* X, int64_t ldx, const int64_t* unit, int64_t ncols, double* Y,
                       int64_t ldy, hipStream_t s);
 
+// --- bqlp.hip: batched pivoted QLP of the block rows of B (block RQLP) ----
+struct BqlpScratch {
+    unsigned long long* keys;   // per block: bs steps x G workgroups x 2 key words
+    unsigned long long* gw;     // per block: result word (one 128-byte line)
+    double* frop;               // per block: G partial ||B_j||_F^2
+    double* candcol;            // per block: 2 x G x 64 candidate columns
+    double* Vh0;                // per block: bs x bs reflectors of the first CPQR
+    double* beta0;              // l
+    int* rank;                  // per block
+    int32_t* shifted;           // per block: a Cholesky of R0_j^T needed the shift
+    double* part;               // per block: ceil(n / 256) Gram partials of 64 x 64
+    double* Ls;                 // 4 passes x per block 64 x 64 Cholesky factors
+    double* Linv;               // per block 64 x 64
+    double* RT;                 // per block 64 x 64: Rt_j^T
+    double* Qhat;               // per block 64 x 64
+    double* QB;                 // per block 64 x 64
+};
+void bqlp_carve(Arena& ar, int64_t n, int64_t l, int64_t bs, BqlpScratch* sc);
+// blocks of bs <= 64 rows, n <= 65536 and a first-CPQR grid that fits on the device
+bool bqlp_supported(int64_t n, int64_t l, int64_t bs);
+// B (l x n, FP64): per block row j (rows [j bs, min(l, (j + 1) bs))): the
+// pivoted QLP B_j = Q_B^(j) L_j P_B^(j)^T; outputs T = blkdiag(L_j) (l x l),
+// Pd (n x l, FP64, column block j = P_B^(j)), Q (m x l, column block j =
+// V_j Q_B^(j)), piv0 (original column indices), piv1 (0-based within the
+// block).  Z: n x l FP64 scratch (R0^T, then Qt).
+template <typename TV>
+int bqlp(const double* B, int64_t ldb, int64_t n, int64_t l, int64_t bs, const BqlpScratch& sc, double* Z,
+         const TV* V, int64_t ldv, int64_t m, TV* Q, int64_t ldq, double* Pd, int64_t ldpd, double* T, int64_t ldt,
+         int64_t* piv0, int64_t* piv1, int32_t* info, hipStream_t s);
+
 // --- misc.hip ---------------------------------------------------------------
 // Columns of X (rows x c) whose squared norm is <= tau2 are replaced by
-// N(0, 1/rows) vectors (Philox4x32-10 counter (i, j, 1, 0), fixed key), and the
-// diagonal entry L(j, j) of the optional c x c factor is zeroed.  Runs only
-// when the device word *gate is non-zero.
+// N(0, 1/rows) vectors (Philox4x32-10 counter (i, col0 + j, 1, 0), fixed
+// key; col0 = the panel's first column in a wider basis, so that blocks of
+// one basis get different vectors), and the diagonal entry L(j, j) of the
+// optional c x c factor is zeroed.  Runs only when the device word *gate is
+// non-zero.
 int complete_columns(int64_t rows, int64_t c, double* X, int64_t ldx, double* L, int64_t ldl, double tau2,
-                     const int32_t* gate, hipStream_t s);
+                     const int32_t* gate, hipStream_t s, int64_t col0 = 0);
 int fill_zero_bytes(void* p, size_t bytes, hipStream_t s);
 int copy_matrix(int64_t rows, int64_t cols, const double* X, int64_t ldx, double* Y, int64_t ldy,
                 hipStream_t s);

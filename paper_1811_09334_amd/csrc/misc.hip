@@ -139,25 +139,8 @@ int copy_i64(int64_t n, const int64_t* src, int64_t* dst, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) + Box-Muller (1958).
+// Philox4x32-10 (philox4x32_10, common.hpp) + Box-Muller (1958).
 // Element (i, j): counter (i, j, 0, 0), key (lo32(seed), hi32(seed)).
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r > 0) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
-
 __device__ __forceinline__ float round_bf16(float x) {
     uint32_t b = __float_as_uint(x);
     b = (b + 0x7FFFu + ((b >> 16) & 1u)) & 0xFFFF0000u;
@@ -208,7 +191,7 @@ int generate_omega(int64_t n, int64_t l, uint64_t seed, int precision, void* Ome
 // row j.  One workgroup per column.
 __global__ __launch_bounds__(256) void complete_columns_kernel(int64_t rows, int64_t c, double* X, int64_t ldx,
                                                                double* L, int64_t ldl, double tau2,
-                                                               const int32_t* gate) {
+                                                               const int32_t* gate, int64_t col0) {
     if (*gate == 0) return;
     __shared__ double s_red[4];
     const int64_t j = blockIdx.x;
@@ -223,7 +206,7 @@ __global__ __launch_bounds__(256) void complete_columns_kernel(int64_t rows, int
     if (!(nrm2 <= tau2)) return;                      // also keeps NaN columns as they are
     const double scale = 1.0 / sqrt((double)rows);
     for (int64_t i = tid; i < rows; i += 256) {
-        uint32_t ctr[4] = {(uint32_t)i, (uint32_t)j, 1u, 0u};
+        uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(col0 + j), 1u, 0u};
         philox4x32_10(ctr, 0x5EED1234u, 0x0C0FFEE5u);
         const double u1 = ((double)ctr[0] + 1.0) * 2.3283064365386963e-10;
         const double u2 = (double)ctr[1] * 2.3283064365386963e-10;
@@ -233,10 +216,10 @@ __global__ __launch_bounds__(256) void complete_columns_kernel(int64_t rows, int
 }
 
 int complete_columns(int64_t rows, int64_t c, double* X, int64_t ldx, double* L, int64_t ldl, double tau2,
-                     const int32_t* gate, hipStream_t s) {
+                     const int32_t* gate, hipStream_t s, int64_t col0) {
     if (rows <= 0 || c <= 0) return 0;
     hipLaunchKernelGGL(complete_columns_kernel, dim3((unsigned)c), dim3(256), 0, s, rows, c, X, ldx, L, ldl, tau2,
-                       gate);
+                       gate, col0);
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 

@@ -76,3 +76,41 @@ def test_block_rqlp_mixed_scaled_workload(gpu, kind):
     Q = to_np(f.Q).astype(np.float64)
     assert np.abs(Q.T @ Q - np.eye(l)).max() < 1e-4
     _check_blocks(to_np(f.P).astype(np.float64), l, b, 1e-5)
+
+
+@pytest.mark.parametrize("q", [0, 1])
+def test_block_rqlp_rank_deficient_block(gpu, q):
+    """rank(A) = 20 < l = 32 with blocks of 16: the second block row of B has
+    4 rows of A's range and 12 rows at rounding level, so its first CPQR stops
+    at rank 4 (Section 2: exact reconstruction when the sketch holds range(A)).
+    Trailing L-values exactly 0, Q orthonormal, each block of P orthonormal
+    (orthonormal completion), Q T P^T = A, leading L-values as the oracle's."""
+    m, n, k, p, b, rank = 600, 300, 24, 8, 16, 20
+    l = k + p
+    A = inputs.svd_matrix(m, n, np.linspace(1.0, 0.5, rank), 11)
+    Om = inputs.gaussian(n, l, 12)
+    f = gpu.factor(to_dev(A), k, p, q=q, b=b, Omega=to_dev(Om))
+    Q, T, P = to_np(f.Q), to_np(f.T), to_np(f.P)
+    lv, info = to_np(f.lvals), int(to_np(f.info)[0])
+    ref = brqlp(A, Om, k, p, b, q=q, deflate=False)
+    assert info & 0x2 and not info & (0x4 | 0x8 | 0x10 | 0x20), f"info {info:#x}"
+    assert np.all(lv[rank:] == 0.0)
+    assert np.max(np.abs(lv[:rank] - ref.lvals[:rank]) / ref.lvals[:rank]) < 1e-10
+    nA = np.linalg.norm(A)
+    assert np.linalg.norm(A - Q @ T @ P.T) < 1e-12 * nA
+    assert np.abs(Q.T @ Q - np.eye(l)).max() < 1e-12
+    _check_blocks(P, l, b, 1e-12)
+
+
+def test_block_rqlp_zero_matrix(gpu):
+    """A = 0: every block's first CPQR reports rank 0, T = 0, Q and every block
+    of P orthonormal."""
+    m, n, k, p, b = 80, 40, 10, 6, 4
+    A = np.zeros((m, n))
+    Om = inputs.gaussian(n, k + p, 3)
+    f = gpu.factor(to_dev(A), k, p, q=1, b=b, Omega=to_dev(Om))
+    Q, T, P, info = to_np(f.Q), to_np(f.T), to_np(f.P), int(to_np(f.info)[0])
+    assert np.all(T == 0.0) and np.all(to_np(f.lvals) == 0.0)
+    assert info & 0x2 and not info & (0x4 | 0x8 | 0x10)
+    assert np.abs(Q.T @ Q - np.eye(k + p)).max() < 1e-12
+    _check_blocks(P, k + p, b, 1e-12)
