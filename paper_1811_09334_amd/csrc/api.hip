@@ -395,15 +395,19 @@ struct BcgsScratch {
     size_t ws_elems;
 };
 
-// Block classical Gram-Schmidt with reorthogonalisation (the twice-applied
-// step 5 of Algorithm 4.1) over the rows x l panel V whose bs-column blocks
-// are already orthonormal: for every block j > 0, twice,
-// V_j <- V_j - V_{<j} (V_{<j}^T V_j), V_j <- qr(V_j).
-// Block Gram-Schmidt twice (BCGS2) of the blocks of bs columns after the
-// first (already orthonormal): each block is projected against the earlier
-// blocks and orthonormalised in place, twice; the first QR is one CholeskyQR
-// pass (with the conditional passes after a shifted retry), the second the
-// full form when `final` (CholeskyQR2), again one pass otherwise.
+// Block classical Gram-Schmidt (step 5 of Algorithm 4.1) over the rows x l
+// panel V whose first bs-column block is already orthonormal: every later
+// block V_j is projected against the earlier blocks,
+// V_j <- V_j - V_{<j} (V_{<j}^T V_j), and orthonormalised in place by one
+// CholeskyQR pass (plus the conditional passes after a shifted retry).  A
+// final basis takes the projection and the CholeskyQR twice (BCGS2, the
+// reorthogonalisation of Algorithm 4.1; the second CholeskyQR sees an almost
+// orthonormal block, so one FP32 pass gives orthogonality to working
+// precision; the FP64 path keeps the full form there).
+// An intermediate basis of the subspace iteration only has to span the same
+// block prefixes and be well conditioned: one projection and one CholeskyQR,
+// which leave a loss of orthogonality between blocks of about u / f (f: the
+// part of a block outside the span of the earlier ones, well above u here).
 template <typename T, typename CtxT>
 int bcgs2(CtxT& cx, int64_t rows, int64_t l, int64_t bs, T* V, int64_t ld, BcgsScratch& sc, bool final,
           hipStream_t s) {
@@ -413,10 +417,12 @@ int bcgs2(CtxT& cx, int64_t rows, int64_t l, int64_t bs, T* V, int64_t ld, BcgsS
     for (int64_t s0 = bs; s0 < l; s0 += bs) {
         const int64_t bj = (l - s0) < bs ? (l - s0) : bs;
         T* Vj = V + s0 * ld;
-        for (int pass = 0; pass < 2; ++pass) {
+        for (int pass = 0; pass < (final ? 2 : 1); ++pass) {
             RQLP_TRY(gemm<T>(true, false, s0, bj, rows, V, ld, Vj, ld, C, s0, false, T(1), T(0), ws, sc.ws_elems, s));
             RQLP_TRY(gemm<T>(false, false, rows, bj, s0, V, ld, C, s0, Vj, ld, false, T(-1), T(1), ws, sc.ws_elems, s));
-            const bool full = pass == 1 && final;
+            // FP64: the full form for the final basis (four passes after a
+            // shifted retry make numerically dependent blocks orthonormal)
+            const bool full = pass == 1 && final && sizeof(T) == sizeof(double);
             T* o = nullptr;
             if constexpr (sizeof(T) == sizeof(double)) {
                 RQLP_TRY(cholqr2(cx, rows, bj, (double*)Vj, (double*)p1, ld, nullptr, (double**)&o, full, s0));

@@ -723,10 +723,7 @@ int rows_class(int64_t bs) { return bs <= 16 ? 16 : (bs <= 32 ? 32 : 64); }
 
 template <int RB>
 int bcpqr_capacity() {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)bcpqr_kernel<RB>, BQ_T, 0) != hipSuccess)
-        nb = 0;
-    return nb * device_info().num_cus;
+    return resident_capacity((const void*)bcpqr_kernel<RB>, BQ_T, 0);
 }
 
 }  // namespace

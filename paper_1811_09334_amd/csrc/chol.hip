@@ -317,13 +317,7 @@ int chol_inv(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float
         return chol_mw<TG>(c, G, ldg, L, Linv, Linv32, ld, shift_scale, info, sync, s, run_flag, shifted_out,
                            shifted_mode, pivot_rel);
     const size_t lds = chol_inv_lds_bytes(c);
-    static bool attr_set = false;
-    if (!attr_set) {
-        RQLP_HIP_TRY(hipFuncSetAttribute((const void*)chol_inv_kernel<TG>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)chol_inv_lds_bytes(1 << 20)));
-        attr_set = true;
-    }
+    RQLP_TRY(raise_lds_limit((const void*)chol_inv_kernel<TG>, (int)chol_inv_lds_bytes(1 << 20)));
     hipLaunchKernelGGL((chol_inv_kernel<TG>), dim3(1), dim3(CH_T), lds, s, (int)c, G, ldg, shift_scale, L, Linv,
                        Linv32, ld, info, ch_prows(c), ch_xcols(c), run_flag, shifted_out, shifted_mode, pivot_rel);
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;

@@ -486,12 +486,7 @@ int chol_mw(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float*
     // per-process start value, so that flag words left in reused memory by
     // another process are unlikely to match
     static std::atomic<unsigned> epoch_counter{(unsigned)(getpid() * 2654435761u) ^ (unsigned)time(nullptr)};
-    static bool attr_set = false;
-    if (!attr_set) {
-        RQLP_HIP_TRY(hipFuncSetAttribute((const void*)chol_mw_kernel<TG>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)chol_mw_lds_bytes(CHOL_MW_MAXC)));
-        attr_set = true;
-    }
+    RQLP_TRY(raise_lds_limit((const void*)chol_mw_kernel<TG>, (int)chol_mw_lds_bytes(CHOL_MW_MAXC)));
     const int NB = (int)((c + 15) / 16);
     if (device_info().num_cus > 0 && NB > device_info().num_cus) return RQLP_E_UNSUPPORTED;
     const size_t lds = chol_mw_lds_bytes(c);

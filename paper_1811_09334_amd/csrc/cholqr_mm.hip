@@ -382,12 +382,7 @@ void launch_gram(const GramPlan& p, int64_t c, const T* X, int64_t ldx, T* ws, c
 template <typename T, int MAXB>
 int launch_trmm(int64_t R, int64_t c, const T* X, int64_t ldx, const T* Li, int64_t ldl, T* Y, int64_t ldy,
                 const int32_t* gate, int gate_copy, hipStream_t s) {
-    static bool attr_set = false;
-    if (!attr_set) {
-        RQLP_HIP_TRY(hipFuncSetAttribute((const void*)trmm_kernel<T, MAXB>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, 4096 * (CQ_MAXC / 16)));
-        attr_set = true;
-    }
+    RQLP_TRY(raise_lds_limit((const void*)trmm_kernel<T, MAXB>, 4096 * (CQ_MAXC / 16)));
     constexpr int RT = 16 * CqMfma<T>::VEC;
     const size_t lds = 4096 * (size_t)ceil_div(c, 16);
     hipLaunchKernelGGL((trmm_kernel<T, MAXB>), dim3((unsigned)ceil_div(R, RT)), dim3(TR_THREADS), lds, s, R, (int)c,

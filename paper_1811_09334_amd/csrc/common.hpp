@@ -48,13 +48,20 @@ struct Arena {
     bool ok() const { return used <= cap; }
 };
 
-// device properties cached per device (immutable after first query)
+// device properties cached per device (immutable after the first query, thread-safe)
 struct DeviceInfo {
     int device = -1;
     int num_cus = 0;
     size_t max_lds = 0;
 };
 const DeviceInfo& device_info();
+// Raises the dynamic LDS limit of kernel fn to `bytes` on the current device,
+// once per device (thread-safe).  RQLP_E_HIP on failure.
+int raise_lds_limit(const void* fn, int bytes);
+// Workgroups of `block` threads with `lds` dynamic LDS bytes of kernel fn that
+// the current device holds at once (occupancy x compute units), cached per
+// device (thread-safe); 0 if the query fails.
+int resident_capacity(const void* fn, int block, size_t lds);
 
 // ---------------------------------------------------------------------------
 // device helpers

@@ -852,15 +852,7 @@ static int cpqr_rpt(int64_t rows) {
 
 template <int RPT>
 static int cpqr_reg_capacity() {
-    static int cap = -1;
-    if (cap < 0) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)cpqr_reg_kernel<RPT>, CP_T, 0) !=
-            hipSuccess)
-            nb = 0;
-        cap = nb * (device_info().num_cus > 0 ? device_info().num_cus : 0);
-    }
-    return cap;
+    return resident_capacity((const void*)cpqr_reg_kernel<RPT>, CP_T, 0);
 }
 
 static int cpqr_reg_cap(int rpt) {
@@ -947,14 +939,10 @@ int cpqr(const double* M, int64_t ldm, int64_t rows, int64_t cols, const CpqrScr
     int ibits = index_bits(cols);
     int rows_i = (int)rows, cols_i = (int)cols, cpw = plan.cpw, kmax_i = (int)kmax;
     unsigned long long spin = CP_SPIN_LIMIT;
-    static bool attr_set = false;
-    if (!attr_set) {
+    {
         const int mx = (int)(device_info().max_lds > 0 ? device_info().max_lds : 65536);
-        RQLP_HIP_TRY(hipFuncSetAttribute((const void*)cpqr_kernel<true>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, mx));
-        RQLP_HIP_TRY(hipFuncSetAttribute((const void*)cpqr_kernel<false>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, mx));
-        attr_set = true;
+        RQLP_TRY(raise_lds_limit((const void*)cpqr_kernel<true>, mx));
+        RQLP_TRY(raise_lds_limit((const void*)cpqr_kernel<false>, mx));
     }
     if (plan.single) {
         hipLaunchKernelGGL(cpqr_kernel<true>, dim3(1), dim3(CP_T), plan.lds, s, M, ldm, rows_i, cols_i, cpw,
@@ -990,10 +978,8 @@ int cpqr(const double* M, int64_t ldm, int64_t rows, int64_t cols, const CpqrScr
 #undef RQLP_CPR
         return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
     }
-    int nb = 0;
-    RQLP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)cpqr_kernel<false>, CP_T,
-                                                             plan.lds));
-    if ((int64_t)nb * device_info().num_cus < plan.G) return RQLP_E_UNSUPPORTED;
+    if ((int64_t)resident_capacity((const void*)cpqr_kernel<false>, CP_T, plan.lds) < plan.G)
+        return RQLP_E_UNSUPPORTED;
     hipLaunchKernelGGL(cpqr_kernel<false>, dim3(plan.G), dim3(CP_T), plan.lds, s, M, ldm, rows_i, cols_i, cpw,
                        kmax_i, ibits, sc.keys, sc.candcol, sc.partial, sc.bar, piv, Vh, ldv, beta, Rpiv, ldr, Rt,
                        ldrt, info, spin);

@@ -3,15 +3,40 @@
 #include <hip/hip_fp16.h>
 #include <math.h>
 
+#include <mutex>
+#include <vector>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace rqlp {
 
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_cache_mu;      // guards every per-device cache of this file
+struct FnEntry {
+    int device;
+    const void* fn;
+    int block;
+    size_t lds;
+    int value;
+};
+// never destroyed: nothing of this library runs code at process exit
+std::vector<FnEntry>& fn_cache() {
+    static std::vector<FnEntry>* v = new std::vector<FnEntry>();
+    return *v;
+}
+}  // namespace
+
+// Device properties, queried once per device (the current device of the
+// calling thread); entries are written once under the lock and never change.
 const DeviceInfo& device_info() {
-    static DeviceInfo di;
+    static DeviceInfo table[kMaxDevices];
+    static const DeviceInfo none;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return di;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return none;
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    DeviceInfo& di = table[dev];
     if (di.device != dev) {
         DeviceInfo n;
         n.device = dev;
@@ -24,6 +49,31 @@ const DeviceInfo& device_info() {
         di = n;
     }
     return di;
+}
+
+int raise_lds_limit(const void* fn, int bytes) {
+    int dev = 0;
+    RQLP_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    for (const FnEntry& e : fn_cache())
+        if (e.device == dev && e.fn == fn && e.block == -1) return 0;
+    RQLP_HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    fn_cache().push_back(FnEntry{dev, fn, -1, (size_t)bytes, 0});
+    return 0;
+}
+
+int resident_capacity(const void* fn, int block, size_t lds) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    const int cus = device_info().num_cus;
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    for (const FnEntry& e : fn_cache())
+        if (e.device == dev && e.fn == fn && e.block == block && e.lds == lds) return e.value;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, lds) != hipSuccess) nb = 0;
+    const int cap = nb * (cus > 0 ? cus : 0);
+    fn_cache().push_back(FnEntry{dev, fn, block, lds, cap});
+    return cap;
 }
 
 __global__ void fill_zero_kernel(uint32_t* p, size_t words) {
