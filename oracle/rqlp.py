@@ -201,6 +201,70 @@ def brqlp(A: np.ndarray, Omega: np.ndarray, k: int, p: int, b: int, q: int = 0,
 
 
 # ---------------------------------------------------------------------------
+# auto-rank (fixed-accuracy) RQLP (Section 6, with the identity (fixedrank) of
+# Section 2)
+# ---------------------------------------------------------------------------
+def autorank_rqlp(A: np.ndarray, Omega: np.ndarray, b: int, eps: float, q: int = 0,
+                  piv0: Optional[Sequence[int]] = None, piv1: Optional[Sequence[int]] = None) -> QLPResult:
+    """Block RQLP whose rank is set by an accuracy tolerance.
+
+    The basis grows one block of b columns of Omega at a time (Algorithm 4.1:
+    range finder on the original A, reorthogonalisation twice against the
+    earlier blocks, B_j = V_j^T A); after each block the error indicator
+    ||E||_F^2 = ||A||_F^2 - ||B||_F^2 of Section 6 (the identity (fixedrank):
+    it equals ||A - V V^T A||_F^2) is evaluated with B the blocks so far, and
+    the loop stops at the first block where it is <= eps, or when the columns
+    of Omega (n x lmax) are used up.  The pivoted QLPs of the blocks taken
+    then give Q, T = blkdiag(L_j), P as in Algorithm 4.1.  extra["rank"] is
+    the number of columns taken, extra["err2"] the indicator there,
+    extra["err2_history"] its value after each block, extra["converged"]
+    whether it reached eps.  piv0 / piv1 freeze the per-block pivots."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    lmax = Omega.shape[1]
+    normA2 = float(np.sum(A * A))
+    normB2 = 0.0
+    Vs, Bs, hist = [], [], []
+    s0 = 0
+    while s0 < lmax:
+        s1 = min(lmax, s0 + b)
+        Vj = range_finder(A, Omega[:, s0:s1], q)
+        for _ in range(2):
+            if Vs:
+                Vprev = np.hstack(Vs)
+                Vj = Vj - Vprev @ (Vprev.T @ Vj)
+            Vj = orthonormal_basis(Vj)
+        Bj = Vj.T @ A
+        Vs.append(Vj)
+        Bs.append(Bj)
+        normB2 += float(np.sum(Bj * Bj))
+        hist.append(normA2 - normB2)
+        s0 = s1
+        if hist[-1] <= eps:
+            break
+    l = s0
+    Qs, Ps, Ts, p0s, p1s = [], [], [], [], []
+    for j, (Vj, Bj) in enumerate(zip(Vs, Bs)):
+        a, e = j * b, j * b + Bj.shape[0]
+        f0 = None if piv0 is None else np.asarray(piv0)[a:e]
+        f1 = None if piv1 is None else np.asarray(piv1)[a:e]
+        QB, Lj, PB, p0, p1, _, _ = qlp_reduced(Bj, 0, f0, f1)
+        Qs.append(Vj @ QB)
+        Ps.append(PB)
+        Ts.append(Lj)
+        p0s.append(p0)
+        p1s.append(p1)
+    T = np.zeros((l, l))
+    for j, Lj in enumerate(Ts):
+        T[j * b:j * b + Lj.shape[0], j * b:j * b + Lj.shape[1]] = Lj
+    V = np.hstack(Vs)
+    return QLPResult(Q=np.hstack(Qs), T=T, P=np.hstack(Ps), piv0=np.concatenate(p0s),
+                     piv1=np.concatenate(p1s), uplo="L", rank0=l, V=V, B=np.vstack(Bs),
+                     extra={"rank": l, "err2": hist[-1], "err2_history": hist, "normA2": normA2,
+                            "converged": hist[-1] <= eps})
+
+
+# ---------------------------------------------------------------------------
 # deterministic pivoted QLP (Stewart; eq. (1.2))
 # ---------------------------------------------------------------------------
 def stewart_qlp(A: np.ndarray):
