@@ -73,6 +73,7 @@ enum rqlp_status {
 #define RQLP_INFO_BARRIER_TIMEOUT  0x8  /* a grid-wide wait exceeded its spin bound  */
 #define RQLP_INFO_CHOL_FAILED      0x10 /* Cholesky failed even after the shift      */
 #define RQLP_INFO_BAD_PIVOTS       0x20 /* rqlp_backward: frozen pivots not valid    */
+#define RQLP_INFO_NOT_CONVERGED    0x40 /* rqlp_factor_autorank: eps not reached     */
 
 /* Library version string (host, static storage). */
 const char* rqlp_version(void);
@@ -163,6 +164,49 @@ int rqlp_factor_noalloc(const void* A, int64_t lda, int64_t m, int64_t n, int64_
                         void* Q, int64_t ldq, double* T, int64_t ldt, void* P, int64_t ldp,
                         int64_t* piv0, int64_t* piv1, double* lvals, int32_t* info, char* uplo,
                         void* stream);
+
+/* Auto-rank (fixed-accuracy) randomized QLP (Section 6): the rank is set by
+ * an accuracy tolerance instead of k.  The basis grows one block of b
+ * columns of Omega at a time as in Algorithm 4.1 (q subspace iterations,
+ * block orthonormalisation against the earlier blocks), and stops at the
+ * first block where the error indicator
+ *     ||E||_F^2 = ||A||_F^2 - ||B||_F^2,   B = V^T A of the blocks so far,
+ * (equal to ||A - Q T P^T||_F^2 by the identity (fixedrank) of Section 2) is
+ * <= eps, or when lmax columns are used.  The factorisation of the columns
+ * taken is block RQLP's (T = blkdiag(L_j), each b-column block of P
+ * orthonormal).
+ *
+ *   A, lda, m, n, q, precision, seed, Omega (n x lmax), ldo: as for
+ *          rqlp_factor.
+ *   lmax   largest rank, 1 <= lmax <= n (the columns of Omega).
+ *   b      block size >= 1 (b >= lmax: one block, plain RQLP of lmax columns).
+ *   eps    tolerance on ||E||_F^2 (absolute, >= 0).  It must lie above the
+ *          rounding level of ||A||_F^2 - ||B||_F^2 in the chosen precision:
+ *          about 1e-15 ||A||_F^2 in FP64, 1e-6 in FP32, 1e-3 for the 16-bit
+ *          products.
+ *   Q (m x lmax), T (lmax x lmax, lower triangular), P (n x lmax),
+ *   piv0, piv1, lvals (lmax each): as for rqlp_factor on the columns taken;
+ *          past the rank the columns of Q and P and all of T there are zero,
+ *          the pivots -1 and the L-values 0.
+ *   info   device word: RQLP_INFO_* flags; RQLP_INFO_NOT_CONVERGED when eps
+ *          was not reached with lmax columns.
+ *   rank   host out: the number of columns taken (a multiple of b, or lmax).
+ *   err2   host out (may be NULL): ||E||_F^2 at that rank.
+ *   work   device workspace of rqlp_autorank_workspace_size() bytes.
+ * The stopping block is read back to the host: unlike the other entry points
+ * this call synchronises `stream` once (after the range finder) and returns
+ * after enqueueing the rest.  This implementation evaluates the basis over
+ * all lmax columns in one blocked pass (every prefix of its blocks is the
+ * basis the block-by-block loop builds) and factorises only the blocks taken,
+ * so its cost grows with lmax, not with the rank found. */
+int rqlp_autorank_workspace_size(int64_t m, int64_t n, int64_t lmax, int64_t b, int q, int precision,
+                                 size_t* bytes);
+int rqlp_factor_autorank(const void* A, int64_t lda, int64_t m, int64_t n, int64_t lmax, int64_t b,
+                         int q, double eps, int precision, uint64_t seed,
+                         const void* Omega, int64_t ldo,
+                         void* Q, int64_t ldq, double* T, int64_t ldt, void* P, int64_t ldp,
+                         int64_t* piv0, int64_t* piv1, double* lvals, int32_t* info,
+                         int64_t* rank, double* err2, void* work, size_t work_bytes, void* stream);
 
 /* ---- building blocks (the steps of Algorithm 2.1, usable on their own) ---- */
 

@@ -19,7 +19,7 @@ from . import _lib
 
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2, "fp16": 3, "bf16x3": 4}
 INFO_FLAGS = {"cholqr_shifted": 0x1, "rank_deficient": 0x2, "nonfinite": 0x4, "barrier_timeout": 0x8,
-              "chol_failed": 0x10, "bad_pivots": 0x20}
+              "chol_failed": 0x10, "bad_pivots": 0x20, "not_converged": 0x40}
 
 
 def _torch():
@@ -127,6 +127,47 @@ def factor(A, k: int, p: int, q: int = 0, d: int = 0, b: int = 0, precision="f64
                           ctypes.byref(uplo), work.data_ptr(), work.numel(), _stream(dev))
     check("rqlp_factor", st)
     return Factorization(Q=Q, T=T, P=P, piv0=piv0, piv1=piv1, lvals=lv, info=info, uplo=uplo.value.decode())
+
+
+def factor_autorank(A, lmax: int, b: int, eps: float, q: int = 0, precision="f64", seed: int = 0, Omega=None,
+                    work=None):
+    """Auto-rank randomized QLP of the device matrix ``A`` through
+    ``rqlp_factor_autorank``: returns (Factorization with lmax columns, rank,
+    err2); the columns past ``rank`` are zero."""
+    torch = _torch()
+    load()
+    prec = _prec(precision)
+    dt = _elem_dtype(prec)
+    if A.dtype != dt:
+        raise TypeError(f"A must be {dt} for precision {precision}")
+    A = colmajor(A)
+    m, n = A.shape
+    dev = A.device
+    if Omega is not None:
+        if Omega.dtype != dt or tuple(Omega.shape) != (n, lmax):
+            raise ValueError("Omega must be n x lmax with the element type of A")
+        Omega = colmajor(Omega)
+    Q = empty_colmajor(m, lmax, dt, dev)
+    T = empty_colmajor(lmax, lmax, torch.float64, dev)
+    P = empty_colmajor(n, lmax, dt, dev)
+    piv0 = torch.empty(lmax, dtype=torch.int64, device=dev)
+    piv1 = torch.empty(lmax, dtype=torch.int64, device=dev)
+    lv = torch.empty(lmax, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    nbytes = _lib.rqlp_autorank_workspace_size(m, n, lmax, b, q, prec)
+    if work is None or work.numel() < nbytes:
+        work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    rank = ctypes.c_int64(0)
+    err2 = ctypes.c_double(0.0)
+    st = _lib.rqlp_factor_autorank(A.data_ptr(), ld(A), m, n, lmax, b, q, float(eps), prec, seed,
+                                   _ptr(Omega), ld(Omega) if Omega is not None else max(n, 1),
+                                   Q.data_ptr(), ld(Q), T.data_ptr(), ld(T), P.data_ptr(), ld(P),
+                                   piv0.data_ptr(), piv1.data_ptr(), lv.data_ptr(), info.data_ptr(),
+                                   ctypes.byref(rank), ctypes.byref(err2), work.data_ptr(), work.numel(),
+                                   _stream(dev))
+    check("rqlp_factor_autorank", st)
+    f = Factorization(Q=Q, T=T, P=P, piv0=piv0, piv1=piv1, lvals=lv, info=info, uplo="L")
+    return f, rank.value, err2.value
 
 
 def backward(A, k: int, p: int, piv0, piv1, dT, q: int = 0, d: int = 0, b: int = 0, precision=None, seed: int = 0,

@@ -696,20 +696,34 @@ int rqlp_generate_omega(int64_t n, int64_t l, uint64_t seed, int precision, void
     return generate_omega(n, l, seed, precision, Omega, ldo, (hipStream_t)stream);
 }
 
-int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int64_t p, int q, int d, int b,
-                int precision, uint64_t seed, const void* Omega, int64_t ldo, void* Q, int64_t ldq, double* T,
-                int64_t ldt, void* P, int64_t ldp, int64_t* piv0, int64_t* piv1, double* lvals, int32_t* info,
-                char* uplo, void* work, size_t work_bytes, void* stream) {
-    RQLP_TRY(rqlp::factor_arg_status(A, lda, m, n, k, p, q, d, b, precision, Omega, ldo, Q, ldq, T, ldt, P, ldp));
-    const int64_t l = k + p;
-    if (!work) return -25;
-    // block RQLP with b >= l is a single block: plain RQLP
-    const int64_t bs = (b > 0 && b < l) ? b : 0;
+}  // extern "C"
 
-    hipStream_t s = (hipStream_t)stream;
+namespace {
+
+// Auto-rank request of factor_core: after the range finder, the first block
+// count J with ||A||_F^2 - ||B_1..J||_F^2 <= eps is read back to the host
+// (the one synchronisation of the call) and only those blocks are factorised.
+struct AutoRank {
+    double eps;
+    int64_t* rank;      // host out: columns taken
+    double* err2;       // host out: indicator at the rank (may be NULL)
+};
+
+// The enqueue order of rqlp_factor (arguments already checked) over l
+// columns; with ar != NULL the auto-rank truncation described above.
+int factor_core(const void* A, int64_t lda, int64_t m, int64_t n, int64_t l, int q, int d, int64_t bs, int precision,
+                uint64_t seed, const void* Omega, int64_t ldo, void* Q, int64_t ldq, double* T, int64_t ldt, void* P,
+                int64_t ldp, int64_t* piv0, int64_t* piv1, double* lvals, int32_t* info, char* uplo, void* work,
+                size_t work_bytes, hipStream_t s, AutoRank* arq) {
     Arena ar = arena_for(work, work_bytes);
     FactorLayout Lay;
     carve_factor(ar, m, n, l, precision, Omega == nullptr, bs, &Lay);
+    double* ar_out = nullptr;
+    double* ar_scratch = nullptr;
+    if (arq) {
+        ar_out = ar.take<double>(4);
+        ar_scratch = ar.take<double>(autorank_scratch_doubles(n, l, bs));
+    }
     if (!ar.ok()) return RQLP_E_WORKSPACE;
     SmallBufs& f = Lay.sm;
     {
@@ -739,6 +753,33 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
                                       (const float*)Omega, ldo, &V32, bs, Lay.bc));
     double* Pd = f64 ? (double*)P : r.Pd;
     const int64_t ldpd = f64 ? ldp : n;
+    // leading columns factorised (all l, or the auto-rank prefix)
+    int64_t le = l;
+    if (arq) {
+        if (f64)
+            RQLP_TRY(autorank_indicator<double>((const double*)A, lda, m, n, f.B, l, l, bs, arq->eps, ar_scratch,
+                                                ar_out, s));
+        else
+            RQLP_TRY(autorank_indicator<float>((const float*)A, lda, m, n, f.B, l, l, bs, arq->eps, ar_scratch,
+                                               ar_out, s));
+        double h[3] = {0.0, 0.0, 0.0};
+        RQLP_HIP_TRY(hipMemcpyAsync(h, ar_out, sizeof(h), hipMemcpyDeviceToHost, s));
+        RQLP_HIP_TRY(hipStreamSynchronize(s));
+        const int64_t J = (int64_t)h[0];
+        le = (bs > 0 && J * bs < l) ? J * bs : l;
+        *arq->rank = le;
+        if (arq->err2) *arq->err2 = h[1];
+        if (!(h[1] <= arq->eps)) RQLP_TRY(set_info_flag(inf, RQLP_INFO_NOT_CONVERGED, s));
+        // outputs past the rank: zero columns, pivots -1 (T is cleared below)
+        RQLP_TRY(zero_cols<double>(l, 0, l, T, ldt, s));
+        if (le < l) {
+            if (f64) RQLP_TRY(zero_cols<double>(m, le, l, (double*)Q, ldq, s));
+            else RQLP_TRY(zero_cols<float>(m, le, l, (float*)Q, ldq, s));
+            RQLP_TRY(zero_cols<double>(n, le, l, Pd, ldpd, s));
+            if (piv0) RQLP_TRY(fill_i64(l - le, piv0 + le, -1, s));
+            if (piv1) RQLP_TRY(fill_i64(l - le, piv1 + le, -1, s));
+        }
+    }
     if (bs == 0) {
         RQLP_TRY(qlp_of_B(cx, f, l, n, d, Pd, ldpd, T, ldt, &tri, &QB));
         // assembly: Q = V Q_B
@@ -752,22 +793,22 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
         }
         if (piv0) RQLP_TRY(copy_i64(l, f.piv0, piv0, s));
         if (piv1) RQLP_TRY(copy_i64(l, d == 0 ? f.piv1 : nullptr, piv1, s));
-    } else if (bqlp_supported(n, l, bs)) {
+    } else if (bqlp_supported(n, le, bs)) {
         // Algorithm 4.1 steps 6-7 for all blocks at once (batched kernels)
         if (f64)
-            RQLP_TRY(bqlp<double>(f.B, l, n, l, bs, Lay.bq, f.Z, V64, m, m, (double*)Q, ldq, Pd, ldpd, T, ldt, f.piv0,
-                                  f.piv1, inf, s));
+            RQLP_TRY(bqlp<double>(f.B, l, n, le, bs, Lay.bq, f.Z, V64, m, m, (double*)Q, ldq, Pd, ldpd, T, ldt,
+                                  f.piv0, f.piv1, inf, s));
         else
-            RQLP_TRY(bqlp<float>(f.B, l, n, l, bs, Lay.bq, f.Z, V32, m, m, (float*)Q, ldq, Pd, ldpd, T, ldt, f.piv0,
-                                 f.piv1, inf, s));
-        if (piv0) RQLP_TRY(copy_i64(l, f.piv0, piv0, s));
-        if (piv1) RQLP_TRY(copy_i64(l, f.piv1, piv1, s));
+            RQLP_TRY(bqlp<float>(f.B, l, n, le, bs, Lay.bq, f.Z, V32, m, m, (float*)Q, ldq, Pd, ldpd, T, ldt,
+                                 f.piv0, f.piv1, inf, s));
+        if (piv0) RQLP_TRY(copy_i64(le, f.piv0, piv0, s));
+        if (piv1) RQLP_TRY(copy_i64(le, f.piv1, piv1, s));
     } else {
         // Algorithm 4.1 steps 6-7, block by block: B_j = V_j^T A is block row j
         // of B; pivoted QLP of B_j; Q_j = V_j Q_B(j), P_j = P_B(j); T = blkdiag(L_j)
-        RQLP_TRY(set_identity(l, T, ldt, s));
-        for (int64_t s0 = 0; s0 < l; s0 += bs) {
-            const int64_t bj = (l - s0) < bs ? (l - s0) : bs;
+        RQLP_TRY(set_identity(le, T, ldt, s));
+        for (int64_t s0 = 0; s0 < le; s0 += bs) {
+            const int64_t bj = (le - s0) < bs ? (le - s0) : bs;
             RQLP_TRY(copy_matrix(bj, n, f.B + s0, l, Lay.Bj, bj, s));
             SmallBufs fj = f;
             fj.B = Lay.Bj;
@@ -789,6 +830,74 @@ int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int
     RQLP_TRY(finish_lvals(l, T, ldt, lvals, inf, s));
     if (uplo) *uplo = tri;
     return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rqlp_factor(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, int64_t p, int q, int d, int b,
+                int precision, uint64_t seed, const void* Omega, int64_t ldo, void* Q, int64_t ldq, double* T,
+                int64_t ldt, void* P, int64_t ldp, int64_t* piv0, int64_t* piv1, double* lvals, int32_t* info,
+                char* uplo, void* work, size_t work_bytes, void* stream) {
+    RQLP_TRY(rqlp::factor_arg_status(A, lda, m, n, k, p, q, d, b, precision, Omega, ldo, Q, ldq, T, ldt, P, ldp));
+    const int64_t l = k + p;
+    if (!work) return -25;
+    // block RQLP with b >= l is a single block: plain RQLP
+    const int64_t bs = (b > 0 && b < l) ? b : 0;
+    return factor_core(A, lda, m, n, l, q, d, bs, precision, seed, Omega, ldo, Q, ldq, T, ldt, P, ldp, piv0, piv1,
+                       lvals, info, uplo, work, work_bytes, (hipStream_t)stream, nullptr);
+}
+
+namespace {
+int check_autorank_args(const void* A, int64_t lda, int64_t m, int64_t n, int64_t lmax, int64_t b, int q, double eps,
+                        int precision) {
+    if (m < 1) return -3;
+    if (n < 1 || n > m) return -4;
+    if (lda < m) return -2;
+    if (lmax < 1 || lmax > n) return -5;
+    if (b < 1) return -6;
+    if (q < 0) return -7;
+    if (!(eps >= 0.0)) return -8;
+    if (!valid_precision(precision)) return -9;
+    if (A == nullptr) return -1;
+    return 0;
+}
+}  // namespace
+
+int rqlp_autorank_workspace_size(int64_t m, int64_t n, int64_t lmax, int64_t b, int q, int precision,
+                                 size_t* bytes) {
+    RQLP_TRY(check_autorank_args((const void*)1, m, m, n, lmax, b, q, 0.0, precision));
+    if (!bytes) return -7;
+    const int64_t bs = b < lmax ? b : 0;
+    Arena ar(nullptr, 0);
+    FactorLayout L;
+    carve_factor(ar, m, n, lmax, precision, true, bs, &L);
+    ar.take<double>(4);
+    ar.take<double>(autorank_scratch_doubles(n, lmax, bs));
+    *bytes = ar.used + 256;
+    return 0;
+}
+
+int rqlp_factor_autorank(const void* A, int64_t lda, int64_t m, int64_t n, int64_t lmax, int64_t b, int q,
+                         double eps, int precision, uint64_t seed, const void* Omega, int64_t ldo, void* Q,
+                         int64_t ldq, double* T, int64_t ldt, void* P, int64_t ldp, int64_t* piv0, int64_t* piv1,
+                         double* lvals, int32_t* info, int64_t* rank, double* err2, void* work, size_t work_bytes,
+                         void* stream) {
+    RQLP_TRY(check_autorank_args(A, lda, m, n, lmax, b, q, eps, precision));
+    if (Omega && ldo < n) return -12;
+    if (!Q) return -13;
+    if (ldq < m) return -14;
+    if (!T) return -15;
+    if (ldt < lmax) return -16;
+    if (!P) return -17;
+    if (ldp < n) return -18;
+    if (!rank) return -23;
+    if (!work) return -25;
+    AutoRank arq{eps, rank, err2};
+    const int64_t bs = b < lmax ? b : 0;
+    return factor_core(A, lda, m, n, lmax, q, 0, bs, precision, seed, Omega, ldo, Q, ldq, T, ldt, P, ldp, piv0, piv1,
+                       lvals, info, nullptr, work, work_bytes, (hipStream_t)stream, &arq);
 }
 
 // ---- building blocks ----

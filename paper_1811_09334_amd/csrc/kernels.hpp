@@ -171,6 +171,24 @@ int bqlp(const double* B, int64_t ldb, int64_t n, int64_t l, int64_t bs, const B
          const TV* V, int64_t ldv, int64_t m, TV* Q, int64_t ldq, double* Pd, int64_t ldpd, double* T, int64_t ldt,
          int64_t* piv0, int64_t* piv1, int32_t* info, hipStream_t s);
 
+// --- autorank.hip: the error indicator of auto-rank RQLP (Section 6) --------
+constexpr int AR_FROB_PARTS = 1024;
+// doubles of scratch autorank_indicator needs
+size_t autorank_scratch_doubles(int64_t n, int64_t l, int64_t bs);
+// From A (m x n) and the block rows of B (l x n, blocks of bs rows; bs = 0:
+// one block): out3[0] = J, the first block count (1-based) at which
+// ||A||_F^2 - ||B_{1..J}||_F^2 <= eps (the number of blocks when none),
+// out3[1] = that indicator, out3[2] = ||A||_F^2 (device doubles).
+template <typename T>
+int autorank_indicator(const T* A, int64_t lda, int64_t m, int64_t n, const double* B, int64_t ldb, int64_t l,
+                       int64_t bs, double eps, double* scratch, double* out3, hipStream_t s);
+// X(:, c0:c1) = 0 (rows x ..., leading dimension ldx)
+template <typename T>
+int zero_cols(int64_t rows, int64_t c0, int64_t c1, T* X, int64_t ldx, hipStream_t s);
+int fill_i64(int64_t n, int64_t* p, int64_t v, hipStream_t s);
+// *info |= bit (device word, one thread)
+int set_info_flag(int32_t* info, int32_t bit, hipStream_t s);
+
 // --- misc.hip ---------------------------------------------------------------
 // Columns of X (rows x c) whose squared norm is <= tau2 are replaced by
 // N(0, 1/rows) vectors (Philox4x32-10 counter (i, col0 + j, 1, 0), fixed

@@ -192,6 +192,23 @@ WORKLOADS = {
 }
 
 
+# Example 5.1 of Section 5 (Tables 1-2): m = n, k = 120, p = 5, q = 0, the
+# pds (t = 30, s = 2) and eds (t = 30, s = 1/20) spectra with Haar factors
+# (the paper's random orthogonal factors are not specified), FP64.
+PAPER_EXAMPLE_SIZES = (2000, 4000, 6000)
+
+
+def paper_example(example: str, n: int, d: int = 0) -> Workload:
+    """The Section 5 replica workload ``example`` ('pds' or 'eds') at m = n."""
+    if example not in ("pds", "eds"):
+        raise ValueError(example)
+    spec = spectrum_pds if example == "pds" else spectrum_eds
+    idx = PAPER_EXAMPLE_SIZES.index(n) if n in PAPER_EXAMPLE_SIZES else 9
+    base = 1100 if example == "pds" else 1200
+    return Workload(f"{example}_{n}", n, n, 120, 5, 0, d, 0, "f64", "f64", "svd", spec, None, 0.0,
+                    base + idx, base + 50 + idx)
+
+
 def make_matrix(w: Workload) -> np.ndarray:
     """Build A for workload ``w`` with NumPy (FP64 values, Fortran order).
 

@@ -160,3 +160,29 @@ def test_backward_workspace_query(lib):
     assert b >= 4 * (16384 + 4096) * 4 * 136          # the two (2q + 2) l panels
     with pytest.raises(rq.RQLPError):
         rq._lib.rqlp_backward_workspace_size(100, 50, 5, 3, 0, 1, 0, 0)
+
+
+def _autorank_status(**kw):
+    import ctypes as ct
+    a = dict(A=1, lda=100, m=100, n=50, lmax=20, b=8, q=0, eps=1e-3, precision=0, seed=0, Omega=None, ldo=50,
+             Q=1, ldq=100, T=1, ldt=20, P=1, ldp=50, piv0=None, piv1=None, lvals=None, info=None,
+             rank=ct.byref(ct.c_int64(0)), err2=None, work=1, work_bytes=0, stream=None)
+    a.update(kw)
+    return _lib.rqlp_factor_autorank(*a.values())
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(A=None), -1), (dict(lda=99), -2), (dict(m=0), -3), (dict(n=101), -4), (dict(lmax=0), -5),
+    (dict(lmax=51), -5), (dict(b=0), -6), (dict(q=-1), -7), (dict(eps=-1.0), -8), (dict(eps=float("nan")), -8),
+    (dict(precision=9), -9), (dict(Omega=1, ldo=49), -12), (dict(Q=None), -13), (dict(ldq=99), -14),
+    (dict(T=None), -15), (dict(ldt=19), -16), (dict(P=None), -17), (dict(ldp=49), -18), (dict(rank=None), -23),
+    (dict(work=None), -25),
+])
+def test_autorank_argument_errors(lib, kw, code):
+    assert _autorank_status(**kw) == code
+
+
+def test_autorank_workspace_query(lib):
+    assert _lib.rqlp_autorank_workspace_size(1000, 500, 64, 16, 1, 0) > 0
+    with pytest.raises(_lib.RQLPError):
+        _lib.rqlp_autorank_workspace_size(1000, 500, 501, 16, 1, 0)
