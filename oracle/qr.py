@@ -57,10 +57,11 @@ def _apply(v: np.ndarray, M: np.ndarray) -> None:
 
 
 def _householder_qr(M: np.ndarray, piv: Optional[Sequence[int]], pivoting: bool,
-                    tol: Optional[float], want_q: bool, want_trace: bool = False) -> QRResult:
+                    tol: Optional[float], want_q: bool, want_trace: bool = False,
+                    steps: Optional[int] = None) -> QRResult:
     R = np.array(M, dtype=np.float64, copy=True, order="F")
     rows, cols = R.shape
-    kmax = min(rows, cols)
+    kmax = min(rows, cols) if steps is None else min(rows, cols, int(steps))
     perm = np.arange(cols)
     if tol is None:
         tol = max(rows, cols) * EPS * float(np.sqrt(np.sum(R * R)))
@@ -114,14 +115,17 @@ def _householder_qr(M: np.ndarray, piv: Optional[Sequence[int]], pivoting: bool,
 
 
 def cpqr(M: np.ndarray, piv: Optional[Sequence[int]] = None, tol: Optional[float] = None,
-         want_q: bool = True, want_trace: bool = False) -> QRResult:
+         want_q: bool = True, want_trace: bool = False, steps: Optional[int] = None) -> QRResult:
     """Column-pivoted QR M[:, perm] = Q R (Businger-Golub, exact norm recompute).
 
     ``piv`` (optional) freezes the first min(rows, cols) pivots (original
     column indices); the rank stop is then disabled.  ``want_trace`` records,
     for every step, the largest residual column norm, the norm of the column
-    taken and the second largest norm (used to judge pivot ties)."""
-    return _householder_qr(M, piv, True, tol, want_q, want_trace)
+    taken and the second largest norm (used to judge pivot ties).  ``steps``
+    (optional) stops after that many Householder steps (truncated CPQR): Q has
+    ``steps`` columns, R is steps x cols, perm[:steps] are the pivots and the
+    other columns of R hold the leading rows of the untouched trailing block."""
+    return _householder_qr(M, piv, True, tol, want_q, want_trace, steps)
 
 
 def householder_qr(M: np.ndarray, want_q: bool = True) -> QRResult:

@@ -267,10 +267,14 @@ def autorank_rqlp(A: np.ndarray, Omega: np.ndarray, b: int, eps: float, q: int =
 # ---------------------------------------------------------------------------
 # deterministic pivoted QLP (Stewart; eq. (1.2))
 # ---------------------------------------------------------------------------
-def stewart_qlp(A: np.ndarray):
-    """A Pi0 = Qhat R, R^T Pi1 = Phat L^T; returns (Q, L, P) with A = Q L P^T."""
+def stewart_qlp(A: np.ndarray, kt: Optional[int] = None):
+    """A Pi0 = Qhat R, R^T Pi1 = Phat L^T; returns (Q, L, P, piv0, piv1) with
+    A = Q L P^T.  ``kt`` (optional): the truncated pivoted QLP, the first CPQR
+    stopped after kt steps (R is kt x n) and the second one on its kt x n R;
+    then Q L P^T = Qhat_kt R Pi0^T, A's projection on the first kt columns of
+    Qhat."""
     A = np.asarray(A, dtype=np.float64)
-    f0 = cpqr(A)
+    f0 = cpqr(A, steps=kt)
     f1 = cpqr(f0.R.T)
     Q = f0.Q[:, f1.perm]
     P = _rows_by_perm(f0.perm, f1.Q)

@@ -281,3 +281,33 @@ def test_block_range_finder_spans_power_iterate_of_leading_blocks(q):
         Qd, _ = np.linalg.qr(Y)
         Vj = rb.V[:, :s1]
         assert np.linalg.norm(Vj @ Vj.T - Qd @ Qd.T, 2) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# truncated pivoted QLP (Stewart, eq. (1.2), first CPQR stopped after kt steps)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape,kt", [((60, 40), 12), ((50, 50), 20), ((80, 30), 30)])
+def test_truncated_stewart_qlp_matches_lapack(shape, kt):
+    """The first CPQR stopped after kt steps takes LAPACK dgeqp3's first kt
+    pivots and rows of R (the steps of a pivoted QR do not depend on how many
+    follow); the L-values are those of dgeqp3 applied to that kt x n R^T; and
+    Q L P^T = Qhat_kt R Pi0^T, the projection of A on the first kt columns of
+    Qhat."""
+    m, n = shape
+    A = _mat(m, n, inputs.spectrum_exp(n, n / 6.0), seed=m + kt)
+    Q, L, P, p0, p1 = stewart_qlp(A, kt=kt)
+    Qh, R0, P0 = sla.qr(A, pivoting=True)
+    assert np.array_equal(p0[:kt], P0[:kt])
+    sg = np.sign(np.diag(R0))[:kt]
+    R1 = (R0[:kt] * sg[:, None])
+    Rorig = np.empty_like(R1)
+    Rorig[:, P0] = R1                                     # R1 in the original column order
+    _, R2, P2 = sla.qr(Rorig.T, pivoting=True)
+    assert np.array_equal(p1, P2)
+    assert np.allclose(np.abs(np.diag(L)), np.abs(np.diag(R2)), rtol=1e-12, atol=1e-15)
+    assert np.allclose(np.triu(L, 1), 0.0)
+    Qk = Qh[:, :kt] * sg[None, :]
+    assert np.allclose(Q @ L @ P.T, Qk @ Rorig, atol=1e-12)
+    assert np.allclose(Q.T @ Q, np.eye(kt), atol=1e-12) and np.allclose(P.T @ P, np.eye(kt), atol=1e-12)
+    if kt == min(m, n):
+        assert np.allclose(Q @ L @ P.T, A, atol=1e-12)
