@@ -208,6 +208,33 @@ int rqlp_factor_autorank(const void* A, int64_t lda, int64_t m, int64_t n, int64
                          int64_t* piv0, int64_t* piv1, double* lvals, int32_t* info,
                          int64_t* rank, double* err2, void* work, size_t work_bytes, void* stream);
 
+/* Deterministic truncated pivoted QLP (Stewart's QLP, eq. (1.2) of
+ * Section 1; the "QLP" comparison method of Section 5), FP64: kt steps of the
+ * column-pivoted Householder QR of A itself, A Pi0 ~= Qhat R with R its first
+ * kt rows, then the pivoted QR of R^T (the second factorisation of
+ * Algorithm 2.1 step 6): A ~= Q T P^T with Q (m x kt) and P (n x kt)
+ * orthonormal, T (kt x kt) lower triangular, diag(T) the L-values.  With
+ * kt = min(m, n) this is Stewart's full pivoted QLP (exact reconstruction).
+ *
+ *   A      m x n double (lda >= m), read only; m <= 6144 in this build
+ *          (RQLP_E_UNSUPPORTED beyond).
+ *   kt     number of pivot steps, 1 <= kt <= min(m, n).
+ *   Q, T, P  outputs (ldq >= m, ldt >= kt, ldp >= n).
+ *   piv0   kt int64 (may be NULL): pivots of the QR of A (original columns).
+ *   piv1   kt int64 (may be NULL): pivots of the QR of R^T.
+ *   lvals  kt doubles (may be NULL): diag(T).
+ *   info   device int32 (may be NULL): RQLP_INFO_* flags (rank stop of
+ *          either pivoted QR: RQLP_INFO_RANK_DEFICIENT, trailing L-values 0).
+ *   work   device workspace of rqlp_qlp_workspace_size() bytes (holds an
+ *          m x n working copy of A).
+ * Pivot rule, ties and rank stop as for rqlp_cpqr.  The QR of A streams the
+ * working copy through the device once per pivot step (one launch each). */
+int rqlp_qlp_workspace_size(int64_t m, int64_t n, int64_t kt, size_t* bytes);
+int rqlp_qlp(const double* A, int64_t lda, int64_t m, int64_t n, int64_t kt,
+             double* Q, int64_t ldq, double* T, int64_t ldt, double* P, int64_t ldp,
+             int64_t* piv0, int64_t* piv1, double* lvals, int32_t* info,
+             void* work, size_t work_bytes, void* stream);
+
 /* ---- building blocks (the steps of Algorithm 2.1, usable on their own) ---- */
 
 /* Adjoint of rqlp_factor with frozen pivots: dA = d<dT, T>/dA, the gradient

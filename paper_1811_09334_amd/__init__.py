@@ -170,6 +170,33 @@ def factor_autorank(A, lmax: int, b: int, eps: float, q: int = 0, precision="f64
     return f, rank.value, err2.value
 
 
+def pivoted_qlp(A, kt: int, work=None) -> Factorization:
+    """Deterministic truncated pivoted QLP (kt steps) of the FP64 device
+    matrix ``A`` through ``rqlp_qlp``."""
+    torch = _torch()
+    load()
+    if A.dtype != torch.float64:
+        raise TypeError("A must be float64")
+    A = colmajor(A)
+    m, n = A.shape
+    dev = A.device
+    Q = empty_colmajor(m, kt, torch.float64, dev)
+    T = empty_colmajor(kt, kt, torch.float64, dev)
+    P = empty_colmajor(n, kt, torch.float64, dev)
+    piv0 = torch.empty(kt, dtype=torch.int64, device=dev)
+    piv1 = torch.empty(kt, dtype=torch.int64, device=dev)
+    lv = torch.empty(kt, dtype=torch.float64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    nbytes = _lib.rqlp_qlp_workspace_size(m, n, kt)
+    if work is None or work.numel() < nbytes:
+        work = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    st = _lib.rqlp_qlp(A.data_ptr(), ld(A), m, n, kt, Q.data_ptr(), ld(Q), T.data_ptr(), ld(T), P.data_ptr(), ld(P),
+                       piv0.data_ptr(), piv1.data_ptr(), lv.data_ptr(), info.data_ptr(), work.data_ptr(),
+                       work.numel(), _stream(dev))
+    check("rqlp_qlp", st)
+    return Factorization(Q=Q, T=T, P=P, piv0=piv0, piv1=piv1, lvals=lv, info=info, uplo="L")
+
+
 def backward(A, k: int, p: int, piv0, piv1, dT, q: int = 0, d: int = 0, b: int = 0, precision=None, seed: int = 0,
              Omega=None, work=None):
     """dA = d<dT, T>/dA with the pivots frozen, through ``rqlp_backward``.

@@ -34,6 +34,9 @@ SIGNATURES = {
                                      c_uint64, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
                                      c_int64, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_int64),
                                      POINTER(c_double), c_void_p, c_size_t, c_void_p]),
+    "rqlp_qlp_workspace_size": (c_int, [c_int64, c_int64, c_int64, POINTER(c_size_t)]),
+    "rqlp_qlp": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64,
+                         c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "rqlp_backward": (c_int, [c_void_p, c_int64, c_int64, c_int64, c_int64, c_int64, c_int, c_int, c_int, c_int,
                               c_uint64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_int64,
                               c_void_p, c_int64, c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_size_t,
@@ -136,6 +139,17 @@ def rqlp_factor_autorank(A, lda, m, n, lmax, b, q, eps, precision, seed, Omega, 
                          piv1, lvals, info, rank, err2, work, work_bytes, stream) -> int:
     return _call("rqlp_factor_autorank", A, lda, m, n, lmax, b, q, eps, precision, seed, Omega, ldo, Q, ldq, T, ldt,
                  P, ldp, piv0, piv1, lvals, info, rank, err2, work, work_bytes, stream)
+
+
+def rqlp_qlp_workspace_size(m, n, kt) -> int:
+    out = c_size_t(0)
+    check("rqlp_qlp_workspace_size", _call("rqlp_qlp_workspace_size", m, n, kt, ctypes.byref(out)))
+    return out.value
+
+
+def rqlp_qlp(A, lda, m, n, kt, Q, ldq, T, ldt, P, ldp, piv0, piv1, lvals, info, work, work_bytes, stream) -> int:
+    return _call("rqlp_qlp", A, lda, m, n, kt, Q, ldq, T, ldt, P, ldp, piv0, piv1, lvals, info, work, work_bytes,
+                 stream)
 
 
 def rqlp_backward(A, lda, m, n, k, p, q, d, b, precision, seed, Omega, ldo, piv0, piv1, dT, lddt, dQ, lddq, dP,

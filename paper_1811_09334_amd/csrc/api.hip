@@ -865,6 +865,98 @@ int check_autorank_args(const void* A, int64_t lda, int64_t m, int64_t n, int64_
 }
 }  // namespace
 
+// ---- deterministic truncated pivoted QLP (eq. (1.2)) ----
+namespace {
+struct QlpLayout {
+    double* M;
+    double* Vh;
+    double* beta;
+    double* mu;
+    int* colstep;
+    unsigned long long* slots;
+    unsigned* counter;
+    int* state;
+    double* dstate;
+    SmallBufs sm;
+};
+void carve_qlp(Arena& ar, int64_t m, int64_t n, int64_t kt, QlpLayout* L) {
+    L->M = ar.take<double>(m * n);
+    L->Vh = ar.take<double>(m * kt);
+    L->beta = ar.take<double>(kt);
+    L->mu = ar.take<double>(kt);
+    L->colstep = ar.take<int>(n);
+    L->slots = ar.take<unsigned long long>(4 * (size_t)qlp_grid(n));
+    L->counter = ar.take<unsigned>(32);
+    L->state = ar.take<int>(2);
+    L->dstate = ar.take<double>(1);
+    carve_small(ar, n, kt, kt, {}, &L->sm);
+}
+int check_qlp_args(const double* A, int64_t lda, int64_t m, int64_t n, int64_t kt) {
+    if (m < 1) return -3;
+    if (n < 1) return -4;
+    if (lda < m) return -2;
+    if (kt < 1 || kt > (m < n ? m : n)) return -5;
+    if (m > qlp_max_rows()) return RQLP_E_UNSUPPORTED;
+    if (A == nullptr) return -1;
+    return 0;
+}
+}  // namespace
+
+int rqlp_qlp_workspace_size(int64_t m, int64_t n, int64_t kt, size_t* bytes) {
+    RQLP_TRY(check_qlp_args((const double*)8, m, m, n, kt));
+    if (!bytes) return -4;
+    Arena ar(nullptr, 0);
+    QlpLayout L;
+    carve_qlp(ar, m, n, kt, &L);
+    *bytes = ar.used + 256;
+    return 0;
+}
+
+int rqlp_qlp(const double* A, int64_t lda, int64_t m, int64_t n, int64_t kt, double* Q, int64_t ldq, double* T,
+             int64_t ldt, double* P, int64_t ldp, int64_t* piv0, int64_t* piv1, double* lvals, int32_t* info,
+             void* work, size_t work_bytes, void* stream) {
+    RQLP_TRY(check_qlp_args(A, lda, m, n, kt));
+    if (!Q) return -6;
+    if (ldq < m) return -7;
+    if (!T) return -8;
+    if (ldt < kt) return -9;
+    if (!P) return -10;
+    if (ldp < n) return -11;
+    if (!work) return -16;
+    hipStream_t s = (hipStream_t)stream;
+    Arena ar = arena_for(work, work_bytes);
+    QlpLayout L;
+    carve_qlp(ar, m, n, kt, &L);
+    if (!ar.ok()) return RQLP_E_WORKSPACE;
+    SmallBufs& f = L.sm;
+    {
+        CpqrPlan pl;
+        RQLP_TRY(cpqr_plan(kt, kt, &pl));
+    }
+    int32_t* inf = info ? info : f.info;
+    RQLP_TRY(fill_zero_bytes(inf, sizeof(int32_t), s));
+    // first CPQR: kt steps on a working copy of A
+    RQLP_TRY(copy_matrix(m, n, A, lda, L.M, m, s));
+    RQLP_TRY(qlp_first_cpqr(L.M, m, m, n, kt, L.Vh, m, L.beta, L.mu, f.piv0, L.colstep, L.slots, L.counter, L.state,
+                            L.dstate, inf, s));
+    RQLP_TRY(qlp_extract_rt(L.M, m, n, kt, L.colstep, L.mu, L.state, f.Z, n, s));
+    // second stage: R^T = Qt Rtil (CholeskyQR2), Rtil Pi1 = Qhat L^T, P = Qt Qhat
+    Ctx cx{s, inf, f.gws, f.gws_elems, f.o, f.o.shifted};
+    double* Qt = nullptr;
+    RQLP_TRY(cholqr2(cx, n, kt, f.Z, f.Z2, n, f.RtT, &Qt));
+    RQLP_TRY(transpose_matrix(kt, kt, f.RtT, kt, f.Rtil, kt, 0, s));
+    RQLP_TRY(cpqr(f.Rtil, kt, kt, kt, f.cs, f.piv1, f.Vh1, kt, f.beta1, f.Lt, kt, nullptr, 1, inf, s));
+    RQLP_TRY(apply_householder(kt, kt, f.Vh1, kt, f.beta1, nullptr, 0, nullptr, kt, f.Mr, kt, s));
+    RQLP_TRY(gemm<double>(false, false, n, kt, kt, Qt, n, f.Mr, kt, P, ldp, false, 1.0, 0.0, f.gws, f.gws_elems, s));
+    RQLP_TRY(transpose_matrix(kt, kt, f.Lt, kt, T, ldt, 'L', s));
+    // Q = Qhat(:, 1:kt) Pi1: the first CPQR's reflectors applied to e_{piv1(c)}
+    RQLP_TRY(householder_tall(m, kt, L.Vh, m, L.beta, f.piv1, kt, Q, ldq, s));
+    if (piv0) RQLP_TRY(copy_i64(kt, f.piv0, piv0, s));
+    if (piv1) RQLP_TRY(copy_i64(kt, f.piv1, piv1, s));
+    RQLP_TRY(finish_lvals(kt, T, ldt, lvals, inf, s));
+    return 0;
+}
+
 int rqlp_autorank_workspace_size(int64_t m, int64_t n, int64_t lmax, int64_t b, int q, int precision,
                                  size_t* bytes) {
     RQLP_TRY(check_autorank_args((const void*)1, m, m, n, lmax, b, q, 0.0, precision));

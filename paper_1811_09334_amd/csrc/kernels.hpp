@@ -189,6 +189,24 @@ int fill_i64(int64_t n, int64_t* p, int64_t v, hipStream_t s);
 // *info |= bit (device word, one thread)
 int set_info_flag(int32_t* info, int32_t bit, hipStream_t s);
 
+// --- qlp.hip: deterministic truncated pivoted QLP (eq. (1.2)) -------------
+int qlp_max_rows();
+int qlp_grid(int64_t n);
+// kt steps of the column-pivoted QR of M (m x n, in place, a working copy):
+// pivots, reflectors Vh (m x kt, v(j) = 1, zero above), beta, mu (the diagonal
+// of R); colstep (n ints): the step a column was taken at, -1 if never;
+// slots: 4 * qlp_grid(n) words; counter: 1 word; state: 2 ints (stopped,
+// rank); dstate: 1 double.
+int qlp_first_cpqr(double* M, int64_t ldm, int64_t m, int64_t n, int64_t kt, double* Vh, int64_t ldv, double* beta,
+                   double* mu, int64_t* piv, int* colstep, unsigned long long* slots, unsigned* counter, int* state,
+                   double* dstate, int32_t* info, hipStream_t s);
+// Z (n x kt) = R^T of that CPQR in original column order (rows of R past the rank zero)
+int qlp_extract_rt(const double* M, int64_t ldm, int64_t n, int64_t kt, const int* colstep, const double* mu,
+                   const int* state, double* Z, int64_t ldz, hipStream_t s);
+// Y(:, c) = H_0 ... H_{k-1} e_{unit[c]} for tall reflectors (rows up to the LDS size / 8)
+int householder_tall(int64_t rows, int64_t k, const double* Vh, int64_t ldv, const double* beta, const int64_t* unit,
+                     int64_t ncols, double* Y, int64_t ldy, hipStream_t s);
+
 // --- misc.hip ---------------------------------------------------------------
 // Columns of X (rows x c) whose squared norm is <= tau2 are replaced by
 // N(0, 1/rows) vectors (Philox4x32-10 counter (i, col0 + j, 1, 0), fixed

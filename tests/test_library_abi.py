@@ -186,3 +186,15 @@ def test_autorank_workspace_query(lib):
     assert _lib.rqlp_autorank_workspace_size(1000, 500, 64, 16, 1, 0) > 0
     with pytest.raises(_lib.RQLPError):
         _lib.rqlp_autorank_workspace_size(1000, 500, 501, 16, 1, 0)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(A=None), -1), (dict(lda=99), -2), (dict(m=0), -3), (dict(n=0), -4), (dict(kt=0), -5), (dict(kt=51), -5),
+    (dict(Q=None), -6), (dict(ldq=99), -7), (dict(T=None), -8), (dict(ldt=19), -9), (dict(P=None), -10),
+    (dict(ldp=49), -11), (dict(work=None), -16), (dict(m=7000, lda=7000, ldq=7000), -1002),
+])
+def test_qlp_argument_errors(lib, kw, code):
+    a = dict(A=1, lda=100, m=100, n=50, kt=20, Q=1, ldq=100, T=1, ldt=20, P=1, ldp=50, piv0=None, piv1=None,
+             lvals=None, info=None, work=1, work_bytes=0, stream=None)
+    a.update(kw)
+    assert _lib.rqlp_qlp(*a.values()) == code
