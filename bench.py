@@ -196,6 +196,74 @@ def other_workloads(rq, inputs, dev):
     return out
 
 
+def paper_tables(rq, inputs, dev):
+    """The Section 5 replica workloads (Example 5.1: pds, eds at m = n = 2000,
+    4000, 6000, k = 120, p = 5, FP64): GPU time of RQLP and ERQLP (d = 2, 4)
+    and of the deterministic truncated pivoted QLP (kt = l = 125, rqlp_qlp),
+    and err = max_{j <= k} |sigma_j - |L_jj|| against the prescribed spectrum,
+    next to the paper's MATLAB times on an i5-7500 (Tables 1-2; its QLP column
+    is the full, not truncated, deterministic QLP).  Context only: the paper's
+    random orthogonal factors are not specified, so errors compare in order,
+    not in value."""
+    import torch
+    paper = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "paper_tables_1_2.txt")):
+        t = line.split()
+        if t and not line.startswith("#"):
+            paper[(t[0], int(t[1]))] = dict(zip(["qlp_t", "qlp", "rqlp_t", "rqlp", "e2_t", "e2", "e4_t", "e4"],
+                                                map(float, t[2:])))
+    rows = []
+    for ex in ("pds", "eds"):
+        for n in inputs.PAPER_EXAMPLE_SIZES:
+            w = inputs.paper_example(ex, n)
+            A = inputs.make_matrix_torch(w, dev)
+            sig = w.spectrum_values()
+            rec = {"example": ex, "n": n}
+            for d, key in ((0, "rqlp"), (2, "erqlp2"), (4, "erqlp4")):
+                work = torch.empty(rq.workspace_size(n, n, w.k, w.p, 0, d, 0, "f64"), dtype=torch.uint8, device=dev)
+                ms, f = timed(lambda: rq.factor(A, w.k, w.p, q=0, d=d, seed=w.seed_omega, work=work), 5, 2)
+                lv = f.lvals.cpu().numpy()
+                rec[key + "_ms"] = round(ms, 3)
+                rec[key + "_err"] = float(np.max(np.abs(sig[: w.k] - np.abs(lv[: w.k]))))
+            qwork = torch.empty(rq._lib.rqlp_qlp_workspace_size(n, n, w.l), dtype=torch.uint8, device=dev)
+            ms, f = timed(lambda: rq.pivoted_qlp(A, w.l, work=qwork), 2, 1)
+            lv = f.lvals.cpu().numpy()
+            rec["qlp_truncated_ms"] = round(ms, 3)
+            rec["qlp_truncated_err"] = float(np.max(np.abs(sig[: w.k] - np.abs(lv[: w.k]))))
+            pp = paper.get((ex, n), {})
+            rec["paper_i5_7500_s"] = {"qlp": pp.get("qlp_t"), "rqlp": pp.get("rqlp_t"), "erqlp2": pp.get("e2_t"),
+                                      "erqlp4": pp.get("e4_t")}
+            rec["paper_err"] = {"qlp": pp.get("qlp"), "rqlp": pp.get("rqlp"), "erqlp2": pp.get("e2"),
+                                "erqlp4": pp.get("e4")}
+            rows.append(rec)
+            print(f"# {ex} n={n}: RQLP {rec['rqlp_ms']:.2f} ms (err {rec['rqlp_err']:.2e}), ERQLP(4) "
+                  f"{rec['erqlp4_ms']:.2f} ms (err {rec['erqlp4_err']:.2e}), QLP(kt=125) {rec['qlp_truncated_ms']:.2f}"
+                  f" ms (err {rec['qlp_truncated_err']:.2e}); paper RQLP {pp.get('rqlp_t')} s", file=sys.stderr,
+                  flush=True)
+            del A, work, qwork, f
+            torch.cuda.empty_cache()
+    return rows
+
+
+def autorank_leg(rq, inputs, dev):
+    """Auto-rank RQLP (Section 6) on the FP64 ERQLP workload's matrix
+    (20000 x 10000): lmax = 256, b = 64, q = 1, eps = 1e-4 ||A||_F^2."""
+    import torch
+    w = inputs.WORKLOADS["erqlp_f64_20000x10000"]
+    A = inputs.make_matrix_torch(w, dev)
+    eps = 1e-4 * float((A * A).sum().item())
+    lmax, b = 256, 64
+    work = torch.empty(rq._lib.rqlp_autorank_workspace_size(w.m, w.n, lmax, b, 1, 0), dtype=torch.uint8, device=dev)
+    ms, out = timed(lambda: rq.factor_autorank(A, lmax, b, eps, q=1, seed=w.seed_omega, work=work), 3, 1)
+    f, rank, err2 = out
+    print(f"# autorank 20000x10000: rank {rank}, ||E||^2 / ||A||^2 {err2 * 1e-4 / eps:.2e}, {ms:.3f} ms",
+          file=sys.stderr, flush=True)
+    del A, work, f
+    torch.cuda.empty_cache()
+    return {"m": w.m, "n": w.n, "lmax": lmax, "b": b, "q": 1, "eps_rel": 1e-4, "rank": rank,
+            "err2_rel": err2 * 1e-4 / eps, "ms_per_call": round(ms, 3)}
+
+
 def main():
     args = parse_args()
     if args.gpus != 1:
@@ -238,6 +306,18 @@ def main():
     F = flop_model(w.m, w.n, l, w.q)
     tflops = F / (ms * 1e-3) / 1e12
     print(f"# {w.precision}: {ms:.3f} ms/step, {tflops:.2f} TFLOP/s, info={info:#x}", file=sys.stderr, flush=True)
+    backward = None
+    if w.name.startswith("drqlp"):
+        # the differentiable workload: the adjoint of the same call, loss sum_j w_j L_jj
+        dT = torch.zeros(l, l, dtype=torch.float64, device=dev)
+        dT.diagonal()[: w.k] = torch.as_tensor(inputs.uniform_weights(w.k, 3000), device=dev)
+        bw = torch.empty(rq._lib.rqlp_backward_workspace_size(w.m, w.n, w.k, w.p, w.q, w.d, w.b,
+                                                              rq.PRECISIONS[w.precision]), dtype=torch.uint8,
+                         device=dev)
+        msb, _ = timed(lambda: rq.backward(A, w.k, w.p, f.piv0, f.piv1, dT, q=w.q, precision=w.precision,
+                                           seed=seed, work=bw), args.steps, args.warmup)
+        backward = {"ms_per_step": round(msb, 4)}
+        print(f"# backward: {msb:.3f} ms/step", file=sys.stderr, flush=True)
 
     # ---- the same call in FP64 on the same matrix (the "mixed vs FP64" ratio) ----
     fp64 = None
@@ -282,10 +362,14 @@ def main():
         del V
 
     others = None
+    tables = None
+    autorank = None
     if not args.no_others and args.workload == DEFAULT_WORKLOAD:
         del work
         torch.cuda.empty_cache()
         others = other_workloads(rq, inputs, dev)
+        tables = paper_tables(rq, inputs, dev)
+        autorank = autorank_leg(rq, inputs, dev)
 
     # ---- CPU baseline: the FP64 oracle on the host cores, same A and Omega ----
     cpu = None
@@ -366,8 +450,11 @@ def main():
         "fp64_same_matrix": fp64,
         "speedup_vs_fp64": round(fp64["ms_per_step"] / ms, 3) if fp64 else None,
         "bf16x3_same_matrix": x3,
+        "backward": backward,
         **acc,
         "other_workloads": others,
+        "paper_tables_1_2": tables,
+        "autorank": autorank,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
