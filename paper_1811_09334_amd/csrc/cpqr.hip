@@ -831,6 +831,221 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// Small matrices (rows <= 16 RPT, cols <= 32 CT) held whole in the registers of
+// one workgroup of 512 threads: 16 lanes per column (one DPP row), lane group
+// s (32 of them) holds the columns s + 32 t (t < CT), its lane qd the rows
+// qd RPT .. qd RPT + RPT - 1.  No grid agreement: every thread combines the
+// 8 waves' best keys itself and takes the same decision; three workgroup
+// barriers per pivot step (keys, the winning column in LDS, the reflector).
+// Pivot rule, reflector, rank stop and outputs as in cpqr_kernel.
+constexpr int CPW_T = 512;
+template <int RPT, int CT>
+__global__ __launch_bounds__(CPW_T) void cpqr_wg_kernel(const double* __restrict__ M, int64_t ldm, int rows, int cols,
+                                                        int kmax, int ibits, int64_t* piv, double* Vh, int64_t ldv,
+                                                        double* beta_out, double* Rpiv, int64_t ldr, double* Rt,
+                                                        int64_t ldrt, int32_t* info) {
+    __shared__ double vcol[16 * RPT];
+    __shared__ unsigned long long s_k[2][CPW_T / 64];
+    __shared__ double s_part[CPW_T / 64];
+    __shared__ double s_beta, s_mu, s_rv0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int qd = lane & 15;
+    const int slot = wave * 4 + (lane >> 4);
+    const int r0 = qd * RPT;
+    int col[CT], act[CT];
+    double x[CT][RPT], nrm2[CT];
+    auto colsum = [](double v) {
+        v += dpp_f64<0xB1>(v);
+        v += dpp_f64<0x4E>(v);
+        v += dpp_f64<0x141>(v);
+        v += dpp_f64<0x140>(v);
+        return v;
+    };
+    double fro = 0.0;
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+        col[t] = slot + 32 * t;
+        const bool have = col[t] < cols;
+        act[t] = have ? -1 : -2;
+        double sq = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            x[t][r] = (have && r0 + r < rows) ? M[r0 + r + (int64_t)col[t] * ldm] : 0.0;
+            sq += x[t][r] * x[t][r];
+        }
+        nrm2[t] = colsum(sq);
+        fro += (qd == 0 && have) ? nrm2[t] : 0.0;
+    }
+    fro = wave_sum(fro);
+    if (lane == 0) s_part[wave] = fro;
+    __syncthreads();
+    double tol2;
+    {
+        double f = 0.0;
+        for (int w = 0; w < CPW_T / 64; ++w) f += s_part[w];
+        const double tol = (double)(rows > cols ? rows : cols) * 2.220446049250313e-16;
+        tol2 = tol * tol * f;
+    }
+    int stopped = 0, rank = kmax;
+    for (int j = 0; j < kmax; ++j) {
+        // ---- best keys: by norm (k0) and by smallest index (k1) ----
+        unsigned long long k0 = 0, k1 = 0;
+#pragma unroll
+        for (int t = 0; t < CT; ++t) {
+            if (act[t] == -1) {
+                const unsigned long long a = pivot_key(stopped ? 0.0 : nrm2[t], (unsigned)col[t], ibits);
+                const unsigned long long b = pivot_key(0.0, (unsigned)col[t], ibits);
+                k0 = a > k0 ? a : k0;
+                k1 = b > k1 ? b : k1;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long a = shfl_xor_u64(k0, off), b = shfl_xor_u64(k1, off);
+            k0 = a > k0 ? a : k0;
+            k1 = b > k1 ? b : k1;
+        }
+        if (lane == 0) {
+            s_k[0][wave] = k0;
+            s_k[1][wave] = k1;
+        }
+        __syncthreads();
+        k0 = 0;
+        k1 = 0;
+#pragma unroll
+        for (int w = 0; w < CPW_T / 64; ++w) {
+            k0 = s_k[0][w] > k0 ? s_k[0][w] : k0;
+            k1 = s_k[1][w] > k1 ? s_k[1][w] : k1;
+        }
+        int stopnow = 0;
+        if (!stopped) {
+            const double kv = key_value(k0, ibits);
+            if (!(kv > tol2) && kv == kv) stopnow = 1;    // NaN norms never stop
+        }
+        const int win = (int)((stopped || stopnow) ? key_index(k1, ibits) : key_index(k0, ibits));
+        const int now_stopped = stopped | stopnow;
+        if (stopnow) {
+            stopped = 1;
+            rank = j;
+        }
+        if (!now_stopped) {
+            // ---- the winning column in LDS, then its reflector (wave 0) ----
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+                if (col[t] == win) {
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) vcol[r0 + r] = (r0 + r >= j) ? x[t][r] : 0.0;
+                }
+            }
+            __syncthreads();
+            if (wave == 0) {
+                double sg = 0.0;
+                for (int i = j + 1 + lane; i < 16 * RPT; i += 64) sg += vcol[i] * vcol[i];
+                sg = wave_sum(sg);
+                if (lane == 0) {
+                    const double x0 = vcol[j];
+                    const double mu = sqrt(x0 * x0 + sg);
+                    double v0, bb;
+                    if (sg == 0.0) {
+                        v0 = 1.0;
+                        bb = (x0 >= 0.0) ? 0.0 : 2.0;
+                    } else {
+                        v0 = (x0 <= 0.0) ? (x0 - mu) : (-sg / (x0 + mu));
+                        bb = 2.0 * v0 * v0 / (sg + v0 * v0);
+                    }
+                    s_beta = bb;
+                    s_mu = mu;
+                    s_rv0 = (sg == 0.0) ? 0.0 : 1.0 / v0;
+                }
+            }
+            __syncthreads();
+            const double b = s_beta, rv0 = s_rv0;
+            double vr[RPT];
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int i = r0 + r;
+                vr[r] = (i > j) ? vcol[i] * rv0 : (i == j ? 1.0 : 0.0);
+            }
+            if (tid == 0) {
+                if (piv) piv[j] = win;
+                if (beta_out) beta_out[j] = b;
+            }
+            if (Vh && tid < rows) Vh[tid + (int64_t)j * ldv] = (tid > j) ? vcol[tid] * rv0 : (tid == j ? 1.0 : 0.0);
+            const double mu = s_mu;
+            double dot[CT];
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+                double sdot = 0.0;
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) sdot += vr[r] * x[t][r];
+                dot[t] = sdot;
+            }
+#pragma unroll
+            for (int t = 0; t < CT; ++t) dot[t] = colsum(dot[t]);
+            double sn[CT];
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+                const bool owner = col[t] == win;
+                const double w = (act[t] == -1 && !owner) ? b * dot[t] : 0.0;
+                double ss = 0.0;
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    const int i = r0 + r;
+                    if (owner) {
+                        if (i >= j) x[t][r] = (i == j) ? mu : 0.0;
+                    } else {
+                        x[t][r] -= w * vr[r];
+                    }
+                    ss += (i > j) ? x[t][r] * x[t][r] : 0.0;
+                }
+                sn[t] = ss;
+                if (owner) act[t] = j;
+            }
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+                const double v = colsum(sn[t]);
+                if (act[t] == -1) nrm2[t] = v;
+            }
+        } else {
+            if (tid == 0) {
+                if (piv) piv[j] = win;
+                if (beta_out) beta_out[j] = 0.0;
+            }
+            if (Vh && tid < rows) Vh[tid + (int64_t)j * ldv] = (tid == j) ? 1.0 : 0.0;
+#pragma unroll
+            for (int t = 0; t < CT; ++t)
+                if (col[t] == win) act[t] = j;
+        }
+    }
+    if (rank < kmax && tid == 0 && info) atomicOr(info, RQLP_INFO_RANK_DEFICIENT);
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+        if (act[t] == -2) continue;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int i = r0 + r;
+            if (i >= rows) continue;
+            if (Rt) Rt[col[t] + (int64_t)i * ldrt] = (i >= rank) ? 0.0 : x[t][r];
+            if (Rpiv && act[t] >= 0) Rpiv[i + (int64_t)act[t] * ldr] = (i >= rank || i > act[t]) ? 0.0 : x[t][r];
+        }
+    }
+}
+
+// rows per lane (16 lanes per column) and column groups of the one-workgroup
+// register kernel, 0 when the matrix does not fit
+static int cpqr_wg_rpt(int64_t rows) {
+    static const int opts[] = {2, 4, 6, 9, 12};
+    for (int o : opts)
+        if (16 * (int64_t)o >= rows) return o;
+    return 0;
+}
+static int cpqr_wg_ct(int64_t cols) {
+    static const int opts[] = {2, 4, 6};               // (one group spills: the compiler keeps more live)
+    for (int o : opts)
+        if (32 * (int64_t)o >= cols) return o;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
 static int index_bits(int64_t cols) {
     int b = 1;
     while ((1ll << b) <= cols) ++b;
@@ -875,6 +1090,18 @@ int cpqr_plan(int64_t rows, int64_t cols, CpqrPlan* plan) {
     const size_t budget = di.max_lds > 0 ? di.max_lds : 65536;
     const int cus = di.num_cus > 0 ? di.num_cus : 1;
     plan->rpt = 0;
+    plan->wg_rpt = 0;
+    plan->wg_ct = 0;
+    // one workgroup, everything in registers
+    if (cpqr_wg_rpt(rows) > 0 && cpqr_wg_ct(cols) > 0) {
+        plan->G = 1;
+        plan->cpw = (int)cols;
+        plan->lds = 0;
+        plan->single = true;
+        plan->wg_rpt = cpqr_wg_rpt(rows);
+        plan->wg_ct = cpqr_wg_ct(cols);
+        return 0;
+    }
     // single workgroup when everything fits
     if (cpqr_lds(rows, (int)cols) <= budget && cols <= 512) {
         plan->G = 1;
@@ -943,6 +1170,27 @@ int cpqr(const double* M, int64_t ldm, int64_t rows, int64_t cols, const CpqrScr
         const int mx = (int)(device_info().max_lds > 0 ? device_info().max_lds : 65536);
         RQLP_TRY(raise_lds_limit((const void*)cpqr_kernel<true>, mx));
         RQLP_TRY(raise_lds_limit((const void*)cpqr_kernel<false>, mx));
+    }
+    if (plan.wg_rpt > 0) {
+#define RQLP_CPW(R, C)                                                                                          \
+    hipLaunchKernelGGL((cpqr_wg_kernel<R, C>), dim3(1), dim3(CPW_T), 0, s, M, ldm, rows_i, cols_i, kmax_i, ibits, piv, \
+                       Vh, ldv, beta, Rpiv, ldr, Rt, ldrt, info)
+#define RQLP_CPW_C(R)                        \
+    switch (plan.wg_ct) {                    \
+        case 2: RQLP_CPW(R, 2); break;       \
+        case 4: RQLP_CPW(R, 4); break;       \
+        default: RQLP_CPW(R, 6); break;      \
+    }
+        switch (plan.wg_rpt) {
+            case 2: RQLP_CPW_C(2); break;
+            case 4: RQLP_CPW_C(4); break;
+            case 6: RQLP_CPW_C(6); break;
+            case 9: RQLP_CPW_C(9); break;
+            default: RQLP_CPW_C(12); break;
+        }
+#undef RQLP_CPW_C
+#undef RQLP_CPW
+        return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
     }
     if (plan.single) {
         hipLaunchKernelGGL(cpqr_kernel<true>, dim3(1), dim3(CP_T), plan.lds, s, M, ldm, rows_i, cols_i, cpw,

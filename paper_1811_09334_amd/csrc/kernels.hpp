@@ -122,6 +122,8 @@ struct CpqrPlan {
     size_t lds;     // dynamic LDS bytes
     bool single;    // one workgroup: no grid-wide exchange
     int rpt;        // > 0: columns held in registers, rpt rows per lane (16 lanes per column)
+    int wg_rpt;     // > 0: one workgroup of 512 threads holds the whole matrix in registers
+    int wg_ct;      //      (wg_rpt rows per lane, wg_ct column groups of 32)
 };
 int cpqr_plan(int64_t rows, int64_t cols, CpqrPlan* plan);
 size_t cpqr_scratch_bytes(int64_t rows, int64_t cols);

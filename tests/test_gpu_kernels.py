@@ -80,7 +80,11 @@ def test_cholqr2_orthonormalizes(gpu, m, c, cond):
                                             # the reduced-matrix shapes of the benchmark workloads: 157, 256
                                             # and 128 workgroups of 64 columns (pivot agreement over more
                                             # than 64 key slots, i.e. several slots per polling lane)
-                                            (210, 10000, 8), (272, 16384, 9), (64, 8192, 10), (17, 4097, 12)])
+                                            (210, 10000, 8), (272, 16384, 9), (64, 8192, 10), (17, 4097, 12),
+                                            # one workgroup holding the whole matrix in registers (rows <= 192,
+                                            # cols <= 192): the l x l second factorisation
+                                            (125, 125, 13), (192, 192, 14), (150, 40, 15), (20, 180, 16),
+                                            (100, 190, 17)])
 def test_cpqr_matches_oracle(gpu, rows, cols, seed):
     rng = np.random.default_rng(seed)
     M = rng.standard_normal((rows, cols)) * np.exp(rng.uniform(-6, 0, cols))[None, :]
@@ -103,9 +107,10 @@ def test_cpqr_matches_oracle(gpu, rows, cols, seed):
     assert int(to_np(info)[0]) == 0
 
 
-def test_cpqr_rank_deficient_stop(gpu):
+@pytest.mark.parametrize("rows,cols", [(40, 300), (40, 150), (60, 60)])
+def test_cpqr_rank_deficient_stop(gpu, rows, cols):
     rng = np.random.default_rng(11)
-    M = rng.standard_normal((40, 6)) @ rng.standard_normal((6, 300))
+    M = rng.standard_normal((rows, 6)) @ rng.standard_normal((6, cols))
     piv, R, Rt, Q, info = gpu.cpqr(to_dev(M))
     piv, R = to_np(piv), to_np(R)
     ref = oracle_cpqr(M)
@@ -114,7 +119,8 @@ def test_cpqr_rank_deficient_stop(gpu):
     assert np.array_equal(piv[:6], ref.perm[:6])
     assert np.allclose(R[6:, :], 0.0)
     # after the stop the remaining pivots are the smallest unused indices
-    assert np.array_equal(piv[6:], ref.perm[6:40])
+    kmax = min(rows, cols)
+    assert np.array_equal(piv[6:], ref.perm[6:kmax])
 
 
 def test_cholqr2_shifted_retry_on_singular_gram(gpu):
