@@ -13,7 +13,8 @@
 //      block's result word, which the others poll.  Every workgroup forms the
 //      Householder reflector of the winner itself (bitwise identical) and
 //      applies it to its active columns, whose residual norms are then
-//      recomputed exactly.  Output: R0_j^T in original column order, the
+//      recomputed exactly (the step's barriers are LDS-only except the drain
+//      before a key slot is published).  Output: R0_j^T in original column order, the
 //      reflectors and the numerical rank of every block.  Columns of R0_j^T
 //      past the rank (exactly zero rows of R0_j) are replaced by Gaussian
 //      vectors, so the next step sees a full-rank panel; their rows of the
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(BQ_T, 3) void bcpqr_kernel(
             s_kred[0][wave] = k0;
             s_kred[1][wave] = k1;
         }
-        __syncthreads();
+        RQLP_LDS_BARRIER();
         unsigned long long lk0 = 0, lk1 = 0;
 #pragma unroll
         for (int w = 0; w < BQ_T / 64; ++w) {
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(BQ_T, 3) void bcpqr_kernel(
             s_pay = pay;
             s_ok = ok;
         }
-        __syncthreads();
+        RQLP_LDS_BARRIER();
         gen += 1u;
         if (!s_ok) return;
         const unsigned pay = s_pay;
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(BQ_T, 3) void bcpqr_kernel(
                 s_rank = j;
             }
         }
-        __syncthreads();
+        RQLP_LDS_BARRIER();
         const double b = s_beta;
         // ---- bookkeeping (first workgroup of the block) ----
         if (g == 0) {
@@ -303,7 +304,7 @@ __global__ __launch_bounds__(BQ_T, 3) void bcpqr_kernel(
             }
             nrm2 = sn;
         }
-        __syncthreads();
+        RQLP_LDS_BARRIER();
     }
 
     // ---- R0_j^T in original column order; rows past the rank: completion ----

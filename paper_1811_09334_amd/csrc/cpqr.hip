@@ -273,7 +273,7 @@ __device__ __forceinline__ bool slot_agree(unsigned long long* slots, unsigned l
         s_pay = pay;
         s_ok = ok;
     }
-    __syncthreads();
+    RQLP_LDS_BARRIER();                                  // (the result word's store need not complete here)
     gen = g + 1u;
     payload = s_pay;
     return s_ok != 0;
@@ -548,6 +548,10 @@ __global__ __launch_bounds__(CP_T) void cpqr_kernel(
 // once and reuses it for its 4 columns; the dot products and norms reduce
 // over the 16 lanes of a column with shuffles.  The reflector and the
 // bookkeeping are those of cpqr_kernel; the pivot agreement is slot_agree.
+// Inside the step loop only the drain before a key slot is published waits
+// for this workgroup's global stores (the candidate column must be visible to
+// the others first); the other barriers guard LDS data and do not wait for
+// the first workgroup's reflector stores, which nothing in the kernel reads.
 // lane permutation of a double within DPP rows of 16 lanes
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -663,7 +667,7 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
             s_kred[0][wave] = k0;
             s_kred[1][wave] = k1;
         }
-        __syncthreads();
+        RQLP_LDS_BARRIER();
         // ---- 2. publish the local best column, agree on the pivot ----
         // (every thread combines the wave maxima itself; s_kred is written
         // again only after the barriers of this step's agreement)
@@ -686,7 +690,7 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
                         for (int r = 0; r < RPT; ++r) cst[r0 + r] = x[t][r];
                     }
                 }
-                __syncthreads();
+                RQLP_LDS_BARRIER();
                 double* dst = candcol + ((size_t)(j & 1) * G + g) * rows;
                 for (int i = j + tid; i < rows; i += CP_T) st_coherent(dst + i, cst[i]);
             }
@@ -716,7 +720,7 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
             }
             sg = wave_sum(sg);
             if (lane == 0) s_red[wave] = sg;
-            __syncthreads();
+            RQLP_LDS_BARRIER();
             if (tid == 0) {
                 double sigma = 0.0;
                 for (int w = 0; w < CP_T / 64; ++w) sigma += s_red[w];
@@ -734,7 +738,7 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
                 s_mu = mu;
                 s_red[0] = (sigma == 0.0) ? 0.0 : 1.0 / v0;
             }
-            __syncthreads();
+            RQLP_LDS_BARRIER();
             const double rv0 = s_red[0];
             for (int i = j + 1 + tid; i < rows; i += CP_T) v[i] *= rv0;
             if (tid == 0) {
@@ -749,7 +753,7 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
                 s_rank = j;
             }
         }
-        __syncthreads();
+        RQLP_LDS_BARRIER();
         const double b = s_beta;
         // ---- 4. bookkeeping ----
         if (g == 0) {
@@ -811,7 +815,7 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
                 if (act[t] == -1) nrm2[t] = s;
             }
         }
-        __syncthreads();
+        RQLP_LDS_BARRIER();
     }
 
     // ---- write back: R^T in original column order, pivoted columns of R ----
@@ -836,7 +840,9 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
 // s (32 of them) holds the columns s + 32 t (t < CT), its lane qd the rows
 // qd RPT .. qd RPT + RPT - 1.  No grid agreement: every thread combines the
 // 8 waves' best keys itself and takes the same decision; three workgroup
-// barriers per pivot step (keys, the winning column in LDS, the reflector).
+// barriers per pivot step (keys, the winning column in LDS, the reflector),
+// LDS-only ones: the step's global stores (pivot, beta, reflector) are never
+// read back inside the kernel, and a full __syncthreads would wait for them.
 // Pivot rule, reflector, rank stop and outputs as in cpqr_kernel.
 constexpr int CPW_T = 512;
 template <int RPT, int CT>
@@ -908,7 +914,7 @@ __global__ __launch_bounds__(CPW_T) void cpqr_wg_kernel(const double* __restrict
             s_k[0][wave] = k0;
             s_k[1][wave] = k1;
         }
-        __syncthreads();
+        RQLP_LDS_BARRIER();
         k0 = 0;
         k1 = 0;
 #pragma unroll
@@ -936,7 +942,7 @@ __global__ __launch_bounds__(CPW_T) void cpqr_wg_kernel(const double* __restrict
                     for (int r = 0; r < RPT; ++r) vcol[r0 + r] = (r0 + r >= j) ? x[t][r] : 0.0;
                 }
             }
-            __syncthreads();
+            RQLP_LDS_BARRIER();
             if (wave == 0) {
                 double sg = 0.0;
                 for (int i = j + 1 + lane; i < 16 * RPT; i += 64) sg += vcol[i] * vcol[i];
@@ -957,7 +963,7 @@ __global__ __launch_bounds__(CPW_T) void cpqr_wg_kernel(const double* __restrict
                     s_rv0 = (sg == 0.0) ? 0.0 : 1.0 / v0;
                 }
             }
-            __syncthreads();
+            RQLP_LDS_BARRIER();
             const double b = s_beta, rv0 = s_rv0;
             double vr[RPT];
 #pragma unroll
