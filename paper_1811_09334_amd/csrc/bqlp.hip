@@ -52,19 +52,6 @@ constexpr unsigned long long BQ_SPIN = 1ull << 20;    // ~1 s of polling
 constexpr double kEpsD = 2.220446049250313e-16;
 constexpr unsigned long long kTag = 1ull << 63;       // "slot written" mark (never set in a finite key)
 
-__device__ __forceinline__ unsigned long long xor_u64(unsigned long long v, int m) {
-    const unsigned lo = __shfl_xor((unsigned)v, m, RQLP_WAVE);
-    const unsigned hi = __shfl_xor((unsigned)(v >> 32), m, RQLP_WAVE);
-    return ((unsigned long long)hi << 32) | lo;
-}
-__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = xor_u64(v, off);
-        v = o > v ? o : v;
-    }
-    return v;
-}
-
 // Householder reflector of x = (x0, x_{j+1}, ...) in Parlett's form: H x =
 // mu e_j with mu = ||x|| >= 0; v = (1, x_{j+1} / v0, ...), beta = 2 v0^2 /
 // (sigma + v0^2).  rv0 = 1 / v0 (0 when sigma == 0).

@@ -75,6 +75,38 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// 64-bit lane exchange within rows of 16 lanes by DPP (a lane whose source
+// lies outside its row reads 0), and reads of one lane's 64-bit value
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, 0xF, 0xF, false);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int l) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
+    return a > b ? a : b;
+}
+// Maximum over the wave of a value that is already the same on the 16 lanes
+// of each DPP row (all 64 lanes active): one read per row.
+__device__ __forceinline__ unsigned long long rows_max_u64(unsigned long long v) {
+    return umax64(umax64(readlane_u64(v, 0), readlane_u64(v, 16)), umax64(readlane_u64(v, 32), readlane_u64(v, 48)));
+}
+// Maximum over the wave (all 64 lanes active): DPP within rows of 16 (pairs,
+// quads, half rows, rows; each level exchanges symmetric partners), then
+// one read per row.  Every lane gets the result.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+    v = umax64(v, dpp_u64<0xB1>(v));      // quad_perm(1, 0, 3, 2)
+    v = umax64(v, dpp_u64<0x4E>(v));      // quad_perm(2, 3, 0, 1)
+    v = umax64(v, dpp_u64<0x141>(v));     // row_half_mirror
+    v = umax64(v, dpp_u64<0x140>(v));     // row_mirror
+    return rows_max_u64(v);
+}
+
 // Order-preserving 64-bit key for a non-negative double: larger value ->
 // larger key.  The low `ibits` bits carry (mask - index) so that among equal
 // truncated values the smallest index wins an unsigned max.

@@ -36,13 +36,6 @@ namespace rqlp {
 constexpr int CP_T = 256;
 constexpr unsigned long long CP_SPIN_LIMIT = 1ull << 20;   // ~1 s of polling
 
-__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
-    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
-    lo = __shfl_xor(lo, m, RQLP_WAVE);
-    hi = __shfl_xor(hi, m, RQLP_WAVE);
-    return ((unsigned long long)hi << 32) | lo;
-}
-
 // Cross-workgroup traffic of the CPQR uses only relaxed device-scope atomic
 // loads and stores (st_coherent / ld_coherent) plus completion waits for
 // ordering (drain_and_sync).
@@ -237,11 +230,8 @@ __device__ __forceinline__ bool slot_agree(unsigned long long* slots, unsigned l
                     __builtin_amdgcn_s_sleep(1);
                 }
             }
-            for (int off = 32; off > 0; off >>= 1) {
-                const unsigned long long a = shfl_xor_u64(m0, off), c = shfl_xor_u64(m1, off);
-                m0 = a > m0 ? a : m0;
-                m1 = c > m1 ? c : m1;
-            }
+            m0 = wave_max_u64(m0);
+            m1 = wave_max_u64(m1);
             if (lane == 0) {
                 unsigned pay = 0;
                 if (ok) {
@@ -360,11 +350,8 @@ __global__ __launch_bounds__(CP_T) void cpqr_kernel(
                 k1 = b > k1 ? b : k1;
             }
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            const unsigned long long a = shfl_xor_u64(k0, off), b = shfl_xor_u64(k1, off);
-            k0 = a > k0 ? a : k0;
-            k1 = b > k1 ? b : k1;
-        }
+        k0 = wave_max_u64(k0);
+        k1 = wave_max_u64(k1);
         if (lane == 0) {
             s_kred[0][wave] = k0;
             s_kred[1][wave] = k1;
@@ -544,14 +531,17 @@ __global__ __launch_bounds__(CP_T) void cpqr_kernel(
 // The same factorisation with the columns held in registers instead of LDS.
 // 64 columns per workgroup, 16 per wave; lane l of a wave owns the RPT
 // consecutive rows 16-group (l % 16) of the 4 columns 4 t + l / 16 (t < 4)
-// of its wave.  A step reads this lane's slice of the reflector v from LDS
-// once and reuses it for its 4 columns; the dot products and norms reduce
-// over the 16 lanes of a column with shuffles.  The reflector and the
-// bookkeeping are those of cpqr_kernel; the pivot agreement is slot_agree.
-// Inside the step loop only the drain before a key slot is published waits
-// for this workgroup's global stores (the candidate column must be visible to
-// the others first); the other barriers guard LDS data and do not wait for
-// the first workgroup's reflector stores, which nothing in the kernel reads.
+// of its wave.  Per pivot step: the 16 lanes of the workgroup's best column
+// store its rows >= j and sigma (its squared norm below row j) straight from
+// registers; slot_agree decides the pivot; every thread then reads the
+// winner's sigma and x(j), forms the same reflector (Parlett's form, as in
+// cpqr_kernel) and scales the published rows into v in LDS; the workgroup
+// owning the pivot column writes the pivot, beta and the Householder vector.
+// The dot products and norms reduce over the 16 lanes of a column with DPP;
+// the update is branch-free (row masks are multipliers).  Inside the step
+// loop only the drain before a key slot is published waits for this
+// workgroup's global stores (the candidate column must be visible to the
+// others first); the other barriers guard LDS data.
 // lane permutation of a double within DPP rows of 16 lanes
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -577,11 +567,9 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
     double* candcol, double* partial, unsigned* bar, int64_t* piv, double* Vh, int64_t ldv, double* beta_out,
     double* Rpiv, int64_t ldr, double* Rt, int64_t ldrt, int32_t* info, unsigned long long spin_limit) {
     __shared__ double v[CPR_RG * RPT];
-    __shared__ double cst[CPR_RG * RPT];             // staging of the published column
     __shared__ double s_red[CP_T / 64];
-    __shared__ unsigned long long s_kred[2][CP_T / 64];
-    __shared__ double s_beta, s_mu, s_tol2;
-    __shared__ int s_stop, s_rank;
+    __shared__ unsigned long long s_kred[2][2][CP_T / 64];   // [step parity][k0, k1][wave]
+    __shared__ double s_tol2;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int G = gridDim.x, g = blockIdx.x;
@@ -640,14 +628,16 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
         for (int h = 0; h < G; ++h) f += ld_coherent(partial + h);
         const double tol = (double)(rows > cols ? rows : cols) * 2.220446049250313e-16;
         s_tol2 = tol * tol * f;
-        s_stop = 0;
-        s_rank = kmax;
     }
     __syncthreads();
+    const double tol2 = s_tol2;
+    const int64_t cstride = (int64_t)rows + 1;           // published column: rows values, then sigma
+    int stopped = 0, rank = kmax;
 
     for (int j = 0; j < kmax; ++j) {
-        const int stopped = s_stop;
         // ---- 1. local candidates: by norm (k0) and by smallest index (k1) ----
+        // (col, act and nrm2 are the same on the 16 lanes of a column, so the
+        // wave maximum needs only one read per lane group)
         unsigned long long k0 = 0, k1 = 0;
 #pragma unroll
         for (int t = 0; t < CPR_CT; ++t) {
@@ -658,42 +648,46 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
                 k1 = b > k1 ? b : k1;
             }
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            const unsigned long long a = shfl_xor_u64(k0, off), b = shfl_xor_u64(k1, off);
-            k0 = a > k0 ? a : k0;
-            k1 = b > k1 ? b : k1;
-        }
+        k0 = rows_max_u64(k0);
+        k1 = rows_max_u64(k1);
+        // (double-buffered by step parity: nothing else separates this
+        // step's reads from the next step's writes)
+        unsigned long long(*kr)[CP_T / 64] = s_kred[j & 1];
         if (lane == 0) {
-            s_kred[0][wave] = k0;
-            s_kred[1][wave] = k1;
+            kr[0][wave] = k0;
+            kr[1][wave] = k1;
         }
         RQLP_LDS_BARRIER();
-        // ---- 2. publish the local best column, agree on the pivot ----
-        // (every thread combines the wave maxima itself; s_kred is written
-        // again only after the barriers of this step's agreement)
+        unsigned long long lk0 = 0, lk1 = 0;
+#pragma unroll
+        for (int w = 0; w < CP_T / 64; ++w) {
+            lk0 = kr[0][w] > lk0 ? kr[0][w] : lk0;
+            lk1 = kr[1][w] > lk1 ? kr[1][w] : lk1;
+        }
+        // ---- 2. publish the local best column (rows >= j) and sigma, its
+        // squared norm below row j, straight from the 16 lanes that hold it;
+        // slot_agree makes these stores complete before the keys ----
+        if (lk0 != 0 && !stopped) {
+            const int bc = (int)key_index(lk0, ibits);
+            double* dst = candcol + ((size_t)(j & 1) * G + g) * cstride;
+#pragma unroll
+            for (int t = 0; t < CPR_CT; ++t) {
+                if (col[t] == bc) {
+                    double sq = 0.0;
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        const int i = r0 + r;
+                        if (i >= j && i < rows) st_coherent(dst + i, x[t][r]);
+                        const double xm = x[t][r] * ((i > j) ? 1.0 : 0.0);
+                        sq += xm * xm;
+                    }
+                    sq = colsum(sq);
+                    if (qd == 0) st_coherent(dst + rows, sq);
+                }
+            }
+        }
         unsigned pay = 0;
         {
-            unsigned long long lk0 = 0, lk1 = 0;
-#pragma unroll
-            for (int w = 0; w < CP_T / 64; ++w) {
-                lk0 = s_kred[0][w] > lk0 ? s_kred[0][w] : lk0;
-                lk1 = s_kred[1][w] > lk1 ? s_kred[1][w] : lk1;
-            }
-            const double tol2 = s_tol2;
-            if (lk0 != 0 && !stopped) {
-                // the 16 owner lanes stage the column in LDS, then all threads publish it
-                const int bc = (int)key_index(lk0, ibits);
-#pragma unroll
-                for (int t = 0; t < CPR_CT; ++t) {
-                    if (col[t] == bc) {
-#pragma unroll
-                        for (int r = 0; r < RPT; ++r) cst[r0 + r] = x[t][r];
-                    }
-                }
-                RQLP_LDS_BARRIER();
-                double* dst = candcol + ((size_t)(j & 1) * G + g) * rows;
-                for (int i = j + tid; i < rows; i += CP_T) st_coherent(dst + i, cst[i]);
-            }
             auto decide = [&](unsigned long long k0g, unsigned long long k1g) -> unsigned {
                 unsigned stopnow = 0;
                 if (!stopped) {
@@ -706,57 +700,50 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
             unsigned long long* ks = keys + (size_t)j * cpr_key_words(G);
             if (!slot_agree(ks, gw, G, gen, pay, info, spin_limit, lk0, lk1, decide)) return;
         }
-        const int now_stopped = stopped | (int)(pay >> 31);
+        const int stopnow = (int)(pay >> 31);
+        const int now_stopped = stopped | stopnow;
+        if (stopnow) {
+            stopped = 1;
+            rank = j;
+        }
         const int gidx = (int)(pay & 0x7FFFFFFFu);
         const int owner = gidx / CPR_CPW;
-        // ---- 3. reflector (Parlett's form, R(j, j) = ||x|| >= 0) ----
+        // ---- 3. reflector (Parlett's form, R(j, j) = ||x|| >= 0), formed by
+        // every thread from the published sigma and x(j) ----
+        double b = 0.0, mu = 0.0;
         if (!now_stopped) {
-            const double* src = candcol + ((size_t)(j & 1) * G + owner) * rows;
-            double sg = 0.0;
-            for (int i = j + tid; i < rows; i += CP_T) {
-                const double xv = ld_coherent(src + i);
-                v[i] = xv;
-                if (i > j) sg += xv * xv;
+            const double* src = candcol + ((size_t)(j & 1) * G + owner) * cstride;
+            constexpr int NLD = (CPR_RG * RPT + CP_T - 1) / CP_T;
+            double xs[NLD];
+#pragma unroll
+            for (int u = 0; u < NLD; ++u) {
+                const int i = j + 1 + tid + u * CP_T;
+                xs[u] = (i < rows) ? ld_coherent(src + i) : 0.0;
             }
-            sg = wave_sum(sg);
-            if (lane == 0) s_red[wave] = sg;
-            RQLP_LDS_BARRIER();
-            if (tid == 0) {
-                double sigma = 0.0;
-                for (int w = 0; w < CP_T / 64; ++w) sigma += s_red[w];
-                const double x0 = v[j];
-                const double mu = sqrt(x0 * x0 + sigma);
-                double v0, bb;
-                if (sigma == 0.0) {
-                    v0 = 1.0;
-                    bb = (x0 >= 0.0) ? 0.0 : 2.0;
-                } else {
-                    v0 = (x0 <= 0.0) ? (x0 - mu) : (-sigma / (x0 + mu));
-                    bb = 2.0 * v0 * v0 / (sigma + v0 * v0);
-                }
-                s_beta = bb;
-                s_mu = mu;
-                s_red[0] = (sigma == 0.0) ? 0.0 : 1.0 / v0;
+            const double sg = ld_coherent(src + rows), x0 = ld_coherent(src + j);
+            mu = sqrt(x0 * x0 + sg);
+            double v0;
+            if (sg == 0.0) {
+                v0 = 1.0;
+                b = (x0 >= 0.0) ? 0.0 : 2.0;
+            } else {
+                v0 = (x0 <= 0.0) ? (x0 - mu) : (-sg / (x0 + mu));
+                b = 2.0 * v0 * v0 / (sg + v0 * v0);
             }
-            RQLP_LDS_BARRIER();
-            const double rv0 = s_red[0];
-            for (int i = j + 1 + tid; i < rows; i += CP_T) v[i] *= rv0;
+            const double rv0 = (sg == 0.0) ? 0.0 : 1.0 / v0;
+#pragma unroll
+            for (int u = 0; u < NLD; ++u) {
+                const int i = j + 1 + tid + u * CP_T;
+                if (i < rows) v[i] = xs[u] * rv0;
+            }
             if (tid == 0) {
                 v[j] = 1.0;
                 if (j > 0) v[j - 1] = 0.0;               // v(i) = 0 for every i < j
             }
-        } else if (tid == 0) {
-            s_beta = 0.0;
-            s_mu = 0.0;
-            if (!stopped) {
-                s_stop = 1;
-                s_rank = j;
-            }
+            RQLP_LDS_BARRIER();
         }
-        RQLP_LDS_BARRIER();
-        const double b = s_beta;
-        // ---- 4. bookkeeping ----
-        if (g == 0) {
+        // ---- 4. bookkeeping, by the workgroup of the pivot column ----
+        if (owner == g) {
             if (tid == 0) {
                 if (piv) piv[j] = gidx;
                 if (beta_out) beta_out[j] = b;
@@ -765,9 +752,6 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
                 for (int i = tid; i < rows; i += CP_T)
                     Vh[i + (int64_t)j * ldv] = (i < j || now_stopped) ? ((i == j) ? 1.0 : 0.0) : v[i];
             }
-        }
-        if (owner == g) {
-            const double mu = s_mu;
 #pragma unroll
             for (int t = 0; t < CPR_CT; ++t) {
                 if (col[t] != gidx) continue;
@@ -782,18 +766,22 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
             }
         }
         // ---- 5. apply H = I - b v v^T to the active columns, exact norms ----
-        // (v is zero above row j and past the last row, so the sums run over all rows)
+        // (v is zero above row j and past the last row, so the sums run over
+        // all rows; the row mask i > j is a multiplier, not a select)
         if (!now_stopped) {
-            double vr[RPT];
+            double vr[RPT], msk[RPT];
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) vr[r] = v[r0 + r];
+            for (int r = 0; r < RPT; ++r) {
+                vr[r] = v[r0 + r];
+                msk[r] = (r0 + r > j) ? 1.0 : 0.0;
+            }
             double dot[CPR_CT];
 #pragma unroll
             for (int t = 0; t < CPR_CT; ++t) {
-                double s = 0.0;
+                double sd = 0.0;
 #pragma unroll
-                for (int r = 0; r < RPT; ++r) s += vr[r] * x[t][r];
-                dot[t] = s;
+                for (int r = 0; r < RPT; ++r) sd += vr[r] * x[t][r];
+                dot[t] = sd;
             }
 #pragma unroll
             for (int t = 0; t < CPR_CT; ++t) dot[t] = colsum(dot[t]);
@@ -801,25 +789,27 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
 #pragma unroll
             for (int t = 0; t < CPR_CT; ++t) {
                 const double w = (act[t] == -1) ? b * dot[t] : 0.0;
-                double s = 0.0;
+                double ss = 0.0;
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
                     x[t][r] -= w * vr[r];
-                    s += (r0 + r > j) ? x[t][r] * x[t][r] : 0.0;
+                    const double xm = x[t][r] * msk[r];
+                    ss += xm * x[t][r];
                 }
-                sn[t] = s;
+                sn[t] = ss;
             }
 #pragma unroll
             for (int t = 0; t < CPR_CT; ++t) {
-                const double s = colsum(sn[t]);
-                if (act[t] == -1) nrm2[t] = s;
+                const double sv = colsum(sn[t]);
+                if (act[t] == -1) nrm2[t] = sv;
             }
         }
-        RQLP_LDS_BARRIER();
+        // (v and the key buffers are written again only after the next
+        // step's slot_agree, whose workgroup barrier every thread reaches
+        // after its reads here)
     }
 
     // ---- write back: R^T in original column order, pivoted columns of R ----
-    const int rank = s_rank;
     if (rank < kmax && g == 0 && tid == 0 && info) atomicOr(info, RQLP_INFO_RANK_DEFICIENT);
 #pragma unroll
     for (int t = 0; t < CPR_CT; ++t) {
@@ -839,10 +829,11 @@ __global__ __launch_bounds__(CP_T) void cpqr_reg_kernel(
 // one workgroup of 512 threads: 16 lanes per column (one DPP row), lane group
 // s (32 of them) holds the columns s + 32 t (t < CT), its lane qd the rows
 // qd RPT .. qd RPT + RPT - 1.  No grid agreement: every thread combines the
-// 8 waves' best keys itself and takes the same decision; three workgroup
-// barriers per pivot step (keys, the winning column in LDS, the reflector),
-// LDS-only ones: the step's global stores (pivot, beta, reflector) are never
-// read back inside the kernel, and a full __syncthreads would wait for them.
+// 8 waves' best keys itself and takes the same decision; two workgroup
+// barriers per pivot step (the keys, then the winning column in LDS, from
+// which every thread forms the same reflector), LDS-only ones: the step's
+// global stores (pivot, beta, reflector) are never read back inside the
+// kernel, and a full __syncthreads would wait for them.
 // Pivot rule, reflector, rank stop and outputs as in cpqr_kernel.
 constexpr int CPW_T = 512;
 template <int RPT, int CT>
@@ -851,9 +842,9 @@ __global__ __launch_bounds__(CPW_T) void cpqr_wg_kernel(const double* __restrict
                                                         double* beta_out, double* Rpiv, int64_t ldr, double* Rt,
                                                         int64_t ldrt, int32_t* info) {
     __shared__ double vcol[16 * RPT];
-    __shared__ unsigned long long s_k[2][CPW_T / 64];
+    __shared__ unsigned long long s_k[2][2][CPW_T / 64];   // [step parity][k0, k1][wave]
     __shared__ double s_part[CPW_T / 64];
-    __shared__ double s_beta, s_mu, s_rv0;
+    __shared__ double s_sig;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int qd = lane & 15;
     const int slot = wave * 4 + (lane >> 4);
@@ -895,6 +886,8 @@ __global__ __launch_bounds__(CPW_T) void cpqr_wg_kernel(const double* __restrict
     int stopped = 0, rank = kmax;
     for (int j = 0; j < kmax; ++j) {
         // ---- best keys: by norm (k0) and by smallest index (k1) ----
+        // (col, act and nrm2 are the same on the 16 lanes of a column, so the
+        // wave maximum needs only one read per lane group)
         unsigned long long k0 = 0, k1 = 0;
 #pragma unroll
         for (int t = 0; t < CT; ++t) {
@@ -905,22 +898,23 @@ __global__ __launch_bounds__(CPW_T) void cpqr_wg_kernel(const double* __restrict
                 k1 = b > k1 ? b : k1;
             }
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            const unsigned long long a = shfl_xor_u64(k0, off), b = shfl_xor_u64(k1, off);
-            k0 = a > k0 ? a : k0;
-            k1 = b > k1 ? b : k1;
-        }
+        k0 = rows_max_u64(k0);
+        k1 = rows_max_u64(k1);
+        // (double-buffered by step parity: after the rank stop a step has no
+        // second barrier, and a fast wave's next keys must not overwrite
+        // slots a slow wave is still reading)
+        unsigned long long(*sk)[CPW_T / 64] = s_k[j & 1];
         if (lane == 0) {
-            s_k[0][wave] = k0;
-            s_k[1][wave] = k1;
+            sk[0][wave] = k0;
+            sk[1][wave] = k1;
         }
         RQLP_LDS_BARRIER();
         k0 = 0;
         k1 = 0;
 #pragma unroll
         for (int w = 0; w < CPW_T / 64; ++w) {
-            k0 = s_k[0][w] > k0 ? s_k[0][w] : k0;
-            k1 = s_k[1][w] > k1 ? s_k[1][w] : k1;
+            k0 = sk[0][w] > k0 ? sk[0][w] : k0;
+            k1 = sk[1][w] > k1 ? sk[1][w] : k1;
         }
         int stopnow = 0;
         if (!stopped) {
@@ -934,49 +928,52 @@ __global__ __launch_bounds__(CPW_T) void cpqr_wg_kernel(const double* __restrict
             rank = j;
         }
         if (!now_stopped) {
-            // ---- the winning column in LDS, then its reflector (wave 0) ----
+            // ---- the owner group stages the winning column (rows >= j) in
+            // LDS with sigma = its squared norm below row j; every thread
+            // then forms the same reflector (no third barrier) ----
 #pragma unroll
             for (int t = 0; t < CT; ++t) {
                 if (col[t] == win) {
+                    double sq = 0.0;
 #pragma unroll
-                    for (int r = 0; r < RPT; ++r) vcol[r0 + r] = (r0 + r >= j) ? x[t][r] : 0.0;
-                }
-            }
-            RQLP_LDS_BARRIER();
-            if (wave == 0) {
-                double sg = 0.0;
-                for (int i = j + 1 + lane; i < 16 * RPT; i += 64) sg += vcol[i] * vcol[i];
-                sg = wave_sum(sg);
-                if (lane == 0) {
-                    const double x0 = vcol[j];
-                    const double mu = sqrt(x0 * x0 + sg);
-                    double v0, bb;
-                    if (sg == 0.0) {
-                        v0 = 1.0;
-                        bb = (x0 >= 0.0) ? 0.0 : 2.0;
-                    } else {
-                        v0 = (x0 <= 0.0) ? (x0 - mu) : (-sg / (x0 + mu));
-                        bb = 2.0 * v0 * v0 / (sg + v0 * v0);
+                    for (int r = 0; r < RPT; ++r) {
+                        const int i = r0 + r;
+                        const double xv = x[t][r];
+                        vcol[i] = (i >= j) ? xv : 0.0;
+                        sq += (i > j) ? xv * xv : 0.0;
                     }
-                    s_beta = bb;
-                    s_mu = mu;
-                    s_rv0 = (sg == 0.0) ? 0.0 : 1.0 / v0;
+                    sq = colsum(sq);
+                    if (qd == 0) s_sig = sq;
                 }
             }
             RQLP_LDS_BARRIER();
-            const double b = s_beta, rv0 = s_rv0;
-            double vr[RPT];
+            const double sg = s_sig, x0 = vcol[j];
+            const double mu = sqrt(x0 * x0 + sg);
+            double v0, b;
+            if (sg == 0.0) {
+                v0 = 1.0;
+                b = (x0 >= 0.0) ? 0.0 : 2.0;
+            } else {
+                v0 = (x0 <= 0.0) ? (x0 - mu) : (-sg / (x0 + mu));
+                b = 2.0 * v0 * v0 / (sg + v0 * v0);
+            }
+            const double rv0 = (sg == 0.0) ? 0.0 : 1.0 / v0;
+            // the reflector rows of this lane and the row mask i > j, in
+            // arithmetic form (v(i) = x(i) / v0 below row j, 1 at row j, 0
+            // above: vcol is zero above row j): a select here compiles to a
+            // divergent branch per row
+            double vr[RPT], msk[RPT];
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 const int i = r0 + r;
-                vr[r] = (i > j) ? vcol[i] * rv0 : (i == j ? 1.0 : 0.0);
+                msk[r] = (i > j) ? 1.0 : 0.0;
+                vr[r] = vcol[i] * (rv0 * msk[r]) + ((i == j) ? 1.0 : 0.0);
             }
             if (tid == 0) {
                 if (piv) piv[j] = win;
                 if (beta_out) beta_out[j] = b;
             }
             if (Vh && tid < rows) Vh[tid + (int64_t)j * ldv] = (tid > j) ? vcol[tid] * rv0 : (tid == j ? 1.0 : 0.0);
-            const double mu = s_mu;
             double dot[CT];
 #pragma unroll
             for (int t = 0; t < CT; ++t) {
@@ -987,24 +984,31 @@ __global__ __launch_bounds__(CPW_T) void cpqr_wg_kernel(const double* __restrict
             }
 #pragma unroll
             for (int t = 0; t < CT; ++t) dot[t] = colsum(dot[t]);
+            // the pivot column becomes column j of R and leaves the active set
+            // (its update below is then the identity)
+#pragma unroll
+            for (int t = 0; t < CT; ++t) {
+                if (col[t] == win) {
+#pragma unroll
+                    for (int r = 0; r < RPT; ++r) {
+                        const int i = r0 + r;
+                        if (i >= j) x[t][r] = (i == j) ? mu : 0.0;
+                    }
+                    act[t] = j;
+                }
+            }
             double sn[CT];
 #pragma unroll
             for (int t = 0; t < CT; ++t) {
-                const bool owner = col[t] == win;
-                const double w = (act[t] == -1 && !owner) ? b * dot[t] : 0.0;
+                const double w = (act[t] == -1) ? b * dot[t] : 0.0;
                 double ss = 0.0;
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
-                    const int i = r0 + r;
-                    if (owner) {
-                        if (i >= j) x[t][r] = (i == j) ? mu : 0.0;
-                    } else {
-                        x[t][r] -= w * vr[r];
-                    }
-                    ss += (i > j) ? x[t][r] * x[t][r] : 0.0;
+                    x[t][r] -= w * vr[r];
+                    const double xm = x[t][r] * msk[r];
+                    ss += xm * x[t][r];
                 }
                 sn[t] = ss;
-                if (owner) act[t] = j;
             }
 #pragma unroll
             for (int t = 0; t < CT; ++t) {
@@ -1021,6 +1025,7 @@ __global__ __launch_bounds__(CPW_T) void cpqr_wg_kernel(const double* __restrict
             for (int t = 0; t < CT; ++t)
                 if (col[t] == win) act[t] = j;
         }
+        // vcol and s_sig are written again only after the next step's key barrier
     }
     if (rank < kmax && tid == 0 && info) atomicOr(info, RQLP_INFO_RANK_DEFICIENT);
 #pragma unroll
@@ -1157,7 +1162,7 @@ void cpqr_carve(Arena& ar, int64_t rows, int64_t cols, CpqrScratch* sc) {
     const int kw = cp_key_words(gm) > cpr_key_words(gm) ? cp_key_words(gm) : cpr_key_words(gm);
     const int bw = cp_bar_words(gm) > cpr_bar_words(gm) ? cp_bar_words(gm) : cpr_bar_words(gm);
     sc->keys = ar.take<unsigned long long>((size_t)kmax * kw);
-    sc->candcol = ar.take<double>((size_t)2 * gm * rows);
+    sc->candcol = ar.take<double>((size_t)2 * gm * (rows + 1));   // a column and its sigma per slot
     sc->partial = ar.take<double>(gm);
     sc->bar = ar.take<unsigned>(bw);
 }

@@ -84,7 +84,10 @@ def test_cholqr2_orthonormalizes(gpu, m, c, cond):
                                             # one workgroup holding the whole matrix in registers (rows <= 192,
                                             # cols <= 192): the l x l second factorisation
                                             (125, 125, 13), (192, 192, 14), (150, 40, 15), (20, 180, 16),
-                                            (100, 190, 17)])
+                                            (100, 190, 17),
+                                            # more than 256 workgroups (313): the decider polls its key
+                                            # slots in two chunks of 256
+                                            (24, 20000, 18)])
 def test_cpqr_matches_oracle(gpu, rows, cols, seed):
     rng = np.random.default_rng(seed)
     M = rng.standard_normal((rows, cols)) * np.exp(rng.uniform(-6, 0, cols))[None, :]
