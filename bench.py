@@ -161,6 +161,32 @@ def roofline_lp(rq, A, V, w, dev):
             "mfma_tflops": round(flops / t / 1e12, 2), "mfma_frac": round(flops / t / 1e12 / PEAK["bf16"], 4)}
 
 
+def lval_vs(f, ref, k):
+    """L-values j < k of factorisation f against those of ref (the FP64 GPU
+    factorisation of the same matrix and Omega): the first step where the
+    first-CPQR pivots differ (-1: none), the largest relative difference over
+    the steps before it (same pivots, so the difference is rounding), and
+    over all k steps ("free": after a divergence the two runs factor
+    different columns, so that figure mixes pivot choice with rounding)."""
+    lv, lr = f.lvals.cpu().numpy(), ref.lvals.cpu().numpy()
+    d = np.flatnonzero(f.piv0.cpu().numpy() != ref.piv0.cpu().numpy())
+    div = int(d[0]) if d.size else -1
+    rel = np.abs(lv[:k] - lr[:k]) / lr[:k]
+    pre = rel[: (div if div >= 0 else k)]
+    return {"first_pivot_divergence_vs_f64": div,
+            "lval_rel_err_vs_f64_before_divergence": float(pre.max()) if pre.size else None,
+            "lval_rel_err_vs_f64": float(rel.max())}
+
+
+def lval_text(r):
+    pre = r["lval_rel_err_vs_f64_before_divergence"]
+    return (f"L-value rel err vs f64 {pre:.2e} over the {r['first_pivot_divergence_vs_f64']} steps before the "
+            f"first pivot divergence (free {r['lval_rel_err_vs_f64']:.2e})"
+            if r["first_pivot_divergence_vs_f64"] >= 0 else
+            f"L-value rel err vs f64 {r['lval_rel_err_vs_f64']:.2e} (same pivots)") if pre is not None else \
+        f"first pivots differ (free L-value rel err vs f64 {r['lval_rel_err_vs_f64']:.2e})"
+
+
 def other_workloads(rq, inputs, dev):
     """Short timings (3 steps after 1 warm-up) of the other workloads of the
     hot path, each on its own synthetic matrix: FP64 ERQLP (20000 x 10000),
@@ -178,6 +204,18 @@ def other_workloads(rq, inputs, dev):
         F = flop_model(w.m, w.n, w.l, w.q)
         rec = {"ms_per_step": round(ms, 3), "tflops": round(F / (ms * 1e-3) / 1e12, 3), "precision": w.precision,
                "m": w.m, "n": w.n, "k": w.k, "p": w.p, "q": w.q, "d": w.d, "b": w.b, "info": int(f.info.item())}
+        if w.precision in ("bf16", "fp16", "bf16x3"):
+            # accuracy of the 16-bit products: one FP64 factorisation of the same matrix and Omega
+            del work
+            A64 = rq.empty_colmajor(w.m, w.n, torch.float64, dev)
+            A64.copy_(A)
+            w64 = torch.empty(rq.workspace_size(w.m, w.n, w.k, w.p, w.q, w.d, w.b, "f64"), dtype=torch.uint8,
+                              device=dev)
+            f64r = rq.factor(A64, w.k, w.p, q=w.q, d=w.d, b=w.b, precision="f64", seed=w.seed_omega, work=w64)
+            rec.update(lval_vs(f, f64r, w.k))
+            del A64, w64, f64r
+            work = None
+            torch.cuda.empty_cache()
         if name.startswith("drqlp"):
             dT = torch.zeros(w.l, w.l, dtype=torch.float64, device=dev)
             dT.diagonal()[: w.k] = torch.as_tensor(inputs.uniform_weights(w.k, 3000), device=dev)
@@ -190,7 +228,8 @@ def other_workloads(rq, inputs, dev):
             del bw
         out[name] = rec
         print(f"# {name}: {ms:.3f} ms/step" + (f", backward {rec['backward_ms']:.3f} ms" if "backward_ms" in rec
-                                               else ""), file=sys.stderr, flush=True)
+                                               else "")
+              + (f"; {lval_text(rec)}" if "lval_rel_err_vs_f64" in rec else ""), file=sys.stderr, flush=True)
         del A, work, f
         torch.cuda.empty_cache()
     return out
@@ -267,8 +306,8 @@ def autorank_leg(rq, inputs, dev):
 def main():
     args = parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1811_09334_amd as rq
@@ -330,9 +369,9 @@ def main():
         ms64, f64r = timed(lambda: rq.factor(A64, w.k, w.p, q=w.q, d=w.d, b=w.b, precision="f64", seed=seed,
                                              work=w64), steps64, 1)
         fp64 = {"ms_per_step": round(ms64, 4), "tflops": round(F / (ms64 * 1e-3) / 1e12, 4), "steps": steps64,
-                "info": int(f64r.info.item())}
-        print(f"# f64 on the same matrix: {ms64:.3f} ms/step ({ms64 / ms:.2f}x the {w.precision} time)",
-              file=sys.stderr, flush=True)
+                "info": int(f64r.info.item()), **lval_vs(f, f64r, w.k)}
+        print(f"# f64 on the same matrix: {ms64:.3f} ms/step ({ms64 / ms:.2f}x the {w.precision} time); "
+              f"{lval_text(fp64)}", file=sys.stderr, flush=True)
         del A64, w64, f64r
         torch.cuda.empty_cache()
 

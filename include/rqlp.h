@@ -61,7 +61,7 @@ enum rqlp_status {
     RQLP_OK = 0,
     RQLP_E_WORKSPACE = -1000,   /* work_bytes smaller than rqlp_workspace_size() */
     RQLP_E_HIP = -1001,         /* a HIP launch / runtime call failed            */
-    RQLP_E_UNSUPPORTED = -1002, /* valid arguments this build does not handle     */
+    RQLP_E_UNSUPPORTED = -1002, /* valid arguments the library does not handle  */
     RQLP_E_SCRATCH_LIMIT = -1003 /* rqlp_factor_noalloc: problem needs more than
                                     RQLP_NOALLOC_SCRATCH_BYTES of workspace      */
 };
@@ -216,7 +216,7 @@ int rqlp_factor_autorank(const void* A, int64_t lda, int64_t m, int64_t n, int64
  * orthonormal, T (kt x kt) lower triangular, diag(T) the L-values.  With
  * kt = min(m, n) this is Stewart's full pivoted QLP (exact reconstruction).
  *
- *   A      m x n double (lda >= m), read only; m <= 6144 in this build
+ *   A      m x n double (lda >= m), read only; m <= 6144 in this library
  *          (RQLP_E_UNSUPPORTED beyond).
  *   kt     number of pivot steps, 1 <= kt <= min(m, n).
  *   Q, T, P  outputs (ldq >= m, ldt >= kt, ldp >= n).

@@ -8,7 +8,7 @@ library; it takes the Gaussian test matrix Omega as data.
 Notation follows the paper: A is m x n, k the target rank, p the
 oversampling, l = k + p, d the number of inner (unpivoted) QR steps of ERQLP,
 b the block size of block RQLP.  q (subspace/power iterations of the range
-finder, Halko et al. 2011, Sec. 4.5) is an extra input of this build: with
+finder, Halko et al. 2011, Sec. 4.5) is an extra input here: with
 q = 0 the range finder is exactly the paper's (Section 2, three steps).
 
 Readings taken where the paper is silent or inconsistent (listed with the

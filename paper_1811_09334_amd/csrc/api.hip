@@ -388,9 +388,8 @@ void carve_range_lp(Arena& ar, int64_t m, int64_t n, int64_t l, int precision, b
 
 // Scratch of the block reorthogonalisation.
 struct BcgsScratch {
-    void* C;        // l x bs coefficients
-    void* p0;       // rows x bs panels
-    void* p1;
+    void* C;        // l x ob coefficients (ob: the column block of ortho_block)
+    void* p1;       // rows x ob panel
     void* ws;       // split-K partials (T)
     size_t ws_elems;
 };
@@ -437,31 +436,47 @@ int bcgs2(CtxT& cx, int64_t rows, int64_t l, int64_t bs, T* V, int64_t ld, BcgsS
     return 0;
 }
 
-// Orthonormalisation of a rows x l panel: as a whole (bs == 0, CholeskyQR),
-// or by blocks of bs columns (the last one ragged): a QR of the first block,
-// then block Gram-Schmidt twice for the others.  Both forms are triangular
-// (column j of the result lies in the span of columns 0..j of the input), so
-// the leading blocks of the range finder's basis span the images of the
-// leading blocks of Omega: the blocks of Algorithm 4.1.  The result is in
-// *out (buf0 or buf1).
+// Column block of the block orthonormalisation for the block size bs of
+// Algorithm 4.1: the largest multiple of bs that one CholeskyQR pass on the
+// matrix cores takes (448 FP64, 512 FP32 columns), or the whole panel.  Any
+// such blocking gives the same basis up to rounding: every form here is
+// triangular (column j of the result lies in the span of columns 0..j of the
+// input, with a positive diagonal), so the leading blocks of the range
+// finder's basis span the images of the leading blocks of Omega and are
+// those of Algorithm 4.1's one-block-at-a-time construction (for a fixed
+// Omega the block and unblocked range finders agree).  Wider blocks turn the
+// many narrow projections into a few wide products.
+int64_t ortho_block(int64_t bs, int64_t l, bool f64) {
+    const int64_t cap = f64 ? 448 : 512;
+    if (bs <= 0 || bs >= l) return l;
+    int64_t ob = bs <= cap ? (cap / bs) * bs : bs;
+    return ob >= l ? l : ob;
+}
+
+// Orthonormalisation of a rows x l panel: as a whole (bs == 0, or one block
+// covers it: CholeskyQR), or by the column blocks of ortho_block (the last
+// one ragged): a QR of the first block, then block Gram-Schmidt for the
+// others.  The result is in *out (buf0 or buf1).
 int ortho_f64(Ctx& cx, int64_t rows, int64_t l, int64_t bs, double* buf0, double* buf1, int64_t ld, double** out,
               bool final, BcgsScratch& bc) {
-    if (bs <= 0 || bs >= l) return cholqr2(cx, rows, l, buf0, buf1, ld, nullptr, out, final);
+    const int64_t ob = ortho_block(bs, l, true);
+    if (ob >= l) return cholqr2(cx, rows, l, buf0, buf1, ld, nullptr, out, final);
     double* o = nullptr;
-    RQLP_TRY(cholqr2(cx, rows, bs, buf0, buf1, ld, nullptr, &o, final));
-    if (o != buf0) RQLP_TRY(copy_matrix(rows, bs, o, ld, buf0, ld, cx.s));
-    RQLP_TRY((bcgs2<double, Ctx>(cx, rows, l, bs, buf0, ld, bc, final, cx.s)));
+    RQLP_TRY(cholqr2(cx, rows, ob, buf0, buf1, ld, nullptr, &o, final));
+    if (o != buf0) RQLP_TRY(copy_matrix(rows, ob, o, ld, buf0, ld, cx.s));
+    RQLP_TRY((bcgs2<double, Ctx>(cx, rows, l, ob, buf0, ld, bc, final, cx.s)));
     *out = buf0;
     return 0;
 }
 
 int ortho_f32(Ctx32& cx, int64_t rows, int64_t l, int64_t bs, float* buf0, float* buf1, int64_t ld, float** out,
               bool final, BcgsScratch& bc) {
-    if (bs <= 0 || bs >= l) return cholqr_f32(cx, rows, l, buf0, buf1, ld, out, final);
+    const int64_t ob = ortho_block(bs, l, false);
+    if (ob >= l) return cholqr_f32(cx, rows, l, buf0, buf1, ld, out, final);
     float* o = nullptr;
-    RQLP_TRY(cholqr_f32(cx, rows, bs, buf0, buf1, ld, &o, final));
-    if (o != buf0) RQLP_TRY((cast_matrix<float, float>(rows, bs, o, ld, buf0, ld, cx.s)));
-    RQLP_TRY((bcgs2<float, Ctx32>(cx, rows, l, bs, buf0, ld, bc, final, cx.s)));
+    RQLP_TRY(cholqr_f32(cx, rows, ob, buf0, buf1, ld, &o, final));
+    if (o != buf0) RQLP_TRY((cast_matrix<float, float>(rows, ob, o, ld, buf0, ld, cx.s)));
+    RQLP_TRY((bcgs2<float, Ctx32>(cx, rows, l, ob, buf0, ld, bc, final, cx.s)));
     *out = buf0;
     return 0;
 }
@@ -557,14 +572,15 @@ void carve_factor(Arena& ar, int64_t m, int64_t n, int64_t l, int precision, boo
         carve_range_lp(ar, m, n, l, precision, need_omega, &L->rlp);
         carve_small(ar, n, l, cp_rows, {}, &L->sm);
     }
-    L->bc = BcgsScratch{nullptr, nullptr, nullptr, nullptr, 0};
+    L->bc = BcgsScratch{nullptr, nullptr, nullptr, 0};
     L->Bj = nullptr;
     if (bs > 0) {
         const size_t es = precision == RQLP_F64 ? sizeof(double) : sizeof(float);
-        L->bc.C = ar.take<char>(l * bs * es);
-        L->bc.p0 = ar.take<char>(m * bs * es);
-        L->bc.p1 = ar.take<char>(m * bs * es);
-        L->bc.ws_elems = max_ws(gemm_workspace_elems, {{l, bs, m}, {m, bs, l}, {l, bs, n}, {n, bs, l}});
+        const int64_t ob = ortho_block(bs, l, precision == RQLP_F64);
+        const int64_t mx = m > n ? m : n;            // rows of the Y (m) and Z (n) panels
+        L->bc.C = ar.take<char>(l * ob * es);
+        L->bc.p1 = ar.take<char>(mx * ob * es);
+        L->bc.ws_elems = max_ws(gemm_workspace_elems, {{l, ob, m}, {m, ob, l}, {l, ob, n}, {n, ob, l}});
         L->bc.ws = ar.take<char>(L->bc.ws_elems * es);
         L->Bj = ar.take<double>(bs * n);
         if (bs <= 64) bqlp_carve(ar, n, l, bs, &L->bq);
@@ -666,7 +682,7 @@ const char* rqlp_status_string(int status) {
     if (status == RQLP_OK) return "success";
     if (status == RQLP_E_WORKSPACE) return "workspace too small";
     if (status == RQLP_E_HIP) return "HIP runtime or launch error";
-    if (status == RQLP_E_UNSUPPORTED) return "arguments valid but not supported by this build";
+    if (status == RQLP_E_UNSUPPORTED) return "arguments valid but not supported by this library";
     if (status == RQLP_E_SCRATCH_LIMIT)
         return "rqlp_factor_noalloc: the problem needs more workspace than the library's static scratch "
                "(RQLP_NOALLOC_SCRATCH_BYTES); use rqlp_factor with a caller workspace";

@@ -59,11 +59,11 @@ constexpr int GEMM_THREADS = 256;
 
 // T: arithmetic (MFMA) type; TI: element type of A and B (converted to T on
 // load); TC: element type of C / of the split-K partials.
-template <typename T, bool TA, bool TB, int MB, int NB, int BK, typename TI, typename TC>
+template <typename T, bool TA, bool TB, int MB, int NB, int BK, typename TI, typename TC, bool AB>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
     int64_t M, int64_t N, int64_t K, const TI* __restrict__ A, int64_t lda,
     const TI* __restrict__ B, int64_t ldb, TC* __restrict__ C, int64_t ldc, int64_t split_stride,
-    int64_t kchunk, const int32_t* __restrict__ gate, int gate_copy, int tri) {
+    int64_t kchunk, const int32_t* __restrict__ gate, int gate_copy, int tri, T alpha, T beta) {
     constexpr int BM = 64 * MB;
     constexpr int BN = 16 * NB;
     constexpr int SA = TA ? (BK + 2) : (BM + 16);
@@ -209,7 +209,8 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
         buf ^= 1;
     }
 
-    // ---- write C (or this split's partial) ----
+    // ---- write C (or this split's partial); AB: C = alpha op(A) op(B) + beta C
+    // for a product in one K split (C read only when beta != 0) ----
     TC* Cs = C + (int64_t)blockIdx.z * split_stride;
 #pragma unroll
     for (int a = 0; a < MB; ++a)
@@ -220,7 +221,15 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t i = m0 + wave * 16 * MB + a * 16 + Mfma<T>::row(lane, r);
-                if (i < M) Cs[i + j * ldc] = (TC)acc[a][b][r];
+                if (i < M) {
+                    if constexpr (AB) {
+                        T v = alpha * acc[a][b][r];
+                        if (beta != T(0)) v += beta * (T)Cs[i + j * ldc];
+                        Cs[i + j * ldc] = (TC)v;
+                    } else {
+                        Cs[i + j * ldc] = (TC)acc[a][b][r];
+                    }
+                }
             }
         }
 }
@@ -322,20 +331,29 @@ GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K) {
 template <typename T, typename TI, typename TC, bool TA, bool TB, int NB>
 void launch_nb(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const TI* A, int64_t lda,
                const TI* B, int64_t ldb, TC* C, int64_t ldc, int64_t split_stride, const int32_t* gate, int gate_copy,
-               int tri, hipStream_t s) {
+               int tri, T alpha, T beta, hipStream_t s) {
     dim3 grid((unsigned)p.tm, (unsigned)p.tn, (unsigned)p.S);
-    hipLaunchKernelGGL((gemm_skinny_kernel<T, TA, TB, 1, NB, GEMM_BK, TI, TC>), grid, dim3(GEMM_THREADS), 0, s, M, N,
-                       K, A, lda, B, ldb, C, ldc, split_stride, p.kchunk, gate, gate_copy, tri);
+    // (the alpha / beta epilogue is a variant of its own: keeping it out of the
+    // plain product leaves that kernel's register count, hence its occupancy, alone)
+    if (alpha == T(1) && beta == T(0))
+        hipLaunchKernelGGL((gemm_skinny_kernel<T, TA, TB, 1, NB, GEMM_BK, TI, TC, false>), grid, dim3(GEMM_THREADS),
+                           0, s, M, N, K, A, lda, B, ldb, C, ldc, split_stride, p.kchunk, gate, gate_copy, tri, alpha,
+                           beta);
+    else
+        hipLaunchKernelGGL((gemm_skinny_kernel<T, TA, TB, 1, NB, GEMM_BK, TI, TC, true>), grid, dim3(GEMM_THREADS),
+                           0, s, M, N, K, A, lda, B, ldb, C, ldc, split_stride, p.kchunk, gate, gate_copy, tri, alpha,
+                           beta);
 }
 
 template <typename T, typename TI, typename TC, bool TA, bool TB>
 void launch_dispatch(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const TI* A, int64_t lda,
                      const TI* B, int64_t ldb, TC* C, int64_t ldc, int64_t split_stride, const int32_t* gate,
-                     int gate_copy, int tri, hipStream_t s) {
+                     int gate_copy, int tri, T alpha, T beta, hipStream_t s) {
     switch (p.nb) {
 #define RQLP_NB_CASE(X)                                                                                           \
     case X:                                                                                                       \
-        launch_nb<T, TI, TC, TA, TB, X>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, tri, s); \
+        launch_nb<T, TI, TC, TA, TB, X>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, tri,   \
+                                        alpha, beta, s);                                                          \
         break;
         RQLP_NB_CASE(1) RQLP_NB_CASE(2) RQLP_NB_CASE(3) RQLP_NB_CASE(4)
         RQLP_NB_CASE(5) RQLP_NB_CASE(6) RQLP_NB_CASE(7)
@@ -358,17 +376,17 @@ size_t gemm_workspace_elems(int64_t M, int64_t N, int64_t K) {
 template <typename T, typename TI, typename TC>
 static void launch_any(bool ta, bool tb, const GemmPlan& p, int64_t M, int64_t N, int64_t K, const TI* A,
                        int64_t lda, const TI* B, int64_t ldb, TC* C, int64_t ldc, int64_t split_stride,
-                       const int32_t* gate, int gate_copy, int tri, hipStream_t s) {
+                       const int32_t* gate, int gate_copy, int tri, T alpha, T beta, hipStream_t s) {
     if (ta && tb) return;   // not needed by the method
     if (ta)
         launch_dispatch<T, TI, TC, true, false>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, tri,
-                                                s);
+                                                alpha, beta, s);
     else if (tb)
         launch_dispatch<T, TI, TC, false, true>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy, tri,
-                                                s);
+                                                alpha, beta, s);
     else
         launch_dispatch<T, TI, TC, false, false>(p, M, N, K, A, lda, B, ldb, C, ldc, split_stride, gate, gate_copy,
-                                                 tri, s);
+                                                 tri, alpha, beta, s);
 }
 
 // T: arithmetic and split-K partial type; TI: A, B; TC: C.
@@ -390,17 +408,18 @@ static int gemm_impl(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const TI
         }
     }
     GemmPlan p = plan_gemm(M, N, K);
-    const bool direct = (p.S == 1 && !trans_out && alpha == T(1) && beta == T(0));
+    // one K split: the product kernel applies alpha and beta itself
+    const bool direct = (p.S == 1 && !trans_out);
     // the gated copy (gate_mode 2) writes op(A) straight into C: only for a
-    // direct product with op(A) = A of the output's shape
-    if (gate_mode == 2 && (!direct || ta || K != N)) return RQLP_E_UNSUPPORTED;
+    // direct product C = op(A) op(B) with op(A) = A of the output's shape
+    if (gate_mode == 2 && (!direct || ta || K != N || alpha != T(1) || beta != T(0))) return RQLP_E_UNSUPPORTED;
     const int gate_copy = gate_mode == 2 ? 1 : 0;
     if (direct) {
-        launch_any<T, TI, TC>(ta, tb, p, M, N, K, A, lda, B, ldb, C, ldc, 0, gate, gate_copy, tri, s);
+        launch_any<T, TI, TC>(ta, tb, p, M, N, K, A, lda, B, ldb, C, ldc, 0, gate, gate_copy, tri, alpha, beta, s);
         return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
     }
     if ((size_t)(p.S * M * N) > ws_elems || ws == nullptr) return RQLP_E_WORKSPACE;
-    launch_any<T, TI, T>(ta, tb, p, M, N, K, A, lda, B, ldb, ws, M, M * N, gate, 0, tri, s);
+    launch_any<T, TI, T>(ta, tb, p, M, N, K, A, lda, B, ldb, ws, M, M * N, gate, 0, tri, T(1), T(0), s);
     if (trans_out) {
         dim3 grid((unsigned)ceil_div(M, 32), (unsigned)ceil_div(N, 32));
         hipLaunchKernelGGL((splitk_reduce_t_kernel<T, TC>), grid, dim3(256), 0, s, M, N, ws, M, M * N, (int)p.S,

@@ -523,13 +523,24 @@ int cast_panel(int kind, int64_t R, int64_t K, const float* src, int64_t ld, uns
 }
 
 // colexp[j] = e with max_i |A(i, j)| 2^-e in [2^14, 2^15) (0 for a zero or
-// non-finite column); one workgroup per column.
+// non-finite column); one workgroup per column, 16-byte loads when the
+// columns are 16-byte aligned (vec).
 __global__ __launch_bounds__(256) void colexp_kernel(int64_t rows, const float* __restrict__ A, int64_t lda,
-                                                     int* __restrict__ colexp) {
+                                                     int vec, int* __restrict__ colexp) {
     __shared__ float red[4];
     const int64_t j = blockIdx.x;
+    const float* col = A + j * lda;
     float mx = 0.f;
-    for (int64_t i = threadIdx.x; i < rows; i += 256) mx = fmaxf(mx, fabsf(A[i + j * lda]));
+    int64_t i = threadIdx.x;
+    if (vec) {
+        const int64_t r4 = rows >> 2;
+        for (int64_t q = threadIdx.x; q < r4; q += 256) {
+            const float4_t v = *(const float4_t*)(col + 4 * q);
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))));
+        }
+        i = 4 * r4 + threadIdx.x;
+    }
+    for (; i < rows; i += 256) mx = fmaxf(mx, fabsf(col[i]));
     for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
     __syncthreads();
@@ -553,7 +564,8 @@ __global__ __launch_bounds__(256) void gexp_kernel(int64_t n, const int* __restr
 int column_exponents(int64_t rows, int64_t cols, const float* A, int64_t lda, int* colexp, int* gexp,
                      hipStream_t s) {
     if (rows <= 0 || cols <= 0) return 0;
-    hipLaunchKernelGGL(colexp_kernel, dim3((unsigned)cols), dim3(256), 0, s, rows, A, lda, colexp);
+    const int vec = (lda % 4 == 0) && ((((uintptr_t)A) & 15) == 0);
+    hipLaunchKernelGGL(colexp_kernel, dim3((unsigned)cols), dim3(256), 0, s, rows, A, lda, vec, colexp);
     hipLaunchKernelGGL(gexp_kernel, dim3(1), dim3(256), 0, s, cols, colexp, gexp);
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
