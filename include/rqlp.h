@@ -86,8 +86,8 @@ const char* rqlp_status_string(int status);
 int rqlp_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p, int q, int d, int b,
                         int precision, size_t* bytes);
 
-/* Gaussian test matrix (Section 2, range finder step 1; Algorithm 2.1
- * step 1): Omega (n x l, leading dimension ldo) with N(0,1) entries.
+/* Gaussian test matrix (Section 2, the range finder's random matrix;
+ * Algorithm 2.1): Omega (n x l, leading dimension ldo) with N(0,1) entries.
  * Element (i, j) is Box-Muller applied to the first two 32-bit words of
  * Philox4x32-10 (Salmon et al., SC'11) with counter (i, j, 0, 0) and key
  * (low 32 bits of seed, high 32 bits of seed):
@@ -105,7 +105,7 @@ int rqlp_generate_omega(int64_t n, int64_t l, uint64_t seed, int precision,
  *   k, p   target rank k >= 2 and oversampling p >= 2 (Algorithm 2.1 input),
  *          l = k + p <= n <= m (Section 1 problem statement).
  *   q      number of subspace iterations of the range finder, q >= 0.
- *   d      0: RQLP, second factorisation pivoted (Algorithm 2.1 step 6);
+ *   d      0: RQLP, second factorisation pivoted (Algorithm 2.1);
  *          d >= 1: ERQLP with d unpivoted inner QR steps (Algorithm 2.2).
  *   b      0: unblocked; b >= 1: block RQLP with blocks of b columns of
  *          Omega (Algorithm 4.1; the last block is ragged when b does not
@@ -212,7 +212,7 @@ int rqlp_factor_autorank(const void* A, int64_t lda, int64_t m, int64_t n, int64
  * Section 1; the "QLP" comparison method of Section 5), FP64: kt steps of the
  * column-pivoted Householder QR of A itself, A Pi0 ~= Qhat R with R its first
  * kt rows, then the pivoted QR of R^T (the second factorisation of
- * Algorithm 2.1 step 6): A ~= Q T P^T with Q (m x kt) and P (n x kt)
+ * Algorithm 2.1): A ~= Q T P^T with Q (m x kt) and P (n x kt)
  * orthonormal, T (kt x kt) lower triangular, diag(T) the L-values.  With
  * kt = min(m, n) this is Stewart's full pivoted QLP (exact reconstruction).
  *
@@ -275,7 +275,7 @@ int rqlp_backward(const void* A, int64_t lda, int64_t m, int64_t n, int64_t k, i
 int rqlp_backward_workspace_size(int64_t m, int64_t n, int64_t k, int64_t p, int q, int d, int b,
                                  int precision, size_t* bytes);
 
-/* Y = A X  (Algorithm 2.1 step 2, and every pass of the subspace iteration):
+/* Y = A X  (the sketch of Algorithm 2.1, and every pass of the subspace iteration):
  * A m x n, X n x c, Y m x c, all double (RQLP_F64) or all float (any other
  * precision).  The mixed precisions round A and X to their 16-bit type as
  * rqlp_encode does and accumulate in FP32 (RQLP_MIXED_FP16 scales column j
@@ -286,7 +286,7 @@ int rqlp_sketch(const void* A, int64_t lda, int64_t m, int64_t n, const void* X,
                 int64_t c, void* Y, int64_t ldy, int precision, void* work, size_t work_bytes,
                 void* stream);
 
-/* B = V^T A  (Algorithm 2.1 step 4): V m x c, A m x n, B c x n; element
+/* B = V^T A  (the projection of Algorithm 2.1): V m x c, A m x n, B c x n; element
  * types and 16-bit rounding as for rqlp_sketch (FP16: B(:, j) carries the
  * column scale 2^e_j back). */
 int rqlp_project(const void* A, int64_t lda, int64_t m, int64_t n, const void* V, int64_t ldv,
@@ -300,7 +300,7 @@ int rqlp_gemm_workspace(int64_t m, int64_t n, int64_t c, int precision, size_t* 
 
 /* 16-bit encoding of the FP32 matrix A (m x n) used by the MFMA products of
  * the mixed precisions (the sketch / projection operands of Algorithm 2.1
- * steps 2 and 4 in reduced precision).  precision is RQLP_MIXED_BF16,
+ * in reduced precision).  precision is RQLP_MIXED_BF16,
  * RQLP_MIXED_FP16 or RQLP_MIXED_BF16X3; each element x of A becomes
  *   BF16   : hi = bf16(x) (round to nearest even);
  *   BF16X3 : hi = bf16(x), lo = bf16(x - hi);
@@ -325,7 +325,7 @@ int rqlp_encoded_elems(int64_t m, int64_t n, int form, size_t* elems);
 int rqlp_encode(const float* A, int64_t lda, int64_t m, int64_t n, int precision, int form,
                 uint16_t* Ahi, uint16_t* Alo, int32_t* colexp, int32_t* gexp, void* stream);
 
-/* B = V^T A (Algorithm 2.1 step 4) with A given by rqlp_encode in form
+/* B = V^T A (the projection of Algorithm 2.1) with A given by rqlp_encode in form
  * RQLP_ENC_COLS (Ahi, Alo; colexp for RQLP_MIXED_FP16, else NULL; gexp is
  * not used and may be NULL); V is m x c float, rounded to the same 16-bit
  * type inside; B is c x n float, FP32 accumulation.  Lets a caller encode A
@@ -335,7 +335,7 @@ int rqlp_project_encoded(const uint16_t* Ahi, const uint16_t* Alo, const int32_t
                          int64_t c, float* B, int64_t ldb, int precision, void* work,
                          size_t work_bytes, void* stream);
 
-/* Y = A X (Algorithm 2.1 step 2 and the subspace iterations) with A given by
+/* Y = A X (the sketch of Algorithm 2.1 and the subspace iterations) with A given by
  * rqlp_encode in form RQLP_ENC_ROWS (colexp and gexp required for
  * RQLP_MIXED_FP16); X is n x c float, rounded inside (FP16: row j scaled by
  * 2^(e_j - g), Y by 2^g); Y is m x c float.  Same error conventions as
@@ -345,7 +345,7 @@ int rqlp_sketch_encoded(const uint16_t* Ahi, const uint16_t* Alo, const int32_t*
                         int64_t c, float* Y, int64_t ldy, int precision, void* work,
                         size_t work_bytes, void* stream);
 
-/* [V, ~] = qr(Y)  (Algorithm 2.1 step 3): V (m x c) gets an orthonormal basis
+/* Orthonormalisation of the range finder (Algorithm 2.1): V (m x c) gets an orthonormal basis
  * of range(Y) by CholeskyQR2 (shifted retry on breakdown); Y is m x c,
  * double.  R (c x c upper, ldr >= c, may be NULL) receives the triangular
  * factor with Y = V R, diag(R) > 0.  V may alias Y. */
@@ -355,7 +355,7 @@ int rqlp_orthonormalize(const double* Y, int64_t ldy, int64_t m, int64_t c, doub
 int rqlp_orthonormalize_workspace(int64_t m, int64_t c, size_t* bytes);
 
 /* Column-pivoted Householder QR of the rows x cols double matrix M
- * (Algorithm 2.1 steps 5-6; the CPQR of Section 1): M Pi = Qm R with the
+ * (the first CPQR of Algorithm 2.1; the CPQR of Section 1): M Pi = Qm R with the
  * Businger-Golub pivot rule (largest residual column norm, residual norms
  * recomputed each step), diag(R) >= 0.  Outputs (any may be NULL):
  *   piv   min(rows, cols) int64 pivots (original column indices);

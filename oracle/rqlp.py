@@ -57,7 +57,7 @@ class QLPResult:
 # range finder (Section 2: draw Omega, Y = A Omega, orthonormalise Y)
 # ---------------------------------------------------------------------------
 def orthonormal_basis(Y: np.ndarray) -> np.ndarray:
-    """[V, ~] = qr(Y): thin Householder QR (LAPACK), V has orthonormal columns."""
+    """Orthonormal basis V of range(Y): thin Householder QR (LAPACK)."""
     V, _ = np.linalg.qr(Y, mode="reduced")
     return V
 
@@ -72,7 +72,7 @@ def range_finder(A: np.ndarray, Omega: np.ndarray, q: int = 0) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# pivoted QLP of the reduced matrix B (steps 5-7 of Alg. 2.1, 5-9 of Alg. 2.2)
+# pivoted QLP of the reduced matrix B (Alg. 2.1 and Alg. 2.2)
 # ---------------------------------------------------------------------------
 def _rows_by_perm(perm: np.ndarray, M: np.ndarray) -> np.ndarray:
     """Pi M for the permutation matrix Pi with (X Pi) = X[:, perm]: row perm[i] <- row i."""
@@ -140,7 +140,7 @@ def rqlp(A: np.ndarray, Omega: np.ndarray, k: int, p: int, q: int = 0, d: int = 
          piv0: Optional[Sequence[int]] = None, piv1: Optional[Sequence[int]] = None) -> QLPResult:
     """Randomized QLP of A (m x n) with the given n x (k+p) Gaussian matrix Omega.
 
-    Steps: Y = A Omega; V = qr(Y) (+ q power iterations); B = V^T A;
+    Steps: Y = A Omega; V an orthonormal basis of range(Y) (+ q power iterations); B = V^T A;
     pivoted QLP of B (d = 0) or CPQR + d inner QRs (d >= 1); Q = V QB, P = PB."""
     A = np.asarray(A, dtype=np.float64)
     Omega = np.asarray(Omega, dtype=np.float64)
@@ -159,7 +159,7 @@ def brqlp(A: np.ndarray, Omega: np.ndarray, k: int, p: int, b: int, q: int = 0,
           deflate: bool = True, piv0: Optional[Sequence[int]] = None,
           piv1: Optional[Sequence[int]] = None) -> QLPResult:
     """Block randomized QLP.  Blocks of b columns of Omega (the last one ragged
-    when b does not divide l).  Per block j: Y_j = A Omega_j, V_j = qr(Y_j)
+    when b does not divide l).  Per block j: Y_j = A Omega_j, V_j orthonormal with range Y_j
     (+ q power iterations on the original A), V_j re-orthogonalised against
     V_1..V_{j-1} (twice), B_j = V_j^T A^(j-1), A^(j) = A^(j-1) - V_j B_j,
     pivoted QLP of B_j, Q_j = V_j QB_j, P_j = PB_j; T = blkdiag(L_j).

@@ -388,7 +388,7 @@ def sketch_encoded(E: Encoded, X, Y=None, work=None):
 
 
 def orthonormalize(Y, want_r: bool = False):
-    """[V, R] = qr(Y) by CholeskyQR2 through ``rqlp_orthonormalize`` (FP64)."""
+    """Y = V R with V orthonormal, R upper triangular, by CholeskyQR2 through ``rqlp_orthonormalize`` (FP64)."""
     torch = _torch()
     Y = colmajor(Y)
     m, c = Y.shape

@@ -242,7 +242,7 @@ void carve_small(Arena& ar, int64_t n, int64_t l, int64_t cp_rows, std::initiali
     f->info = ar.take<int32_t>(1);
 }
 
-// Algorithm 2.1 steps 5-6 (d = 0) or Algorithm 2.2 steps 5-8 (d >= 1) on
+// Pivoted QLP of the reduced matrix, Algorithm 2.1 (d = 0) or Algorithm 2.2 (d >= 1), on
 // the l x n matrix f.B: first CPQR B Pi0 = Q0 R0, then the second
 // factorisation of R0^T.  Writes T (l x l, triangle *tri), P_B (n x l, FP64,
 // into Pd) and returns Q_B (l x l, FP64) in *QB; B = Q_B T P_B^T.
@@ -394,7 +394,7 @@ struct BcgsScratch {
     size_t ws_elems;
 };
 
-// Block classical Gram-Schmidt (step 5 of Algorithm 4.1) over the rows x l
+// Block classical Gram-Schmidt (the reorthogonalisation of Algorithm 4.1) over the rows x l
 // panel V whose first bs-column block is already orthonormal: every later
 // block V_j is projected against the earlier blocks,
 // V_j <- V_j - V_{<j} (V_{<j}^T V_j), and orthonormalised in place by one
@@ -595,8 +595,8 @@ Arena arena_for(void* work, size_t bytes) {
     return Arena(work ? (void*)al : nullptr, bytes > lost ? bytes - lost : 0);
 }
 
-// FP64 range finder (Algorithm 2.1 steps 1-3 with q subspace iterations) and
-// projection B = V^T A (step 4).  Returns V (m x l) in *Vout.
+// FP64 range finder of Algorithm 2.1 (with q subspace iterations) and the
+// projection B = V^T A.  Returns V (m x l) in *Vout.
 int range_and_project_f64(Ctx& cx, RangeBufs64& r, SmallBufs& f, const double* A, int64_t lda, int64_t m, int64_t n,
                           int64_t l, int q, uint64_t seed, const double* Om, int64_t ldom, double** Vout, int64_t bs,
                           BcgsScratch& bc) {
@@ -810,7 +810,7 @@ int factor_core(const void* A, int64_t lda, int64_t m, int64_t n, int64_t l, int
         if (piv0) RQLP_TRY(copy_i64(l, f.piv0, piv0, s));
         if (piv1) RQLP_TRY(copy_i64(l, d == 0 ? f.piv1 : nullptr, piv1, s));
     } else if (bqlp_supported(n, le, bs)) {
-        // Algorithm 4.1 steps 6-7 for all blocks at once (batched kernels)
+        // the block rows B_j and their QLPs (Algorithm 4.1) for all blocks at once (batched kernels)
         if (f64)
             RQLP_TRY(bqlp<double>(f.B, l, n, le, bs, Lay.bq, f.Z, V64, m, m, (double*)Q, ldq, Pd, ldpd, T, ldt,
                                   f.piv0, f.piv1, inf, s));
@@ -820,7 +820,7 @@ int factor_core(const void* A, int64_t lda, int64_t m, int64_t n, int64_t l, int
         if (piv0) RQLP_TRY(copy_i64(le, f.piv0, piv0, s));
         if (piv1) RQLP_TRY(copy_i64(le, f.piv1, piv1, s));
     } else {
-        // Algorithm 4.1 steps 6-7, block by block: B_j = V_j^T A is block row j
+        // Algorithm 4.1 block by block: B_j = V_j^T A is block row j
         // of B; pivoted QLP of B_j; Q_j = V_j Q_B(j), P_j = P_B(j); T = blkdiag(L_j)
         RQLP_TRY(set_identity(le, T, ldt, s));
         for (int64_t s0 = 0; s0 < le; s0 += bs) {

@@ -3,7 +3,7 @@
 // range finder with q subspace iterations).
 //
 // The forward is recomputed from A and Omega (nothing is stored between the
-// calls): Y0 = A Omega, V0 = qr(Y0), W_i = qr(A^T V_{i-1}), V_i = qr(A W_i),
+// calls): Y0 = A Omega, V0 = orth(Y0), W_i = orth(A^T V_{i-1}), V_i = orth(A W_i),
 // B = V_q^T A, then with the frozen pivots X1 = B(:, piv0) = Q0 R01 (square
 // QR), R0^T = B^T Q0 (original column order) and R0^T(:, piv1) = Q1 L^T.
 // Every QR is CholeskyQR (two FP64 passes, or FP32 shifted CholeskyQR3 for

@@ -28,10 +28,11 @@
 //   3. bqlp_small_kernel, one wave per block: the pivoted QR of the bj x bj
 //      factor Rt_j, Rt_j Pi1_j = Qhat_j L_j^T.  A pivoted QR is unchanged by
 //      an orthogonal factor on the left, so Pi1_j and L_j are those of the
-//      pivoted QR of R0_j^T (Algorithm 2.1 step 6); the kernel writes L_j
-//      into T, forms Qhat_j, and Q_B^(j) = Q0_j Pi1_j from the reflectors of
-//      step 1.
-//   4. bd_rmul_kernel: P_j = Qt_j Qhat_j and Q_j = V_j Q_B^(j) (step 7).
+//      pivoted QR of R0_j^T (the second factorisation of Algorithm 2.1); the
+//      kernel writes L_j into T, forms Qhat_j, and Q_B^(j) = Q0_j Pi1_j from
+//      the reflectors of stage 1.
+//   4. bd_rmul_kernel: P_j = Qt_j Qhat_j and Q_j = V_j Q_B^(j) (the assembly
+//      of Algorithm 4.1).
 // Pivot rule, sign convention (diag(R) >= 0, Parlett's form of the reflector)
 // and numerical-rank stop (largest residual <= max(rows, cols) eps ||M||_F)
 // are those of the single-matrix CPQR.
@@ -367,7 +368,8 @@ __global__ __launch_bounds__(256) void bd_gram_kernel(const double* __restrict__
 // L_j; rt_mode 2: RT_j <- RT_j Lprev_j L_j; the rows of RT_j at and past
 // rank[blk] are zeroed (the completed columns).  Outputs per block (64 x 64):
 // Lout column-major, Linv row-major.
-__global__ __launch_bounds__(256) void bd_chol_kernel(const double* __restrict__ part, int nch, int l, int bs,
+constexpr int BDC_T = 512;
+__global__ __launch_bounds__(BDC_T) void bd_chol_kernel(const double* __restrict__ part, int nch, int l, int bs,
                                                       double shift_scale, double pivot_rel, double* Lout,
                                                       double* Linv, const double* Lprev, double* RT, int rt_mode,
                                                       const int* rank, int32_t* shifted, int shifted_mode,
@@ -380,52 +382,113 @@ __global__ __launch_bounds__(256) void bd_chol_kernel(const double* __restrict__
     __shared__ double a[64 * LA];        // a[i * LA + k] = L(i, k)
     __shared__ double w[64 * LA];        // inverse, then products
     __shared__ double s_shift;
-    __shared__ int s_fail;
     const double* Pb = part + (size_t)blk * nch * BQ_SQ;
+    // Thread (q = tid / 8, r = tid % 8) holds rows i = 8 r + e (e < 8) of
+    // column q of the matrix being reduced (x) and of X = L^{-1} (y), in
+    // registers.  Step j: the owner group of column j puts it (unscaled) in
+    // LDS, one barrier, then every thread applies the trailing update
+    // A(i, q) -= c_i c_q / d (q > j, c = column j, d = c_j) and the
+    // Gauss-Jordan step of L X = I: X(j, :) /= sqrt(d), X(i, :) -= (c_i / d)
+    // X(j, :) for i > j (row j of X comes from the same group by a shuffle).
+    // Row and column conditions are multipliers, not selects.  The columns
+    // of L are scaled by 1 / sqrt of their pivots at the end.
+    __shared__ double col[2][64];        // column of the step, by step parity
+    __shared__ double gdiag[64];         // diagonal of G (pivot test, trace)
+    const int q = tid >> 3, r = tid & 7, i0 = 8 * r;
+    double x[8], y[8];
+    double dq = 1.0;                     // pivot of step q
     int used_shift = 0;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        // G_j (lower triangle) from the partials, in chunk order; padding rows / columns -> identity
-        for (int idx = tid; idx < 64 * 64; idx += 256) {
-            const int i = idx & 63, k = idx >> 6;
-            double v = 0.0;
-            if (i < bj && k < bj && k <= i)
-                for (int ch = 0; ch < nch; ++ch) v += Pb[(size_t)ch * BQ_SQ + i + BQ_LD * k];
-            if (i >= bj || k >= bj) v = (i == k) ? 1.0 : 0.0;
-            a[i * LA + k] = v;
-            if (k <= i) w[i * LA + k] = v;               // original G for the pivot test
+    bool ok = false;
+    for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
+        // G_j from the partials, summed in chunk order (eight chunks in
+        // flight): element (i, k) = (tid % 64, tid / 64 + 8 f) so that a wave
+        // reads one contiguous column per load, then through LDS into the
+        // register layout
+        {
+            double g[8];
+#pragma unroll
+            for (int f = 0; f < 8; ++f) g[f] = 0.0;
+            const int gi = tid & 63, gk0 = tid >> 6;
+            for (int ch = 0; ch < nch; ch += 8) {
+                double t[8][8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+#pragma unroll
+                    for (int f = 0; f < 8; ++f) {
+                        const int gk = gk0 + 8 * f;
+                        t[c][f] = (ch + c < nch && gk <= gi)
+                                      ? Pb[(size_t)(ch + c) * BQ_SQ + gi + BQ_LD * gk] : 0.0;
+                    }
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+#pragma unroll
+                    for (int f = 0; f < 8; ++f) g[f] += t[c][f];
+            }
+#pragma unroll
+            for (int f = 0; f < 8; ++f) a[gi * LA + gk0 + 8 * f] = g[f];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = a[(i0 + e) * LA + q];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int i = i0 + e;
+            if (i >= bj || q >= bj) x[e] = (i == q) ? 1.0 : 0.0;
+            else if (i < q) x[e] = 0.0;
+            if (i == q) gdiag[q] = x[e];
+            y[e] = (i == q) ? 1.0 : 0.0;
         }
         __syncthreads();
         if (tid == 0) {
             double tr = 0.0;
-            for (int i = 0; i < bj; ++i) tr += a[i * LA + i];
+            for (int i = 0; i < bj; ++i) tr += gdiag[i];
             s_shift = shift_scale * tr;
-            s_fail = 0;
         }
         __syncthreads();
-        if (attempt == 1)
-            for (int i = tid; i < bj; i += 256) a[i * LA + i] += s_shift;
+        if (attempt == 1 && q < bj) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (i0 + e == q) x[e] += s_shift;
+        }
         const double prel = attempt == 0 ? pivot_rel : 0.0;
-        for (int j = 0; j < bj; ++j) {
-            __syncthreads();
-            const double d = a[j * LA + j];
-            if (!(d > prel * w[j * LA + j]) || !(d > 0.0)) {
-                if (tid == 0) s_fail = 1;
-                break;                                   // every thread reads the same d
-            }
-            const double ljj = sqrt(d);
-            __syncthreads();
-            for (int i = j + 1 + tid; i < bj; i += 256) a[i * LA + j] /= ljj;
-            if (tid == 0) a[j * LA + j] = ljj;
-            __syncthreads();
-            const int t = bj - j - 1;
-            for (int idx = tid; idx < t * t; idx += 256) {
-                const int i = j + 1 + idx / t, k = j + 1 + idx % t;
-                if (k <= i) a[i * LA + k] -= a[i * LA + j] * a[k * LA + j];
+        bool fail = false;
+        for (int jj = 0; jj < 8; ++jj) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int j = 8 * jj + u;
+                if (fail) continue;                          // (uniform: every thread read the same d)
+                double* cb = col[j & 1];
+                if (q == j) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) cb[i0 + e] = x[e];
+                }
+                RQLP_LDS_BARRIER();
+                const double d = cb[j];
+                if (!(d > prel * gdiag[j]) || !(d > 0.0)) {
+                    fail = true;
+                    continue;
+                }
+                // 1 / sqrt(d): hardware estimate and two Newton steps; 1 / d = its square
+                double rs = __builtin_amdgcn_rsq(d);
+                rs = rs * (1.5 - 0.5 * d * rs * rs);
+                rs = rs * (1.5 - 0.5 * d * rs * rs);
+                const double rd = rs * rs;
+                if (q == j) dq = d;
+                const double cq = (q > j) ? cb[q] * rd : 0.0;         // trailing columns only
+                const double xj = __shfl(y[u], (tid & ~7) + jj, RQLP_WAVE);   // X(j, q)
+                const double xr = xj * rd;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const double c = cb[i0 + e];
+                    x[e] -= c * cq;
+                    y[e] -= (c * ((i0 + e > j) ? xr : 0.0));
+                }
+                if (r == jj) y[u] = xj * rs;                  // row j of X
             }
         }
-        __syncthreads();
-        if (!s_fail) break;
-        if (attempt == 0) {
+        if (!fail) {
+            ok = true;
+        } else if (attempt == 0) {
             used_shift = 1;
         } else if (tid == 0 && info) {
             atomicOr(info, RQLP_INFO_CHOL_FAILED);
@@ -437,60 +500,65 @@ __global__ __launch_bounds__(256) void bd_chol_kernel(const double* __restrict__
         else if (used_shift) shifted[blk] = 1;
         if (used_shift && info) atomicOr(info, RQLP_INFO_CHOLQR_SHIFTED);
     }
-    // strict upper triangle -> 0
-    for (int idx = tid; idx < 64 * 64; idx += 256) {
-        const int i = idx & 63, k = idx >> 6;
-        if (k > i) a[i * LA + k] = 0.0;
-    }
-    __syncthreads();
-    // L^{-1} by forward substitution, thread k owns column k
-    if (tid < 64) {
-        const int k = tid;
-        for (int i = 0; i < 64; ++i) {
-            double v = 0.0;
-            if (i >= k) {
-                double s = (i == k) ? 1.0 : 0.0;
-                for (int t = k; t < i; ++t) s -= a[i * LA + t] * w[t * LA + k];
-                v = s / a[i * LA + i];
-            }
-            w[i * LA + k] = v;
+    // L (column q scaled by 1 / sqrt(pivot q), zero above the diagonal) and
+    // L^{-1} into LDS for the outputs and the products below
+    {
+        double rsq = __builtin_amdgcn_rsq(dq);
+        rsq = rsq * (1.5 - 0.5 * dq * rsq * rsq);
+        rsq = rsq * (1.5 - 0.5 * dq * rsq * rsq);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int i = i0 + e;
+            a[i * LA + q] = (i >= q) ? x[e] * rsq : 0.0;
+            w[i * LA + q] = y[e];
         }
     }
     __syncthreads();
     double* Lo = Lout + (size_t)blk * BQ_SQ;
     double* Li = Linv + (size_t)blk * BQ_SQ;
-    for (int idx = tid; idx < 64 * 64; idx += 256) {
+    for (int idx = tid; idx < 64 * 64; idx += BDC_T) {
         const int i = idx & 63, k = idx >> 6;
         Lo[i + BQ_LD * k] = a[i * LA + k];
         Li[i * BQ_LD + k] = w[i * LA + k];               // row-major (uniform reads of the update)
     }
     if (rt_mode == 0) return;
-    __syncthreads();
-    // M = Lprev L (lower) into w, then RT = M or RT <- RT M
+    // M = Lprev L (lower) into w, then RT = M or RT <- RT M; the global
+    // operand of each product is staged in LDS (stg) first
+    __shared__ double stg[64 * LA];
     const double* Lp = Lprev + (size_t)blk * BQ_SQ;
-    for (int idx = tid; idx < 64 * 64; idx += 256) {
+    for (int idx = tid; idx < 64 * 64; idx += BDC_T) {
+        const int i = idx & 63, t = idx >> 6;
+        stg[i * LA + t] = Lp[i + BQ_LD * t];
+    }
+    __syncthreads();
+    for (int idx = tid; idx < 64 * 64; idx += BDC_T) {
         const int i = idx & 63, k = idx >> 6;
         double v = 0.0;
-        for (int t = k; t <= i; ++t) v += Lp[i + BQ_LD * t] * a[t * LA + k];
+        for (int t = k; t <= i; ++t) v += stg[i * LA + t] * a[t * LA + k];
         w[i * LA + k] = (k <= i) ? v : 0.0;
     }
     __syncthreads();
     double* R = RT + (size_t)blk * BQ_SQ;
     const int rk = rank[blk];
     if (rt_mode == 2) {
-        for (int idx = tid; idx < 64 * 64; idx += 256) {
+        for (int idx = tid; idx < 64 * 64; idx += BDC_T) {
+            const int i = idx & 63, t = idx >> 6;
+            stg[i * LA + t] = R[i + BQ_LD * t];
+        }
+        __syncthreads();
+        for (int idx = tid; idx < 64 * 64; idx += BDC_T) {
             const int i = idx & 63, k = idx >> 6;
             double v = 0.0;
-            for (int t = k; t <= i; ++t) v += R[i + BQ_LD * t] * w[t * LA + k];
+            for (int t = k; t <= i; ++t) v += stg[i * LA + t] * w[t * LA + k];
             a[i * LA + k] = (k <= i) ? v : 0.0;
         }
         __syncthreads();
-        for (int idx = tid; idx < 64 * 64; idx += 256) {
+        for (int idx = tid; idx < 64 * 64; idx += BDC_T) {
             const int i = idx & 63, k = idx >> 6;
             R[i + BQ_LD * k] = (i >= rk || i >= bj || k >= bj) ? 0.0 : a[i * LA + k];
         }
     } else {
-        for (int idx = tid; idx < 64 * 64; idx += 256) {
+        for (int idx = tid; idx < 64 * 64; idx += BDC_T) {
             const int i = idx & 63, k = idx >> 6;
             R[i + BQ_LD * k] = (i >= rk || i >= bj || k >= bj) ? 0.0 : w[i * LA + k];
         }
@@ -782,7 +850,7 @@ int bqlp(const double* B, int64_t ldb, int64_t n, int64_t l, int64_t bs, const B
         double* Lp = sc.Ls + (size_t)pass * nb * BQ_SQ;
         const double* Lprev = (pass == 1) ? sc.Ls : (pass == 3 ? sc.Ls + (size_t)2 * nb * BQ_SQ : nullptr);
         const int rt_mode = pass == 1 ? 1 : (pass == 3 ? 2 : 0);
-        hipLaunchKernelGGL(bd_chol_kernel, dim3(nb), dim3(256), 0, s, sc.part, nch, l_i, bs_i, shift,
+        hipLaunchKernelGGL(bd_chol_kernel, dim3(nb), dim3(BDC_T), 0, s, sc.part, nch, l_i, bs_i, shift,
                            pass == 0 ? 1e-12 : 0.0, Lp, sc.Linv, Lprev, sc.RT, rt_mode, sc.rank, sc.shifted,
                            pass == 0 ? 1 : 2, gate, info);
         if (rc == 16) hipLaunchKernelGGL(bd_trmm_kernel<16>, pgrid, dim3(256), 0, s, Z, n, n_i, l_i, bs_i, sc.Linv, gate);

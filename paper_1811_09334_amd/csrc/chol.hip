@@ -1,5 +1,5 @@
-// Cholesky factor and its inverse for CholeskyQR (the "[V, ~] = qr(Y)" step of
-// the range finder, Algorithm 2.1 step 3, and the inner QR steps of
+// Cholesky factor and its inverse for CholeskyQR (the orthonormalisation of
+// the range finder in Algorithm 2.1, and the inner QR steps of
 // Algorithm 2.2, realised as CholeskyQR2: Fukaya, Nakatsukasa, Yanagisawa,
 // Yamamoto 2014; shifted retry per Fukaya, Kannan, Nakatsukasa, Zhang,
 // Yamamoto 2020).

@@ -1,6 +1,6 @@
 // Cholesky factor and inverse of a c x c Gram matrix (c <= 512) on many
-// workgroups: the orthonormalisation step of CholeskyQR ("[V, ~] = qr(Y)",
-// Algorithm 2.1 step 3, and the inner QR steps of Algorithm 2.2).
+// workgroups: the Cholesky step of CholeskyQR (the orthonormalisation of the
+// range finder in Algorithm 2.1, and the inner QR steps of Algorithm 2.2).
 //
 // Workgroup J owns block column J (16 columns) of both the factor L and of
 // X = L^{-1}, rows 16 J .. c-1, in LDS for the whole factorisation.  The

@@ -1,6 +1,6 @@
 // The two products of one CholeskyQR pass on a tall panel X (R x c,
 // column-major, c <= 512), the orthonormalisation of the range finder
-// (Algorithm 2.1 step 3 and the inner QR steps of Algorithm 2.2):
+// (Algorithm 2.1, and the inner QR steps of Algorithm 2.2):
 //   G = X^T X       Gram matrix, lower triangle only
 //   Y = X L^{-T}    update with the inverse Cholesky factor (L^{-1} lower
 //                   triangular, so Y(i, j) = sum_{k <= j} X(i, k) L^{-1}(j, k))

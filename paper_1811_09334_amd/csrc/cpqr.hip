@@ -1,6 +1,6 @@
-// Column-pivoted Householder QR of the reduced matrix (Algorithm 2.1 step 5,
-// Algorithm 2.2 step 5; CPQR as defined in Section 1) and of the small l x l
-// factor of the second stage (Algorithm 2.1 step 6).
+// Column-pivoted Householder QR of the reduced matrix (the first CPQR of
+// Algorithms 2.1 and 2.2; CPQR as defined in Section 1) and of the small l x l
+// factor of the second stage (the pivoted second factorisation of Algorithm 2.1).
 //
 // Design: the matrix is distributed by columns over G co-resident workgroups
 // (a grid no larger than the device holds at once), each holding its columns in LDS for the whole

@@ -1,6 +1,6 @@
 // Skinny dense products of the range finder and the projection:
-//   Y = A * X          (sketch, Algorithm 2.1 step 2; subspace iteration)
-//   Z = A^T * V        (subspace iteration; B^T = A^T V, Algorithm 2.1 step 4)
+//   Y = A * X          (sketch of Algorithm 2.1; subspace iteration)
+//   Z = A^T * V        (subspace iteration; the projection B^T = A^T V of Algorithm 2.1)
 //   G = X^T * X        (Gram matrix of CholeskyQR)
 //   Y = X * L^{-T}     (CholeskyQR update, B transposed), Q = V Q_B (assembly)
 // in FP64 or FP32 on the gfx950 matrix cores (v_mfma_f64_16x16x4f64 /

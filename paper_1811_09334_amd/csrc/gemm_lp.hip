@@ -1,5 +1,5 @@
 // 16-bit skinny products of the mixed-precision range finder and projection:
-//   Y = A W   and   Z = A^T V   (Algorithm 2.1 steps 2 and 4, and the
+//   Y = A W   and   Z = A^T V   (the sketch and the projection of Algorithm 2.1, and the
 // subspace iterations), with A, W, V rounded to bfloat16 or IEEE half and
 // FP32 accumulation on the gfx950 matrix cores (v_mfma_f32_16x16x32_bf16 /
 // _f16).  The split form ("bf16x3") keeps x = hi + lo in two bfloat16 parts
