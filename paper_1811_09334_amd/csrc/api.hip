@@ -64,8 +64,9 @@ constexpr double kPivotRel = 1e-12;
 constexpr double kZeroCol2 = 1e-12;
 
 // CholeskyQR of the rows x c panel held in buf0 (leading dimension ld):
-// passes of G = X^T X, G = L L^T, X <- X L^{-T}.  Returns the buffer holding
-// the orthonormal result (buf0 or buf1; buf0 is overwritten).  RT (c x c,
+// passes of G = X^T X, G = L L^T, X <- X L^{-T}, in place when the update
+// kernel takes the panel.  Returns the buffer holding the orthonormal result
+// (buf0 or buf1; buf0 is overwritten).  RT (c x c,
 // optional) receives R^T = L1 L2 ... (lower triangular), where X_in = V R
 // with diag(R) >= 0.
 // final == true (a basis that is returned): CholeskyQR2, plus two more passes
@@ -86,8 +87,11 @@ constexpr double kZeroCol2 = 1e-12;
 // second only when the first needed the shifted retry.
 int cholqr2(Ctx& cx, int64_t rows, int64_t c, double* buf0, double* buf1, int64_t ld, double* RT,
             double** out, bool final = true, int64_t col0 = 0) {
+    // in place (the result stays in buf0) when the update kernel takes the
+    // panel, which may write its own input; else the passes alternate buffers
+    const bool inplace = trmm_fits<double>(rows, c, buf0, ld, buf0, ld);
     double* cur = buf0;
-    double* nxt = buf1;
+    double* nxt = inplace ? buf0 : buf1;
     const int npass = final ? 4 : 2;
     double* Ls[4] = {cx.o.L1, cx.o.L2, cx.o.L1, cx.o.L2};
     for (int pass = 0; pass < npass; ++pass) {
@@ -104,13 +108,16 @@ int cholqr2(Ctx& cx, int64_t rows, int64_t c, double* buf0, double* buf1, int64_
         // shifted word: written by the first pass, only ever set by the later ones
         RQLP_TRY(chol_inv<double>(c, cx.o.G, c, Lp, cx.o.Li, nullptr, c, shift_scale(rows, c), cx.info, cx.s,
                                   gate, cx.shifted, cx.o.sync, pass == 0 ? 1 : 2, pass == 0 ? kPivotRel : 0.0));
-        // a skipped second pass of an intermediate basis copies X through (static result buffer)
+        // a skipped second pass of an intermediate basis copies X through (static
+        // result buffer), unless the passes run in place
         RQLP_TRY(gemm<double>(false, true, rows, c, c, cur, ld, cx.o.Li, c, nxt, ld, false, 1.0, 0.0, cx.gws,
-                              cx.gws_elems, cx.s, gate, final ? 1 : 2, 2));
+                              cx.gws_elems, cx.s, gate, (final || inplace) ? 1 : 2, 2));
         if (pass == 0) RQLP_TRY(complete_columns(rows, c, nxt, ld, cx.o.L1, c, kZeroCol2, cx.shifted, cx.s, col0));
-        double* t = cur;
-        cur = nxt;
-        nxt = t;
+        if (!inplace) {
+            double* t = cur;
+            cur = nxt;
+            nxt = t;
+        }
     }
     if (RT) {
         if (!final) {
@@ -149,17 +156,21 @@ struct Ctx32 {
 // iteration, which only has to span range(X) and be well conditioned) and
 // the rest only when a Cholesky of an earlier pass needed the shifted retry
 // (device word cx.shifted, set by any such pass and never cleared by a later
-// one).  A skipped pass forms no Gram; the result is always in buf1: for the
-// final basis the skipped third pass copies X through, and for an
-// intermediate basis the two conditional passes run or are skipped together
-// (the second runs only when the word is set, and then the third does too),
-// so their updates are simply left out when skipped.
+// one).  A skipped pass forms no Gram.  The passes run in place when the
+// update kernel takes the panel (result in buf0); otherwise they alternate
+// buffers and the result is always in buf1: for the final basis the skipped
+// third pass copies X through, and for an intermediate basis the two
+// conditional passes run or are skipped together (the second runs only when
+// the word is set, and then the third does too), so their updates are simply
+// left out when skipped.
 int cholqr_f32(Ctx32& cx, int64_t rows, int64_t c, float* buf0, float* buf1, int64_t ld, float** out,
                bool final = true) {
+    // in place (result in buf0) when the update kernel takes the panel
+    const bool inplace = trmm_fits<float>(rows, c, buf0, ld, buf0, ld);
     float* cur = buf0;
-    float* nxt = buf1;
+    float* nxt = inplace ? buf0 : buf1;
     const int always = final ? 2 : 1;
-    const int skip_mode = final ? 2 : 1;          // gemm gate modes: 2 copy op(A), 1 skip
+    const int skip_mode = (final && !inplace) ? 2 : 1;   // gemm gate modes: 2 copy op(A), 1 skip
     for (int pass = 0; pass < 3; ++pass) {
         const int32_t* gate = pass >= always ? cx.shifted : nullptr;
         RQLP_TRY(gemm<float>(true, false, c, c, rows, cur, ld, cur, ld, cx.G, c, false, 1.0f, 0.0f, cx.ws,
@@ -168,9 +179,11 @@ int cholqr_f32(Ctx32& cx, int64_t rows, int64_t c, float* buf0, float* buf1, int
                                  gate, pass < 2 ? cx.shifted : nullptr, cx.sync, pass == 0 ? 1 : 2));
         RQLP_TRY(gemm<float>(false, true, rows, c, c, cur, ld, cx.Li, c, nxt, ld, false, 1.0f, 0.0f, cx.ws,
                              cx.ws_elems, cx.s, gate, skip_mode, 2));
-        float* t = cur;
-        cur = nxt;
-        nxt = t;
+        if (!inplace) {
+            float* t = cur;
+            cur = nxt;
+            nxt = t;
+        }
     }
     *out = cur;
     return 0;

@@ -231,8 +231,8 @@ constexpr int TR_THREADS = 256;
 // nothing is computed, or with gate_copy the rows of X are copied to Y.
 template <typename T, int MAXB>
 __global__ __launch_bounds__(TR_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void trmm_kernel(
-    int64_t R, int c, const T* __restrict__ X, int64_t ldx, const T* __restrict__ Li, int64_t ldl,
-    T* __restrict__ Y, int64_t ldy, const int32_t* __restrict__ gate, int gate_copy) {
+    int64_t R, int c, const T* X, int64_t ldx, const T* __restrict__ Li, int64_t ldl,
+    T* Y, int64_t ldy, const int32_t* __restrict__ gate, int gate_copy) {
     typedef CqMfma<T> Mm;
     typedef typename Mm::acc_t acc_t;
     typedef typename Mm::vec_t vec_t;
@@ -433,8 +433,10 @@ bool trmm_fits(int64_t R, int64_t c, const T* X, int64_t ldx, const T* Y, int64_
     // FP64 beyond 28 column blocks would spill (eight blocks per wave)
     const int64_t cmax = sizeof(T) == 8 ? 448 : CQ_MAXC;
     // a workgroup per 16 VEC rows: below 16 workgroups the general product is faster
+    // (Y may be X itself: a workgroup reads all of its rows into LDS, waits
+    // for every copy, and only then writes those same rows)
     return c >= 1 && c <= cmax && R >= 16 * 16 * VEC && R % VEC == 0 && ldx % VEC == 0 && ldy % VEC == 0 &&
-           aligned16(X) && aligned16(Y) && (const void*)X != (const void*)Y;
+           aligned16(X) && aligned16(Y) && (X != Y || ldx == ldy);
 }
 
 template <typename T>

@@ -407,6 +407,8 @@ static int gemm_impl(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const TI
                 return trmm_lt<T>(M, N, A, lda, B, ldb, C, ldc, s, gate, gate_mode);
         }
     }
+    // the general kernels read A and B while other workgroups write C: no aliasing
+    if ((const void*)C == (const void*)A || (const void*)C == (const void*)B) return RQLP_E_UNSUPPORTED;
     GemmPlan p = plan_gemm(M, N, K);
     // one K split: the product kernel applies alpha and beta itself
     const bool direct = (p.S == 1 && !trans_out);
