@@ -53,7 +53,11 @@ struct Mfma<float> {
     static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-constexpr int GEMM_BK = 16;        // K depth of one LDS stage (two stages resident)
+constexpr int GEMM_BK = 16;        // K depth of one LDS stage (two stages resident), FP64
+// FP32 stages are twice as deep: the next stage's loads are issued one stage
+// ahead, and a 16-deep FP32 stage computes for less than a memory round trip
+template <typename T>
+constexpr int gemm_bk() { return sizeof(T) == 4 ? 2 * GEMM_BK : GEMM_BK; }
 constexpr int GEMM_MAX_NB = 7;     // at most 7 blocks of 16 columns per tile: 3 workgroups per CU
 constexpr int GEMM_THREADS = 256;
 
@@ -300,7 +304,7 @@ struct GemmPlan {
     int64_t kchunk;
 };
 
-GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K) {
+GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K, int bk = GEMM_BK) {
     GemmPlan p;
     int64_t nblk = ceil_div(N, 16);
     int64_t ntiles = ceil_div(nblk, GEMM_MAX_NB);
@@ -319,10 +323,10 @@ GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K) {
     if (S < 1) S = 1;
     if (K <= 0) {
         p.S = 1;
-        p.kchunk = GEMM_BK;
+        p.kchunk = bk;
         return p;
     }
-    p.kchunk = ceil_div(ceil_div(K, S), GEMM_BK) * GEMM_BK;
+    p.kchunk = ceil_div(ceil_div(K, S), bk) * bk;
     p.S = ceil_div(K, p.kchunk);
     if (p.S < 1) p.S = 1;
     return p;
@@ -336,11 +340,11 @@ void launch_nb(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const TI* A, 
     // (the alpha / beta epilogue is a variant of its own: keeping it out of the
     // plain product leaves that kernel's register count, hence its occupancy, alone)
     if (alpha == T(1) && beta == T(0))
-        hipLaunchKernelGGL((gemm_skinny_kernel<T, TA, TB, 1, NB, GEMM_BK, TI, TC, false>), grid, dim3(GEMM_THREADS),
+        hipLaunchKernelGGL((gemm_skinny_kernel<T, TA, TB, 1, NB, gemm_bk<T>(), TI, TC, false>), grid, dim3(GEMM_THREADS),
                            0, s, M, N, K, A, lda, B, ldb, C, ldc, split_stride, p.kchunk, gate, gate_copy, tri, alpha,
                            beta);
     else
-        hipLaunchKernelGGL((gemm_skinny_kernel<T, TA, TB, 1, NB, GEMM_BK, TI, TC, true>), grid, dim3(GEMM_THREADS),
+        hipLaunchKernelGGL((gemm_skinny_kernel<T, TA, TB, 1, NB, gemm_bk<T>(), TI, TC, true>), grid, dim3(GEMM_THREADS),
                            0, s, M, N, K, A, lda, B, ldb, C, ldc, split_stride, p.kchunk, gate, gate_copy, tri, alpha,
                            beta);
 }
@@ -364,6 +368,8 @@ void launch_dispatch(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const T
 }  // namespace
 
 size_t gemm_workspace_elems(int64_t M, int64_t N, int64_t K) {
+    // (the 16-deep plan: deeper stages only round the split size up, so they
+    // never need more partial sums)
     GemmPlan p = plan_gemm(M, N, K);
     size_t e = (size_t)(p.S * M * N);
     if (M == N) {                                    // a Gram matrix may take the CholeskyQR kernel
@@ -409,7 +415,7 @@ static int gemm_impl(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const TI
     }
     // the general kernels read A and B while other workgroups write C: no aliasing
     if ((const void*)C == (const void*)A || (const void*)C == (const void*)B) return RQLP_E_UNSUPPORTED;
-    GemmPlan p = plan_gemm(M, N, K);
+    GemmPlan p = plan_gemm(M, N, K, gemm_bk<T>());
     // one K split: the product kernel applies alpha and beta itself
     const bool direct = (p.S == 1 && !trans_out);
     // the gated copy (gate_mode 2) writes op(A) straight into C: only for a
