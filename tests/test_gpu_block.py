@@ -23,11 +23,15 @@ def _check_blocks(P, l, b, tol):
         assert np.abs(Pj.T @ Pj - np.eye(Pj.shape[1])).max() < tol
 
 
+@pytest.mark.timeout(300)
 @pytest.mark.parametrize("m,n,k,p,b,q", [
     (600, 300, 40, 8, 16, 0),      # 3 blocks of 16
     (600, 300, 40, 10, 16, 1),     # ragged last block (50 = 3 x 16 + 2)
     (1000, 500, 120, 8, 64, 1),    # 2 blocks of 64
     (777, 333, 30, 5, 64, 0),      # b >= l: one block (plain RQLP)
+    # l = 520: the FP64 orthonormalisation runs in column blocks of 448 and 72
+    # (block Gram-Schmidt over two blocks, the last one ragged)
+    (2400, 1200, 500, 20, 64, 1),
 ])
 def test_block_rqlp_f64_matches_oracle(gpu, m, n, k, p, b, q):
     l = k + p
@@ -75,6 +79,34 @@ def test_block_rqlp_mixed_scaled_workload(gpu, kind):
     assert rel.max() < (1e-6 if kind == "f32" else 1e-3)
     Q = to_np(f.Q).astype(np.float64)
     assert np.abs(Q.T @ Q - np.eye(l)).max() < 1e-4
+    _check_blocks(to_np(f.P).astype(np.float64), l, b, 1e-5)
+
+
+@pytest.mark.timeout(300)
+def test_block_rqlp_f32_two_orthonormalisation_blocks(gpu):
+    """FP32 block RQLP with l = 632: the panels are orthonormalised in column
+    blocks of 512 and 120 (block Gram-Schmidt, CholeskyQR in place);
+    frozen-pivot L-values against the FP64 oracle within the norm-wise FP32
+    scale max_j |L_jj - L_jj(ref)| <= 4 sqrt(l) u32 L_11(ref) (rounding of
+    FP32 products and orthonormalisation is absolute, of size u ||A||; it
+    is about 1e-6 relative at the tail L-values, 0.036 L_11, here), Q and
+    every block of P orthonormal to FP32 accuracy."""
+    import torch
+    m, n, k, p, b, q = 4096, 2048, 600, 32, 64, 1
+    l = k + p
+    A = inputs.svd_matrix(m, n, inputs.spectrum_exp(n, l / 3.5), 1013).astype(np.float32)
+    Om = inputs.gaussian(n, l, 2013).astype(np.float32).astype(np.float64)
+    f = gpu.factor(to_dev(A, torch.float32), k, p, q=q, b=b, precision="f32", Omega=to_dev(Om, torch.float32))
+    piv0, piv1, lv = to_np(f.piv0), to_np(f.piv1), to_np(f.lvals)
+    assert int(to_np(f.info)[0]) == 0
+    frozen = brqlp(A.astype(np.float64), Om, k, p, b, q=q, deflate=False, piv0=piv0, piv1=piv1)
+    err = np.abs(lv[:k] - frozen.lvals[:k])
+    u32 = 2.0 ** -24
+    print(f"[block f32 l={l}] max rel {np.max(err / frozen.lvals[:k]):.2e}, "
+          f"norm-wise {err.max() / frozen.lvals[0]:.2e} (bar {4 * np.sqrt(l) * u32:.2e})")
+    assert err.max() <= 4 * np.sqrt(l) * u32 * frozen.lvals[0]
+    Q = to_np(f.Q).astype(np.float64)
+    assert np.abs(Q.T @ Q - np.eye(l)).max() < 1e-5
     _check_blocks(to_np(f.P).astype(np.float64), l, b, 1e-5)
 
 
