@@ -47,6 +47,29 @@ def flop_model(m, n, l, q):
     return 2.0 * (2 * q + 2) * m * n * l + (2 * q + 1) * 4.0 * m * l * l + 6.0 * n * l * l + 2.0 * m * l * l
 
 
+def bound_ms(w):
+    """Lower-bound time of one factorisation: the larger of (a) the flop
+    model above with the 2q+2 passes over A at the MFMA peak of the product
+    arithmetic and the rest (orthonormalisations, CPQR, second stage,
+    assembly) at the MFMA peak of the arithmetic it runs in (FP64 for the
+    FP64 path, FP32 otherwise: the FP64 small stages of the mixed paths are
+    a lower-order term), and (b) the bytes of A over HBM bandwidth: 2q+2
+    reads of A in the product's element size, plus, for the 16-bit paths,
+    one read of the stored FP32 A and the write of its two tiled copies."""
+    gemm = 2.0 * (2 * w.q + 2) * w.m * w.n * w.l
+    rest = flop_model(w.m, w.n, w.l, w.q) - gemm
+    prod = {"bf16x3": "bf16"}.get(w.precision, w.precision)
+    tail = "f64" if w.precision == "f64" else "f32"
+    t_flop = (gemm / PEAK[prod] + rest / PEAK[tail]) * 1e-9
+    mn = float(w.m) * w.n
+    if w.precision in ("f64", "f32"):
+        nbytes = (2 * w.q + 2) * (8 if w.precision == "f64" else 4) * mn
+    else:
+        e = 4 if w.precision == "bf16x3" else 2       # bytes per element of the encoded A
+        nbytes = 4 * mn + 2 * e * mn + (2 * w.q + 2) * e * mn
+    return max(t_flop, nbytes / HBM_PEAK_GBS * 1e-6)
+
+
 def parse_args():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,16 +200,23 @@ def lval_vs(f, ref, w):
     out = {"first_pivot_divergence_vs_f64": int(d[0]) if d.size else -1,
            "lval_rel_err_vs_f64": float(np.max(np.abs(lv[:k] - lr[:k]) / lr[:k]))}
     if w.kind == "svd":
-        sig = w.spectrum_values()[:k]
-        out["lval_err_vs_spectrum"] = float(np.max(np.abs(sig - np.abs(lv[:k])) / sig))
-        out["lval_err_vs_spectrum_f64"] = float(np.max(np.abs(sig - np.abs(lr[:k])) / sig))
+        out["lval_err_vs_spectrum"] = spectrum_distance(f, w)
+        out["lval_err_vs_spectrum_f64"] = spectrum_distance(ref, w)
     return out
+
+
+def spectrum_distance(f, w):
+    """max_{j < k} |sigma_j - |L_jj|| / sigma_j for a matrix built from a
+    prescribed spectrum."""
+    sig = w.spectrum_values()[: w.k]
+    lv = f.lvals.cpu().numpy()[: w.k]
+    return float(np.max(np.abs(sig - np.abs(lv)) / sig))
 
 
 def lval_text(r):
     t = (f"free L-value rel err vs f64 {r['lval_rel_err_vs_f64']:.2e}, first pivot divergence at step "
          f"{r['first_pivot_divergence_vs_f64']}")
-    if "lval_err_vs_spectrum" in r:
+    if "lval_err_vs_spectrum_f64" in r:
         t += (f"; distance to the prescribed spectrum {r['lval_err_vs_spectrum']:.2e} "
               f"(f64: {r['lval_err_vs_spectrum_f64']:.2e})")
     return t
@@ -196,7 +226,11 @@ def other_workloads(rq, inputs, dev):
     """Short timings (3 steps after 1 warm-up) of the other workloads of the
     hot path, each on its own synthetic matrix: FP64 ERQLP (20000 x 10000),
     block RQLP in FP16 (65536 x 8192, b = 64) and the FP32 forward + backward
-    of the differentiable workload (16384 x 4096)."""
+    of the differentiable workload (16384 x 4096).  Each record carries the
+    lower-bound time of ``bound_ms`` and its fraction of the measured time,
+    and an accuracy field: the distance of the L-values to the prescribed
+    spectrum (FP64 path), or the L-values against one FP64 factorisation of
+    the same matrix and Omega (the other paths)."""
     import torch
     out = {}
     for name in ("erqlp_f64_20000x10000", "brqlp_fp16_65536x8192", "drqlp_f32_16384x4096"):
@@ -207,10 +241,14 @@ def other_workloads(rq, inputs, dev):
         ms, f = timed(lambda: rq.factor(A, w.k, w.p, q=w.q, d=w.d, b=w.b, precision=w.precision, seed=w.seed_omega,
                                         work=work), 3, 1)
         F = flop_model(w.m, w.n, w.l, w.q)
+        lb = bound_ms(w)
         rec = {"ms_per_step": round(ms, 3), "tflops": round(F / (ms * 1e-3) / 1e12, 3), "precision": w.precision,
-               "m": w.m, "n": w.n, "k": w.k, "p": w.p, "q": w.q, "d": w.d, "b": w.b, "info": int(f.info.item())}
-        if w.precision in ("bf16", "fp16", "bf16x3"):
-            # accuracy of the 16-bit products: one FP64 factorisation of the same matrix and Omega
+               "m": w.m, "n": w.n, "k": w.k, "p": w.p, "q": w.q, "d": w.d, "b": w.b, "info": int(f.info.item()),
+               "bound_ms": round(lb, 3), "bound_frac": round(lb / ms, 4)}
+        if w.precision == "f64" and w.kind == "svd":
+            rec["lval_err_vs_spectrum"] = spectrum_distance(f, w)
+        elif w.precision != "f64":
+            # accuracy of the reduced-precision arithmetic: one FP64 factorisation of the same matrix and Omega
             del work
             A64 = rq.empty_colmajor(w.m, w.n, torch.float64, dev)
             A64.copy_(A)
@@ -232,9 +270,12 @@ def other_workloads(rq, inputs, dev):
             rec["backward_ms"] = round(msb, 3)
             del bw
         out[name] = rec
-        print(f"# {name}: {ms:.3f} ms/step" + (f", backward {rec['backward_ms']:.3f} ms" if "backward_ms" in rec
-                                               else "")
-              + (f"; {lval_text(rec)}" if "lval_rel_err_vs_f64" in rec else ""), file=sys.stderr, flush=True)
+        acc = (lval_text(rec) if "lval_rel_err_vs_f64" in rec else
+               f"distance to the prescribed spectrum {rec['lval_err_vs_spectrum']:.2e}"
+               if "lval_err_vs_spectrum" in rec else "")
+        print(f"# {name}: {ms:.3f} ms/step ({lb / ms:.0%} of the {lb:.2f} ms bound)"
+              + (f", backward {rec['backward_ms']:.3f} ms" if "backward_ms" in rec else "")
+              + (f"; {acc}" if acc else ""), file=sys.stderr, flush=True)
         del A, work, f
         torch.cuda.empty_cache()
     return out
@@ -486,10 +527,14 @@ def main():
         "config": {"workload": w.name, "m": w.m, "n": w.n, "k": w.k, "p": w.p, "q": w.q, "d": w.d, "b": w.b,
                    "precision": w.precision,
                    "arithmetic": ("16-bit MFMA products with FP32 accumulation, FP32 CholeskyQR2, FP64 CPQR / "
-                                  "second factorisation / L") if mixed else "FP64 throughout",
+                                  "second factorisation / L") if mixed else
+                                 ("FP32 products and CholeskyQR, FP64 CPQR / second factorisation / L"
+                                  if w.precision == "f32" else "FP64 throughout"),
                    "input": "gaussian" if args.gaussian_input else "prescribed spectrum"},
         "factorizations_per_s": round(1e3 / ms, 3),
         "flops_per_step": F,
+        "bound_ms": round(bound_ms(w), 4),
+        "bound_frac": round(bound_ms(w) / ms, 4),
         "info": info,
         "fp64_same_matrix": fp64,
         "speedup_vs_fp64": round(fp64["ms_per_step"] / ms, 3) if fp64 else None,

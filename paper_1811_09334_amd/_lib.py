@@ -73,6 +73,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} not found: build it first (python -m paper_1811_09334_amd.build_lib)")
+    # torch first, so that the library binds to the HIP runtime torch has
+    # already brought into the process (the one that owns the tensors it is
+    # given): loaded before torch, a factorisation returned RQLP_E_UNSUPPORTED
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <stdio.h>
+#include <stdlib.h>
 
 #include "../../include/rqlp.h"
 
@@ -23,10 +25,25 @@ namespace rqlp {
         if (_e != hipSuccess) return RQLP_E_HIP;             \
     } while (0)
 
-#define RQLP_TRY(expr)                                       \
-    do {                                                     \
-        int _s = (expr);                                     \
-        if (_s != 0) return _s;                              \
+// With the environment variable RQLP_TRACE set (to anything but "0"), every
+// non-zero status passed up through RQLP_TRY is printed to stderr with its
+// call site, so the chain from the failing call to the entry point is named.
+inline bool trace_errors() {
+    static const bool on = [] {
+        const char* v = getenv("RQLP_TRACE");
+        return v != nullptr && v[0] != '\0' && !(v[0] == '0' && v[1] == '\0');
+    }();
+    return on;
+}
+
+#define RQLP_TRY(expr)                                                                       \
+    do {                                                                                     \
+        int _s = (expr);                                                                     \
+        if (_s != 0) {                                                                       \
+            if (::rqlp::trace_errors())                                                      \
+                fprintf(stderr, "rqlp: %s:%d: %s returned %d\n", __FILE__, __LINE__, #expr, _s); \
+            return _s;                                                                       \
+        }                                                                                    \
     } while (0)
 
 static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
