@@ -81,6 +81,7 @@ __global__ __launch_bounds__(BQ_T, 3) void bcpqr_kernel(
     double* frop, double* candcol, unsigned long long* gwords, int64_t* piv0, double* Vh0, double* beta0,
     double* Rt, int64_t ldrt, int* rank_out, int32_t* info, unsigned long long spin_limit) {
     __shared__ double vsh[RB];                           // the step's scaled reflector
+    __shared__ double colsh[RB];                         // this workgroup's candidate column
     __shared__ double s_red[BQ_T / 64];
     __shared__ unsigned long long s_kred[2][BQ_T / 64];
     __shared__ double s_beta, s_mu, s_tol2;
@@ -137,18 +138,29 @@ __global__ __launch_bounds__(BQ_T, 3) void bcpqr_kernel(
             lk0 = s_kred[0][w] > lk0 ? s_kred[0][w] : lk0;
             lk1 = s_kred[1][w] > lk1 ? s_kred[1][w] : lk1;
         }
-        // ---- publish the best column, then the keys; the last workgroup decides ----
-        if (lk0 != 0 && !stopped && c == (int)key_index(lk0, ibits)) {
-            double* dst = candcol + (((size_t)blk * 2 + (j & 1)) * G + g) * RB;
+        // ---- publish the best column, then the keys; the last workgroup decides.
+        // The owner thread hands its column to LDS; wave 0 stores it with one
+        // coalesced store (lane r: row r), waits for it and stores the keys,
+        // so only that wave waits for the memory round trip ----
+        const bool pub = lk0 != 0 && !stopped;           // the same in every thread
+        if (pub) {
+            if (c == (int)key_index(lk0, ibits)) {
 #pragma unroll
-            for (int r = 0; r < RB; ++r)
-                if (r >= j && r < bj) st_coherent(dst + r, x[r]);
+                for (int r = 0; r < RB; ++r) colsh[r] = x[r];
+            }
+            RQLP_LDS_BARRIER();
         }
-        drain_and_sync();                                // the column stores are complete
         unsigned long long* ks = keys + ((size_t)blk * bs + j) * G * 2;
-        if (tid == 0) {
-            __hip_atomic_store(ks + 2 * g, lk0 | kTag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(ks + 2 * g + 1, lk1 | kTag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (wave == 0) {
+            if (pub) {
+                double* dst = candcol + (((size_t)blk * 2 + (j & 1)) * G + g) * RB;
+                if (lane < RB && lane >= j && lane < bj) st_coherent(dst + lane, colsh[lane]);
+                __builtin_amdgcn_s_waitcnt(0);           // the column store is complete
+            }
+            if (lane == 0) {
+                __hip_atomic_store(ks + 2 * g, lk0 | kTag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(ks + 2 * g + 1, lk1 | kTag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
         if (g == G - 1) {
             if (wave == 0) {
@@ -275,21 +287,30 @@ __global__ __launch_bounds__(BQ_T, 3) void bcpqr_kernel(
             }
         } else if (!now_stopped && act == -1) {
             // ---- apply H = I - b v v^T (v = 0 above row j), exact residual norm ----
-            // (the reflector is read from LDS again for the update: an opaque
-            // zero offset keeps the compiler from holding all RB entries in
-            // registers next to the column)
+            // (chunks of 8 rows wholly above row j are skipped: a uniform
+            // branch; the reflector is read from LDS again for the update: an
+            // opaque zero offset keeps the compiler from holding all RB entries
+            // in registers next to the column)
             double dot = 0.0;
 #pragma unroll
-            for (int r = 0; r < RB; ++r) dot += vsh[r] * x[r];
+            for (int r0 = 0; r0 < RB; r0 += 8)
+                if (r0 + 8 > j) {
+#pragma unroll
+                    for (int r = r0; r < r0 + 8; ++r) dot += vsh[r] * x[r];
+                }
             const double w = b * dot;
             int off = 0;
             asm volatile("" : "+v"(off));
             double sn = 0.0;
 #pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                x[r] -= w * vsh[r + off];
-                sn += (r > j) ? x[r] * x[r] : 0.0;
-            }
+            for (int r0 = 0; r0 < RB; r0 += 8)
+                if (r0 + 8 > j) {
+#pragma unroll
+                    for (int r = r0; r < r0 + 8; ++r) {
+                        x[r] -= w * vsh[r + off];
+                        sn += (r > j) ? x[r] * x[r] : 0.0;
+                    }
+                }
             nrm2 = sn;
         }
         RQLP_LDS_BARRIER();
@@ -655,8 +676,9 @@ __global__ __launch_bounds__(64) void bqlp_small_kernel(const double* __restrict
                 for (int r = 0; r < 64; ++r) vcol[r] = (r >= j) ? x[r] : 0.0;
             }
             __syncthreads();
-            double sigma = 0.0;
-            for (int r = j + 1; r < bj; ++r) sigma += vcol[r] * vcol[r];
+            // sigma: lane r squares row r, one wave reduction (rows past bj are 0)
+            const double vl = vcol[lane];
+            const double sigma = wave_sum(lane > j ? vl * vl : 0.0);
             double mu, rv0;
             reflector(vcol[j], sigma, mu, b, rv0);
             V[j * LV + lane] = (lane > j) ? vcol[lane] * rv0 : (lane == j ? 1.0 : 0.0);
