@@ -48,16 +48,20 @@ __device__ __forceinline__ double mw_readlane(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// One wave, registers only: lane (i = lane % 16, g = lane / 16) holds
-// d[e] = D(i, 4 g + e) of the 16 x 16 block (lower triangle read).  On
-// return d holds the Cholesky factor L (zero above the diagonal) and x its
-// inverse X = L^{-1} (zero above the diagonal).  Returns true when a pivot
-// was non-positive or not finite (it is then replaced by 1).  Each column
-// step broadcasts the pivot with a read-lane and gathers L(i, j), L(k, j)
-// with lane shuffles.  The row sweep of L X = I runs in the same loop: its
-// step j needs only L(i, j) and 1 / L(j, j) from the factor's step j, so the
-// two dependency chains overlap.
-__device__ bool mw_factor_diag(double d[4], double x[4], double thr, int lane) {
+// One wave: lane (i = lane % 16, g = lane / 16) holds d[e] = D(i, 4 g + e)
+// of the 16 x 16 block (lower triangle read).  On return d holds the
+// Cholesky factor L (zero above the diagonal) and x its inverse X = L^{-1}
+// (zero above the diagonal).  Returns true when a pivot was non-positive or
+// not finite (it is then replaced by 1).  Each column step broadcasts the
+// pivot with a read-lane; the lanes holding column j of L write it to the
+// LDS scratch sc (16 doubles), the lanes holding row j of X write that row
+// (sc + 16, 16 doubles), and every lane reads back L(i, j), L(4 g .. 4 g + 3,
+// j) and X(j, 4 g .. 4 g + 3): one LDS round trip per step (the LDS
+// operations of one wave complete in order, so the reads see the writes and
+// the next step's writes come after this step's reads).  The row sweep of
+// L X = I runs in the same loop: its step j needs only L(i, j) and
+// 1 / L(j, j) from the factor's step j, so the two dependency chains overlap.
+__device__ bool mw_factor_diag(double d[4], double x[4], double thr, int lane, double* sc) {
     const int i = lane & 15, g = lane >> 4;
     bool bad = false;
 #pragma unroll
@@ -74,29 +78,58 @@ __device__ bool mw_factor_diag(double d[4], double x[4], double thr, int lane) {
         double rinv = __builtin_amdgcn_rsq(p);
         rinv = rinv * (1.5 - 0.5 * p * rinv * rinv);
         const double lj = p * rinv;
-        if (g == gj) d[ej] = (i == j) ? lj : (i > j ? d[ej] * rinv : 0.0);
-        // column j is read from the lanes of group gj, which the update below
-        // leaves alone; a copy keeps the shuffles independent of that update
-        const double colj = d[ej];
-        const double lij = __shfl(colj, i + 16 * gj, 64);          // L(i, j)
-        double lkj[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) lkj[e] = __shfl(colj, 4 * g + e + 16 * gj, 64);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            if (4 * g + e > j) d[e] -= lij * lkj[e];
+        if (g == gj) {
+            d[ej] = (i == j) ? lj : (i > j ? d[ej] * rinv : 0.0);
+            sc[i] = d[ej];                                   // L(i, j)
+        }
         // row sweep of L X = I: X(j, :) /= L(j, j), then X(i, :) -= L(i, j) X(j, :) below
         if (i == j) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) x[e] *= rinv;
+            for (int e = 0; e < 4; ++e) {
+                x[e] *= rinv;
+                sc[16 + 4 * g + e] = x[e];                   // X(j, 4 g + e)
+            }
         }
+        __builtin_amdgcn_wave_barrier();
+        const double lij = sc[i];
+        double lkj[4], xt[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const double xt = __shfl(x[e], j + 16 * g, 64);
-            if (i > j) x[e] -= lij * xt;
+            lkj[e] = sc[4 * g + e];
+            xt[e] = sc[16 + 4 * g + e];
         }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (4 * g + e > j) d[e] -= lij * lkj[e];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (i > j) x[e] -= lij * xt[e];
     }
     return bad;
+}
+
+// The diagonal-block factorisation of one wave as a function of its own: D
+// from W (LDS, row stride MW_S) is replaced by its factor L, and L^{-1} goes
+// to Dv.  Row i's pivot threshold is pivot_rel G(i, i) (gd: the diagonal of
+// G, rows past nvalid: 0) when use_thr is set, else 0.  Not inlined: inside
+// the kernel the column loop shared the kernel's scalar registers and
+// reloaded spilled ones at every step.
+__device__ __noinline__ int mw_factor_block(double* W, double* Dv, double* sc, const double* gd, int use_thr,
+                                            double pivot_rel, int nvalid) {
+    const int lane = threadIdx.x & 63;
+    const int i = lane & 15, g = lane >> 4;
+    double d[4], x[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) d[e] = W[i * MW_S + 4 * g + e];
+    const double thr = (use_thr && i < nvalid) ? pivot_rel * gd[i] : 0.0;
+    const bool bad = mw_factor_diag(d, x, thr, lane, sc);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        W[i * MW_S + 4 * g + e] = d[e];
+        Dv[i * MW_S + 4 * g + e] = x[e];
+    }
+    return bad ? 1 : 0;
 }
 
 // gate_mode: 0 always run; 1 when *gate == 0 write identities and return
@@ -121,6 +154,8 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
     double* Xc = Wc + (size_t)nrt * 16 * MW_S;          // [16 nrt][MW_S]: X = L^{-1} (rows j0..)
     double* Dv = Xc + (size_t)nrt * 16 * MW_S;          // [16][MW_S]
     __shared__ double s_red[MW_NW];
+    __shared__ __attribute__((aligned(16))) double s_fd[32];   // column / row exchange of the diagonal factor
+    __shared__ double s_gd[16];                                // G(j0 + t, j0 + t): pivot thresholds
     __shared__ int s_bad;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int fr = lane & 15, fk = lane >> 4;
@@ -166,6 +201,7 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
             const int i = j0 + r;
             double w = 0.0;
             if (t < kb && i < c && r >= t) w = (double)G[i + (int64_t)(j0 + t) * ldg] + (r == t ? shift : 0.0);
+            if (r == t) s_gd[t] = (t < kb && i < c) ? (double)G[i + (int64_t)(j0 + t) * ldg] : 0.0;
             if (t >= kb && r == t) w = 1.0;                 // identity padding of a ragged last block
             Wc[r * MW_S + t] = w;
             Xc[r * MW_S + t] = (r == t) ? 1.0 : 0.0;
@@ -182,21 +218,12 @@ __global__ __launch_bounds__(MW_T) void chol_mw_kernel(int c, const TG* __restri
         // tile 0 of Wc, breakdown into s_bad.
         auto factor_diag = [&]() {
             if (wave == 0) {
-                const int i = lane & 15, g = lane >> 4;
-                double d[4], x[4];
-    #pragma unroll
-                for (int e = 0; e < 4; ++e) d[e] = Wc[i * MW_S + 4 * g + e];
                 // plain attempt: a pivot below pivot_rel times the column's squared
                 // norm marks a numerically dependent column (lane i: column j0 + i)
-                const double thr = (attempt == 0 && j0 + i < c)
-                                       ? pivot_rel * (double)G[(j0 + i) + (int64_t)(j0 + i) * ldg] : 0.0;
-                const bool bad = mw_factor_diag(d, x, thr, lane);
-    #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    Wc[i * MW_S + 4 * g + e] = d[e];
-                    Dv[i * MW_S + 4 * g + e] = x[e];
-                }
-                if (lane == 0) s_bad = bad ? 1 : 0;
+                // (G's diagonal was kept in LDS when the block column was loaded:
+                // a global load here would sit on the critical path of every step)
+                const int bad = mw_factor_block(Wc, Dv, s_fd, s_gd, attempt == 0, pivot_rel, c - j0);
+                if (lane == 0) s_bad = bad;
             }
         };
         // W(r0.., J) -= A B^T for one 16-row tile: a = L(rows, K), b = L(J, K)^T
