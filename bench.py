@@ -42,9 +42,12 @@ PMC_PROFILES = {   # dominant kernel -> committed PMC summary (HBM bytes per lau
 
 
 def flop_model(m, n, l, q):
-    """Useful flops of one factorisation: the 2q+2 passes over A, the 2q+1
-    orthonormalisations, CPQR + second stage + assembly (fixed model)."""
-    return 2.0 * (2 * q + 2) * m * n * l + (2 * q + 1) * 4.0 * m * l * l + 6.0 * n * l * l + 2.0 * m * l * l
+    """Useful flops of one factorisation: the 2q+2 passes over A, the
+    orthonormalisations (CholeskyQR2, 4 rows l^2 each) of the q+1 m x l
+    panels and the q n x l panels, CPQR + second stage + assembly (fixed
+    model)."""
+    return (2.0 * (2 * q + 2) * m * n * l + 4.0 * l * l * ((q + 1) * m + q * n) + 6.0 * n * l * l
+            + 2.0 * m * l * l)
 
 
 def bound_ms(w):
