@@ -451,7 +451,7 @@ int bcgs2(CtxT& cx, int64_t rows, int64_t l, int64_t bs, T* V, int64_t ld, BcgsS
 
 // Column block of the block orthonormalisation for the block size bs of
 // Algorithm 4.1: the largest multiple of bs that one CholeskyQR pass on the
-// matrix cores takes (448 FP64, 512 FP32 columns), or the whole panel.  Any
+// matrix cores takes (512 columns), or the whole panel.  Any
 // such blocking gives the same basis up to rounding: every form here is
 // triangular (column j of the result lies in the span of columns 0..j of the
 // input, with a positive diagonal), so the leading blocks of the range
@@ -460,7 +460,8 @@ int bcgs2(CtxT& cx, int64_t rows, int64_t l, int64_t bs, T* V, int64_t ld, BcgsS
 // Omega the block and unblocked range finders agree).  Wider blocks turn the
 // many narrow projections into a few wide products.
 int64_t ortho_block(int64_t bs, int64_t l, bool f64) {
-    const int64_t cap = f64 ? 448 : 512;
+    (void)f64;                                      // the same for FP64 and FP32
+    const int64_t cap = 512;
     if (bs <= 0 || bs >= l) return l;
     int64_t ob = bs <= cap ? (cap / bs) * bs : bs;
     return ob >= l ? l : ob;

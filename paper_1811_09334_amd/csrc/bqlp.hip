@@ -624,6 +624,15 @@ __global__ __launch_bounds__(256) void bd_trmm_kernel(double* __restrict__ Z, in
 // zeros above the diagonal), the pivots (0-based within the block), Qhat_j =
 // H_0 ... H_{bj-1} and Q_B^(j) = Q0_j Pi1_j (Q0_j from the reflectors Vh0 /
 // beta0 of the first CPQR).
+// sum_r v[r] x[r] over 64 rows as four interleaved partial sums (one wave
+// per block: a single 64-long chain of dependent FMAs would set the pace)
+__device__ __forceinline__ double dot64(const double* v, const double (&x)[64]) {
+    double d[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < 64; ++r) d[r & 3] += v[r] * x[r];
+    return (d[0] + d[1]) + (d[2] + d[3]);
+}
+
 __global__ __launch_bounds__(64) void bqlp_small_kernel(const double* __restrict__ RT, int l, int bs,
                                                         const double* __restrict__ Vh0,
                                                         const double* __restrict__ beta0, double* T, int64_t ldt,
@@ -689,10 +698,7 @@ __global__ __launch_bounds__(64) void bqlp_small_kernel(const double* __restrict
                 for (int r = 0; r < 64; ++r)
                     if (r >= j) x[r] = (r == j) ? mu : 0.0;
             } else if (act == -1) {
-                double dot = 0.0;
-#pragma unroll
-                for (int r = 0; r < 64; ++r) dot += V[j * LV + r] * x[r];
-                const double wv = b * dot;
+                const double wv = b * dot64(&V[j * LV], x);
                 double sn = 0.0;
 #pragma unroll
                 for (int r = 0; r < 64; ++r) {
@@ -723,10 +729,7 @@ __global__ __launch_bounds__(64) void bqlp_small_kernel(const double* __restrict
 #pragma unroll
     for (int r = 0; r < 64; ++r) y[r] = (r == lane) ? 1.0 : 0.0;
     for (int j = bj - 1; j >= 0; --j) {
-        double dot = 0.0;
-#pragma unroll
-        for (int r = 0; r < 64; ++r) dot += V[j * LV + r] * y[r];
-        const double wv = sbeta[j] * dot;
+        const double wv = sbeta[j] * dot64(&V[j * LV], y);
 #pragma unroll
         for (int r = 0; r < 64; ++r) y[r] -= wv * V[j * LV + r];
     }
@@ -745,10 +748,7 @@ __global__ __launch_bounds__(64) void bqlp_small_kernel(const double* __restrict
 #pragma unroll
     for (int r = 0; r < 64; ++r) y[r] = (r == u) ? 1.0 : 0.0;
     for (int j = bj - 1; j >= 0; --j) {
-        double dot = 0.0;
-#pragma unroll
-        for (int r = 0; r < 64; ++r) dot += V[j * LV + r] * y[r];
-        const double wv = sbeta[j] * dot;
+        const double wv = sbeta[j] * dot64(&V[j * LV], y);
 #pragma unroll
         for (int r = 0; r < 64; ++r) y[r] -= wv * V[j * LV + r];
     }

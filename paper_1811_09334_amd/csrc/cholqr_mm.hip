@@ -27,11 +27,13 @@
 // into LDS by the load unit (global_load_lds_dwordx4) GR_NBUF - 1 stages
 // ahead, in the layout the MFMA reads with one conflict-free 16-byte load.
 //
-// Update kernel: a workgroup of 4 waves owns 16 VEC rows of Y; the rows of X
-// (all 16 ceil(c / 16) columns) are copied into LDS once, then each wave
-// sweeps k for its column blocks (every fourth block, highest first, so that
+// Update kernel: a workgroup of 8 waves (two per SIMD: at c = 512 its LDS
+// slice leaves room for one workgroup per CU, and a single wave per SIMD
+// issued its MFMAs at half the peak rate) owns 16 VEC rows of Y; the rows of
+// X (all 16 ceil(c / 16) columns) are copied into LDS once, then each wave
+// sweeps k for its column blocks (every eighth block, highest first, so that
 // the triangular work is spread over the waves; odd workgroups mirror the
-// assignment so that the two workgroups on a CU load its four SIMDs evenly),
+// assignment so that consecutive workgroups load the SIMDs evenly),
 // with the L^{-1} values of the next 16 k prefetched into registers.
 #include "common.hpp"
 #include "kernels.hpp"
@@ -224,7 +226,8 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int c, int P, int S, c
     G[i + (int64_t)j * ldg] = v;
 }
 
-constexpr int TR_THREADS = 256;
+constexpr int TR_WAVES = 8;        // two waves per SIMD: one workgroup per CU fills the LDS
+constexpr int TR_THREADS = 64 * TR_WAVES;
 
 // Y = X L^{-T} for the 16 VEC rows of this workgroup; Li = L^{-1} (c x c lower
 // triangular, its strict upper part is not read).  gate: when *gate is 0
@@ -260,15 +263,15 @@ __global__ __launch_bounds__(TR_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
     {
         int64_t row = i0 + VEC * (lane & 15);
         if (row > R - VEC) row = R - VEC;
-        for (int q = wave; q < 4 * nb; q += 4) {
+        for (int q = wave; q < 4 * nb; q += TR_WAVES) {
             int col = 4 * q + (lane >> 4);
             if (col > c - 1) col = c - 1;
             __builtin_amdgcn_global_load_lds((const void*)(X + (int64_t)col * ldx + row), RQLP_LDS_PTR(Xs + q * 1024),
                                              16, 0, 0);
         }
     }
-    // column blocks of this wave: b_q = bmax - 4 q
-    const int wsel = (blockIdx.x & 1) ? 3 - wave : wave;
+    // column blocks of this wave: b_q = bmax - TR_WAVES q
+    const int wsel = (blockIdx.x & 1) ? TR_WAVES - 1 - wave : wave;
     const int bmax = nb - 1 - wsel;
     const int kend = (16 * bmax + 16 < c) ? 16 * bmax + 16 : c;
     const int ng = bmax >= 0 ? (kend + 15) >> 4 : 0;         // groups of 16 k
@@ -287,7 +290,7 @@ __global__ __launch_bounds__(TR_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
     auto load_b = [&](T (&bq)[MAXB][4], int g) {
 #pragma unroll
         for (int q = 0; q < MAXB; ++q) {
-            const int b = bmax - 4 * q;
+            const int b = bmax - TR_WAVES * q;
             const int j = 16 * b + (lane & 15);
             const int jc = j < 0 ? 0 : (j < c ? j : c - 1);
 #pragma unroll
@@ -305,7 +308,7 @@ __global__ __launch_bounds__(TR_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
             a[s] = *(const vec_t*)(Xs + (16 * g + 4 * (lane >> 4) + s) * 256 + 16 * (lane & 15));
 #pragma unroll
         for (int q = 0; q < MAXB; ++q) {
-            const int b = bmax - 4 * q;
+            const int b = bmax - TR_WAVES * q;
             if (b < g) continue;                             // block done: k past its last column
             const bool diag = b == g;
 #pragma unroll
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(TR_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
     // lane l holds rows i0 + VEC row(l, r) + t (t < VEC) of column 16 b_q + l % 16
 #pragma unroll
     for (int q = 0; q < MAXB; ++q) {
-        const int b = bmax - 4 * q;
+        const int b = bmax - TR_WAVES * q;
         const int j = 16 * b + (lane & 15);
         if (b < 0 || j >= c) continue;
 #pragma unroll
@@ -430,8 +433,7 @@ int gram(int64_t R, int64_t c, const T* X, int64_t ldx, T* G, int64_t ldg, T* ws
 template <typename T>
 bool trmm_fits(int64_t R, int64_t c, const T* X, int64_t ldx, const T* Y, int64_t ldy) {
     constexpr int VEC = CqMfma<T>::VEC;
-    // FP64 beyond 28 column blocks would spill (eight blocks per wave)
-    const int64_t cmax = sizeof(T) == 8 ? 448 : CQ_MAXC;
+    const int64_t cmax = CQ_MAXC;
     // a workgroup per 16 VEC rows: below 16 workgroups the general product is faster
     // (Y may be X itself: a workgroup reads all of its rows into LDS, waits
     // for every copy, and only then writes those same rows)
@@ -445,15 +447,11 @@ int trmm_lt(int64_t R, int64_t c, const T* X, int64_t ldx, const T* Li, int64_t 
     if (R <= 0 || c <= 0) return 0;
     if (!trmm_fits<T>(R, c, X, ldx, Y, ldy) || ldl < c || ldl > (1 << 20)) return RQLP_E_UNSUPPORTED;
     const int gc = gate_mode == 2 ? 1 : 0;
-    switch ((int)ceil_div(ceil_div(c, 16), 4)) {
+    switch ((int)ceil_div(ceil_div(c, 16), TR_WAVES)) {
         case 1: return launch_trmm<T, 1>(R, c, X, ldx, Li, ldl, Y, ldy, gate, gc, s);
         case 2: return launch_trmm<T, 2>(R, c, X, ldx, Li, ldl, Y, ldy, gate, gc, s);
         case 3: return launch_trmm<T, 3>(R, c, X, ldx, Li, ldl, Y, ldy, gate, gc, s);
-        case 4: return launch_trmm<T, 4>(R, c, X, ldx, Li, ldl, Y, ldy, gate, gc, s);
-        case 5: return launch_trmm<T, 5>(R, c, X, ldx, Li, ldl, Y, ldy, gate, gc, s);
-        case 6: return launch_trmm<T, 6>(R, c, X, ldx, Li, ldl, Y, ldy, gate, gc, s);
-        case 7: return launch_trmm<T, 7>(R, c, X, ldx, Li, ldl, Y, ldy, gate, gc, s);
-        default: return launch_trmm<T, 8>(R, c, X, ldx, Li, ldl, Y, ldy, gate, gc, s);
+        default: return launch_trmm<T, 4>(R, c, X, ldx, Li, ldl, Y, ldy, gate, gc, s);
     }
 }
 

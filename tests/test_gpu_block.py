@@ -29,8 +29,8 @@ def _check_blocks(P, l, b, tol):
     (600, 300, 40, 10, 16, 1),     # ragged last block (50 = 3 x 16 + 2)
     (1000, 500, 120, 8, 64, 1),    # 2 blocks of 64
     (777, 333, 30, 5, 64, 0),      # b >= l: one block (plain RQLP)
-    # l = 520: the FP64 orthonormalisation runs in column blocks of 448 and 72
-    # (block Gram-Schmidt over two blocks, the last one ragged)
+    # l = 520: the FP64 orthonormalisation runs in column blocks of 512 and 8
+    # (block Gram-Schmidt over two blocks, the last one narrower than a tile)
     (2400, 1200, 500, 20, 64, 1),
 ])
 def test_block_rqlp_f64_matches_oracle(gpu, m, n, k, p, b, q):
