@@ -23,7 +23,7 @@
 // Gram kernel: a workgroup of 8 waves owns a range of row fragments (K split
 // over workgroups, partial sums reduced in a fixed order by a second kernel
 // that also adds the last R mod 4 VEC rows) and a set of lower 16 x 16 blocks
-// of G (GR_BPW per wave).  Fragments of all needed column blocks are copied
+// of G (gr_bpw per wave).  Fragments of all needed column blocks are copied
 // into LDS by the load unit (global_load_lds_dwordx4) GR_NBUF - 1 stages
 // ahead, in the layout the MFMA reads with one conflict-free 16-byte load.
 //
@@ -72,7 +72,13 @@ struct CqMfma<double> {
 constexpr int GR_WAVES = 8;
 constexpr int GR_THREADS = 64 * GR_WAVES;
 constexpr int GR_NBUF = 4;          // LDS stages
-constexpr int GR_BPW = 10;          // lower 16 x 16 blocks of G per wave
+// lower 16 x 16 blocks of G per wave: 10, or for wide FP32 panels 17 (as
+// many as the registers of two waves per SIMD hold: every group of
+// workgroups re-reads the panel, and at c = 512 the 528 blocks make 4
+// groups instead of 7); narrower panels keep 10, which splits their blocks
+// evenly over the groups (at c = 272: 80 + 73 rather than 136 + 17)
+template <typename T>
+inline int gr_bpw(int64_t c) { return (sizeof(T) == 4 && c > 384) ? 17 : 10; }
 constexpr int GR_FRAG = 1024;       // bytes of one fragment (64 lanes x 16 bytes)
 constexpr int CQ_MAXC = 512;
 
@@ -87,7 +93,7 @@ __host__ __device__ inline void cq_pair(int p, int& bi, int& bj) {
 
 // Partial Gram blocks of the row fragments [f0, f1) of this workgroup:
 // ws[(split P + p) 256 + 4 lane + r] = accumulator r of lane l for pair p.
-template <typename T, int OPS>
+template <typename T, int OPS, int GR_BPW>
 __global__ __launch_bounds__(GR_THREADS) void gram_kernel(int c, const T* __restrict__ X, int64_t ldx, int64_t nfrag,
                                                           int64_t fper, int P, T* __restrict__ ws,
                                                           const int32_t* __restrict__ gate) {
@@ -357,11 +363,11 @@ struct GramPlan {
     int64_t nfrag, fper, S;
 };
 
-GramPlan plan_gram(int64_t R, int64_t c, int kf) {
+GramPlan plan_gram(int64_t R, int64_t c, int kf, int bpw) {
     GramPlan p;
     p.nb = (int)((c + 15) / 16);
     p.P = p.nb * (p.nb + 1) / 2;
-    p.groups = (int)ceil_div(p.P, GR_WAVES * GR_BPW);
+    p.groups = (int)ceil_div(p.P, GR_WAVES * bpw);
     p.ops = (int)ceil_div(p.nb, GR_WAVES);
     p.nfrag = R > 0 ? R / kf : 0;
     const int cus = device_info().num_cus > 0 ? device_info().num_cus : 256;
@@ -376,9 +382,9 @@ GramPlan plan_gram(int64_t R, int64_t c, int kf) {
     return p;
 }
 
-template <typename T, int OPS>
+template <typename T, int OPS, int BPW>
 void launch_gram(const GramPlan& p, int64_t c, const T* X, int64_t ldx, T* ws, const int32_t* gate, hipStream_t s) {
-    hipLaunchKernelGGL((gram_kernel<T, OPS>), dim3((unsigned)p.S, (unsigned)p.groups), dim3(GR_THREADS), 0, s,
+    hipLaunchKernelGGL((gram_kernel<T, OPS, BPW>), dim3((unsigned)p.S, (unsigned)p.groups), dim3(GR_THREADS), 0, s,
                        (int)c, X, ldx, p.nfrag, p.fper, p.P, ws, gate);
 }
 
@@ -398,15 +404,17 @@ inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 size_t gram_workspace_elems(int64_t R, int64_t c) {
     if (c <= 0 || c > CQ_MAXC) return 0;
-    const GramPlan p = plan_gram(R, c, 8);                   // FP64 fragments are the shorter: an upper bound
-    return (size_t)(p.S * p.P * 256);
+    // the larger of the FP64 and FP32 plans
+    const GramPlan p64 = plan_gram(R, c, 8, gr_bpw<double>(c)), p32 = plan_gram(R, c, 16, gr_bpw<float>(c));
+    const size_t e64 = (size_t)(p64.S * p64.P * 256), e32 = (size_t)(p32.S * p32.P * 256);
+    return e64 > e32 ? e64 : e32;
 }
 
 template <typename T>
 bool gram_fits(int64_t R, int64_t c, const T* X, int64_t ldx, const T* ws, size_t ws_elems) {
     constexpr int VEC = CqMfma<T>::VEC;
     if (c <= 0 || c > CQ_MAXC || R < 0 || !aligned16(X) || ldx % VEC != 0) return false;
-    const GramPlan p = plan_gram(R, c, 4 * VEC);
+    const GramPlan p = plan_gram(R, c, 4 * VEC, gr_bpw<T>(c));
     return p.S == 0 || (ws != nullptr && (size_t)(p.S * p.P * 256) <= ws_elems);
 }
 
@@ -416,13 +424,19 @@ int gram(int64_t R, int64_t c, const T* X, int64_t ldx, T* G, int64_t ldg, T* ws
     if (c <= 0) return 0;
     if (!gram_fits<T>(R, c, X, ldx, ws, ws_elems)) return RQLP_E_UNSUPPORTED;
     constexpr int KF = 4 * CqMfma<T>::VEC;
-    const GramPlan p = plan_gram(R, c, KF);
+    const int bpw = gr_bpw<T>(c);
+    const GramPlan p = plan_gram(R, c, KF, bpw);
     if (p.S > 0) {
-        switch (p.ops) {
-            case 1: launch_gram<T, 1>(p, c, X, ldx, ws, gate, s); break;
-            case 2: launch_gram<T, 2>(p, c, X, ldx, ws, gate, s); break;
-            case 3: launch_gram<T, 3>(p, c, X, ldx, ws, gate, s); break;
-            default: launch_gram<T, 4>(p, c, X, ldx, ws, gate, s); break;
+        if (bpw == 17) {
+            // (c > 384: four copy slots per wave)
+            if constexpr (sizeof(T) == 4) launch_gram<T, 4, 17>(p, c, X, ldx, ws, gate, s);
+        } else {
+            switch (p.ops) {
+                case 1: launch_gram<T, 1, 10>(p, c, X, ldx, ws, gate, s); break;
+                case 2: launch_gram<T, 2, 10>(p, c, X, ldx, ws, gate, s); break;
+                case 3: launch_gram<T, 3, 10>(p, c, X, ldx, ws, gate, s); break;
+                default: launch_gram<T, 4, 10>(p, c, X, ldx, ws, gate, s); break;
+            }
         }
     }
     hipLaunchKernelGGL((gram_reduce_kernel<T>), dim3((unsigned)(4 * p.P)), dim3(256), 0, s, (int)c, p.P, (int)p.S, ws,
