@@ -86,7 +86,7 @@ constexpr double kZeroCol2 = 1e-12;
 // only has to span range(X) and be well conditioned): one pass, and the
 // second only when the first needed the shifted retry.
 int cholqr2(Ctx& cx, int64_t rows, int64_t c, double* buf0, double* buf1, int64_t ld, double* RT,
-            double** out, bool final = true, int64_t col0 = 0) {
+            double** out, bool final = true, int64_t col0 = 0, bool reortho = false) {
     // in place (the result stays in buf0) when the update kernel takes the
     // panel, which may write its own input; else the passes alternate buffers
     const bool inplace = trmm_fits<double>(rows, c, buf0, ld, buf0, ld);
@@ -106,8 +106,12 @@ int cholqr2(Ctx& cx, int64_t rows, int64_t c, double* buf0, double* buf1, int64_
                               cx.gws_elems, cx.s, gate, 1, 1));
         double* Lp = Ls[pass];
         // shifted word: written by the first pass, only ever set by the later ones
+        // the second pass (and the first one after a reorthogonalising
+        // projection) sees a Gram matrix within rounding of the identity
+        const bool near_id = gate == nullptr && (pass == 1 || reortho);
         RQLP_TRY(chol_inv<double>(c, cx.o.G, c, Lp, cx.o.Li, nullptr, c, shift_scale(rows, c), cx.info, cx.s,
-                                  gate, cx.shifted, cx.o.sync, pass == 0 ? 1 : 2, pass == 0 ? kPivotRel : 0.0));
+                                  gate, cx.shifted, cx.o.sync, pass == 0 ? 1 : 2, pass == 0 ? kPivotRel : 0.0,
+                                  near_id));
         // a skipped second pass of an intermediate basis copies X through (static
         // result buffer), unless the passes run in place
         RQLP_TRY(gemm<double>(false, true, rows, c, c, cur, ld, cx.o.Li, c, nxt, ld, false, 1.0, 0.0, cx.gws,
@@ -164,7 +168,7 @@ struct Ctx32 {
 // the word is set, and then the third does too), so their updates are simply
 // left out when skipped.
 int cholqr_f32(Ctx32& cx, int64_t rows, int64_t c, float* buf0, float* buf1, int64_t ld, float** out,
-               bool final = true) {
+               bool final = true, bool reortho = false) {
     // in place (result in buf0) when the update kernel takes the panel
     const bool inplace = trmm_fits<float>(rows, c, buf0, ld, buf0, ld);
     float* cur = buf0;
@@ -175,8 +179,11 @@ int cholqr_f32(Ctx32& cx, int64_t rows, int64_t c, float* buf0, float* buf1, int
         const int32_t* gate = pass >= always ? cx.shifted : nullptr;
         RQLP_TRY(gemm<float>(true, false, c, c, rows, cur, ld, cur, ld, cx.G, c, false, 1.0f, 0.0f, cx.ws,
                              cx.ws_elems, cx.s, gate, 1, 1));
+        // the second pass (and the first one after a reorthogonalising
+        // projection) sees a Gram matrix within rounding of the identity
+        const bool near_id = gate == nullptr && (pass == 1 || reortho);
         RQLP_TRY(chol_inv<float>(c, cx.G, c, cx.L, cx.Lid, cx.Li, c, shift_scale32(rows, c), cx.info, cx.s,
-                                 gate, pass < 2 ? cx.shifted : nullptr, cx.sync, pass == 0 ? 1 : 2));
+                                 gate, pass < 2 ? cx.shifted : nullptr, cx.sync, pass == 0 ? 1 : 2, 0.0, near_id));
         RQLP_TRY(gemm<float>(false, true, rows, c, c, cur, ld, cx.Li, c, nxt, ld, false, 1.0f, 0.0f, cx.ws,
                              cx.ws_elems, cx.s, gate, skip_mode, 2));
         if (!inplace) {
@@ -437,10 +444,10 @@ int bcgs2(CtxT& cx, int64_t rows, int64_t l, int64_t bs, T* V, int64_t ld, BcgsS
             const bool full = pass == 1 && final && sizeof(T) == sizeof(double);
             T* o = nullptr;
             if constexpr (sizeof(T) == sizeof(double)) {
-                RQLP_TRY(cholqr2(cx, rows, bj, (double*)Vj, (double*)p1, ld, nullptr, (double**)&o, full, s0));
+                RQLP_TRY(cholqr2(cx, rows, bj, (double*)Vj, (double*)p1, ld, nullptr, (double**)&o, full, s0, pass == 1));
                 if ((void*)o != (void*)Vj) RQLP_TRY(copy_matrix(rows, bj, (const double*)o, ld, (double*)Vj, ld, s));
             } else {
-                RQLP_TRY(cholqr_f32(cx, rows, bj, (float*)Vj, (float*)p1, ld, (float**)&o, full));
+                RQLP_TRY(cholqr_f32(cx, rows, bj, (float*)Vj, (float*)p1, ld, (float**)&o, full, pass == 1));
                 if ((void*)o != (void*)Vj)
                     RQLP_TRY((cast_matrix<float, float>(rows, bj, (const float*)o, ld, (float*)Vj, ld, s)));
             }

@@ -308,11 +308,83 @@ __global__ __launch_bounds__(CH_T) void chol_inv_kernel(int c, const TG* __restr
             for (int i = lane; i < c; i += 64) Xf[i + (int64_t)j * ldw] = (float)X[i + (int64_t)j * ldw];
 }
 
+// ---------------------------------------------------------------------------
+// Near-identity form.  The second pass of CholeskyQR2 (and the CholeskyQR
+// after the second projection of block Gram-Schmidt) sees G = I + E with
+// ||E||_F around 1e-6 for FP32 panels and 1e-13 for FP64 ones.  Then
+// L = I + Phi(E) and L^{-1} = I - Phi(E), where Phi(E) is the strict lower
+// triangle of E plus half its diagonal, are exact to about 2 ||E||_F^2:
+// L L^T = I + E + Phi(E) Phi(E)^T, and (I + Phi(E)) (I - Phi(E)) =
+// I - Phi(E)^2.  The first kernel writes both and one partial sum of
+// ||E||_F^2 per 32 x 32 tile; the second sums the partials in a fixed order
+// and keeps the result when ||E||_F <= tau (2 tau^2 at most 1/16 of the unit
+// roundoff of G's arithmetic), else it sets the flag on which the full
+// factorisation then runs and overwrites every output.
+constexpr int NI_T = 256;
+
+template <typename TG>
+__global__ __launch_bounds__(NI_T) void nearid_kernel(int c, const TG* __restrict__ G, int64_t ldg,
+                                                      double* __restrict__ L, double* __restrict__ Linv,
+                                                      float* __restrict__ Linv32, int64_t ld,
+                                                      double* __restrict__ part) {
+    __shared__ double red[NI_T / 64];
+    const int nt = (c + 31) >> 5;
+    const int ti = (int)blockIdx.x % nt, tj = (int)blockIdx.x / nt;
+    double ss = 0.0;
+    for (int q = threadIdx.x; q < 1024; q += NI_T) {
+        const int i = 32 * ti + (q & 31), j = 32 * tj + (q >> 5);
+        if (i >= c || j >= c) continue;
+        double phi = 0.0;
+        if (i >= j) {                                   // (lower triangle of G read)
+            const double e = (double)G[i + (int64_t)j * ldg] - (i == j ? 1.0 : 0.0);
+            ss += (i == j) ? e * e : 2.0 * e * e;
+            phi = (i == j) ? 0.5 * e : e;
+        }
+        const double d = (i == j) ? 1.0 : 0.0;
+        const double li = d - phi;
+        L[i + (int64_t)j * ld] = d + phi;
+        Linv[i + (int64_t)j * ld] = li;
+        if (Linv32) Linv32[i + (int64_t)j * ld] = (float)li;
+    }
+    ss = wave_sum(ss);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(64) void nearid_decide_kernel(int nparts, const double* __restrict__ part, double tau2,
+                                                           int32_t* need_full, int32_t* shifted_out,
+                                                           int shifted_mode) {
+    double t = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += 64) t += part[k];
+    t = wave_sum(t);
+    if (threadIdx.x == 0) {
+        const bool ok = t <= tau2;                      // (NaN: the full factorisation)
+        *need_full = ok ? 0 : 1;
+        // the pass used no shift (the full factorisation writes the word itself)
+        if (ok && shifted_out && shifted_mode == 1) *shifted_out = 0;
+    }
+}
+
 template <typename TG>
 int chol_inv(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
              double shift_scale, int32_t* info, hipStream_t s, const int32_t* run_flag, int32_t* shifted_out,
-             unsigned* sync, int shifted_mode, double pivot_rel) {
+             unsigned* sync, int shifted_mode, double pivot_rel, bool near_identity) {
     if (c <= 0) return 0;
+    if (near_identity && sync && c <= CHOL_MW_MAXC && run_flag == nullptr) {
+        // tau: FP32 4e-5 (2 tau^2 = 3.2e-9 < 6e-8 / 16), FP64 1e-9 (2e-18 < 1.1e-16 / 16)
+        const double tau = sizeof(TG) == 4 ? 4e-5 : 1e-9;
+        const int nt = (int)((c + 31) / 32);
+        double* part = (double*)(sync + NEARID_PART_WORD);
+        int32_t* need = (int32_t*)(sync + NEARID_FLAG_WORD);
+        hipLaunchKernelGGL((nearid_kernel<TG>), dim3((unsigned)(nt * nt)), dim3(NI_T), 0, s, (int)c, G, ldg, L, Linv,
+                           Linv32, ld, part);
+        hipLaunchKernelGGL(nearid_decide_kernel, dim3(1), dim3(64), 0, s, nt * nt, (const double*)part, tau * tau,
+                           need, shifted_out, shifted_mode);
+        RQLP_HIP_TRY(hipGetLastError());
+        return chol_mw<TG>(c, G, ldg, L, Linv, Linv32, ld, shift_scale, info, sync, s, need, shifted_out,
+                           shifted_mode, pivot_rel, 2);
+    }
     if (sync && c <= CHOL_MW_MAXC)
         return chol_mw<TG>(c, G, ldg, L, Linv, Linv32, ld, shift_scale, info, sync, s, run_flag, shifted_out,
                            shifted_mode, pivot_rel);
@@ -323,8 +395,8 @@ int chol_inv(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float
     return hipGetLastError() == hipSuccess ? 0 : RQLP_E_HIP;
 }
 template int chol_inv<double>(int64_t, const double*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
-                              hipStream_t, const int32_t*, int32_t*, unsigned*, int, double);
+                              hipStream_t, const int32_t*, int32_t*, unsigned*, int, double, bool);
 template int chol_inv<float>(int64_t, const float*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
-                             hipStream_t, const int32_t*, int32_t*, unsigned*, int, double);
+                             hipStream_t, const int32_t*, int32_t*, unsigned*, int, double, bool);
 
 }  // namespace rqlp

@@ -509,7 +509,7 @@ size_t chol_mw_lds_bytes(int64_t c) {
 template <typename TG>
 int chol_mw(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
             double shift_scale, int32_t* info, unsigned* sync, hipStream_t s, const int32_t* run_flag,
-            int32_t* shifted_out, int shifted_mode, double pivot_rel) {
+            int32_t* shifted_out, int shifted_mode, double pivot_rel, int gate_mode) {
     // per-process start value, so that flag words left in reused memory by
     // another process are unlikely to match
     static std::atomic<unsigned> epoch_counter{(unsigned)(getpid() * 2654435761u) ^ (unsigned)time(nullptr)};
@@ -525,15 +525,15 @@ int chol_mw(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float*
     // is bounded.  (A cooperative launch gave the same residency but cost
     // ~15 us of idle device time before and ~10 us after each launch.)
     hipLaunchKernelGGL((chol_mw_kernel<TG>), dim3(NB), dim3(MW_T), (unsigned)lds, s, (int)c, G, ldg, shift_scale, L,
-                       Linv, Linv32, ld, info, sync, e0, retry, run_flag, run_flag ? 1 : 0, shifted_out,
-                       shifted_mode, pivot_rel);
+                       Linv, Linv32, ld, info, sync, e0, retry, run_flag,
+                       run_flag ? (gate_mode >= 0 ? gate_mode : 1) : 0, shifted_out, shifted_mode, pivot_rel);
     RQLP_HIP_TRY(hipGetLastError());
     return 0;
 }
 
 template int chol_mw<double>(int64_t, const double*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
-                             unsigned*, hipStream_t, const int32_t*, int32_t*, int, double);
+                             unsigned*, hipStream_t, const int32_t*, int32_t*, int, double, int);
 template int chol_mw<float>(int64_t, const float*, int64_t, double*, double*, float*, int64_t, double, int32_t*,
-                            unsigned*, hipStream_t, const int32_t*, int32_t*, int, double);
+                            unsigned*, hipStream_t, const int32_t*, int32_t*, int, double, int);
 
 }  // namespace rqlp

@@ -95,19 +95,28 @@ int cast_matrix(int64_t rows, int64_t cols, const S* src, int64_t lds, D* dst, i
 // pivot_rel: in the plain attempt a pivot <= pivot_rel * G(j, j) counts as a
 // breakdown (column j numerically dependent on the earlier ones).
 // sync: CHOL_SYNC_WORDS words of device scratch (flags of the multi-workgroup
-// kernel used for c <= CHOL_MW_MAXC); NULL selects the one-workgroup kernel.
+// kernel used for c <= CHOL_MW_MAXC, and the partial sums and flag of the
+// near-identity form); NULL selects the one-workgroup kernel.
+// near_identity (with sync, c <= CHOL_MW_MAXC and no run_flag): G is
+// expected within rounding of I (a second CholeskyQR pass); when
+// ||G - I||_F is small enough L and L^{-1} come from the first-order form,
+// else the factorisation runs as usual.
 constexpr int CHOL_MW_MAXC = 512;
-constexpr int CHOL_SYNC_WORDS = 128;
+constexpr int CHOL_SYNC_WORDS = 1024;
+constexpr int NEARID_PART_WORD = 128;   // 256 doubles of partial sums
+constexpr int NEARID_FLAG_WORD = 640;   // int32: 1 when the full factorisation must run
 size_t chol_inv_lds_bytes(int64_t c);
 template <typename TG>
 int chol_inv(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
              double shift_scale, int32_t* info, hipStream_t s, const int32_t* run_flag = nullptr,
              int32_t* shifted_out = nullptr, unsigned* sync = nullptr, int shifted_mode = 1,
-             double pivot_rel = 0.0);
+             double pivot_rel = 0.0, bool near_identity = false);
+// gate_mode: 1 (default with run_flag) writes identities when *run_flag is 0,
+// 2 returns without writing.
 template <typename TG>
 int chol_mw(int64_t c, const TG* G, int64_t ldg, double* L, double* Linv, float* Linv32, int64_t ld,
             double shift_scale, int32_t* info, unsigned* sync, hipStream_t s, const int32_t* run_flag,
-            int32_t* shifted_out, int shifted_mode, double pivot_rel);
+            int32_t* shifted_out, int shifted_mode, double pivot_rel, int gate_mode = -1);
 
 // --- cpqr.hip ---------------------------------------------------------------
 struct CpqrScratch {
