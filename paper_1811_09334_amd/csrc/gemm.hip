@@ -304,32 +304,83 @@ struct GemmPlan {
     int64_t kchunk;
 };
 
-GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K, int bk = GEMM_BK) {
-    GemmPlan p;
-    int64_t nblk = ceil_div(N, 16);
-    int64_t ntiles = ceil_div(nblk, GEMM_MAX_NB);
-    p.nb = (int)ceil_div(nblk, ntiles);
-    p.tm = ceil_div(M, 64);
-    p.tn = ceil_div(N, 16 * p.nb);
-    const int cus = device_info().num_cus > 0 ? device_info().num_cus : 256;
-    int64_t want = 6 * cus;              // two rounds of three resident workgroups per CU
-    int64_t S = ceil_div(want, p.tm * p.tn);
-    // K chunks of at least 256, and partial sums (S M N) of at most a quarter
-    // of the operands' volume K (M + N)
+// 16-column blocks per workgroup tile (at most GEMM_MAX_NB, the column
+// tiles as even as possible)
+int plan_nb(int64_t N) {
+    const int64_t nblk = ceil_div(N, 16);
+    const int64_t ntiles = ceil_div(nblk, GEMM_MAX_NB);
+    return (int)ceil_div(nblk, ntiles);
+}
+
+// The largest number of K splits: K chunks of at least 256, and partial sums
+// (S M N) of at most a quarter of the operands' volume K (M + N).
+int64_t split_limit(int64_t M, int64_t N, int64_t K) {
     int64_t smax = ceil_div(K, 256);
     const int64_t straffic = (K * (M + N)) / (4 * M * N);
     if (smax > straffic) smax = straffic > 1 ? straffic : 1;
-    if (S > smax) S = smax;
-    if (S < 1) S = 1;
+    return smax < 1 ? 1 : smax;
+}
+
+// cap: the product kernel's resident workgroups on the device (0: three per
+// CU).  The number of K splits is the one whose workgroups fill whole rounds
+// of the resident slots best: a last round a fraction full leaves the rest of
+// the device idle for a whole workgroup's time (FP64 20000 x 10000 x 210: 626
+// tiles fill 768 slots to 82% with any split count up to 5, to 98% with 6).
+// A larger count is taken only for at least 2% more fill (each split adds
+// partial sums to write and reduce).
+GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K, int bk = GEMM_BK, int64_t cap = 0) {
+    GemmPlan p;
+    p.nb = plan_nb(N);
+    p.tm = ceil_div(M, 64);
+    p.tn = ceil_div(N, 16 * p.nb);
     if (K <= 0) {
         p.S = 1;
         p.kchunk = bk;
         return p;
     }
-    p.kchunk = ceil_div(ceil_div(K, S), bk) * bk;
+    const int cus = device_info().num_cus > 0 ? device_info().num_cus : 256;
+    if (cap <= 0) cap = 3 * (int64_t)cus;
+    const int64_t T = p.tm * p.tn, smax = split_limit(M, N, K);
+    int64_t best_kc = ceil_div(K, bk) * bk;
+    double best_fill = -1.0;
+    for (int64_t s = 1; s <= smax; ++s) {
+        const int64_t kc = ceil_div(ceil_div(K, s), bk) * bk;
+        const int64_t w = T * ceil_div(K, kc);                 // workgroups
+        const double fill = (double)w / (double)(ceil_div(w, cap) * cap);
+        if (fill > best_fill + 0.02) {
+            best_fill = fill;
+            best_kc = kc;
+        }
+    }
+    p.kchunk = best_kc;
     p.S = ceil_div(K, p.kchunk);
-    if (p.S < 1) p.S = 1;
     return p;
+}
+
+// resident workgroups of the split-K product kernel that a product with these
+// operand forms and column blocks launches (0 when unknown)
+template <typename T, typename TI, bool TA, bool TB>
+int64_t kernel_capacity(int nb) {
+    const void* f = nullptr;
+    switch (nb) {
+#define RQLP_CAP_CASE(X)                                                                               \
+    case X:                                                                                             \
+        f = (const void*)gemm_skinny_kernel<T, TA, TB, 1, X, gemm_bk<T>(), TI, T, false>;              \
+        break;
+        RQLP_CAP_CASE(1) RQLP_CAP_CASE(2) RQLP_CAP_CASE(3) RQLP_CAP_CASE(4)
+        RQLP_CAP_CASE(5) RQLP_CAP_CASE(6) RQLP_CAP_CASE(7)
+#undef RQLP_CAP_CASE
+        default: break;
+    }
+    return f ? (int64_t)resident_capacity(f, GEMM_THREADS, 0) : 0;
+}
+
+template <typename T, typename TI>
+int64_t product_capacity(bool ta, bool tb, int64_t N) {
+    const int nb = plan_nb(N);
+    if (ta) return kernel_capacity<T, TI, true, false>(nb);
+    if (tb) return kernel_capacity<T, TI, false, true>(nb);
+    return kernel_capacity<T, TI, false, false>(nb);
 }
 
 template <typename T, typename TI, typename TC, bool TA, bool TB, int NB>
@@ -368,10 +419,8 @@ void launch_dispatch(const GemmPlan& p, int64_t M, int64_t N, int64_t K, const T
 }  // namespace
 
 size_t gemm_workspace_elems(int64_t M, int64_t N, int64_t K) {
-    // (the 16-deep plan: deeper stages only round the split size up, so they
-    // never need more partial sums)
-    GemmPlan p = plan_gemm(M, N, K);
-    size_t e = (size_t)(p.S * M * N);
+    // (every plan splits K at most split_limit times)
+    size_t e = (size_t)(split_limit(M, N, K) * M * N);
     if (M == N) {                                    // a Gram matrix may take the CholeskyQR kernel
         const size_t g = gram_workspace_elems(K, M);
         if (g > e) e = g;
@@ -415,7 +464,7 @@ static int gemm_impl(bool ta, bool tb, int64_t M, int64_t N, int64_t K, const TI
     }
     // the general kernels read A and B while other workgroups write C: no aliasing
     if ((const void*)C == (const void*)A || (const void*)C == (const void*)B) return RQLP_E_UNSUPPORTED;
-    GemmPlan p = plan_gemm(M, N, K, gemm_bk<T>());
+    GemmPlan p = plan_gemm(M, N, K, gemm_bk<T>(), product_capacity<T, TI>(ta, tb, N));
     // one K split: the product kernel applies alpha and beta itself
     const bool direct = (p.S == 1 && !trans_out);
     // the gated copy (gate_mode 2) writes op(A) straight into C: only for a
