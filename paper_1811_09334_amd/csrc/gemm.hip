@@ -14,8 +14,9 @@
 // of LDS so that three are resident per CU and hide each other's latencies
 // (measured: 1 resident workgroup with 224-column tiles ran at ~33 TFLOP/s,
 // 3 resident with 112-column tiles at ~50 TFLOP/s on the 20000 x 10000 x 210
-// products).  K is split across blockIdx.z to give ~6 workgroups per CU;
-// partial sums go to a workspace and a second kernel adds them in a fixed
+// products).  K is split across the grid's third dimension (the split count
+// fills whole rounds of the resident workgroups), and the tiles are dealt to
+// the XCDs in contiguous ranges (gemm_tile); partial sums go to a workspace and a second kernel adds them in a fixed
 // order (bitwise reproducible results).
 //
 // LDS layouts (chosen for conflict-free fragment reads on 64 banks):
@@ -61,6 +62,23 @@ constexpr int gemm_bk() { return sizeof(T) == 4 ? 2 * GEMM_BK : GEMM_BK; }
 constexpr int GEMM_MAX_NB = 7;     // at most 7 blocks of 16 columns per tile: 3 workgroups per CU
 constexpr int GEMM_THREADS = 256;
 
+// Tile of this workgroup.  Workgroups are dealt to the 8 XCDs round-robin
+// (linear id L to XCD L % 8), so tile P = (first tile of XCD L % 8) + L / 8
+// gives every XCD a contiguous range of tiles; in that order the N tiles run
+// fastest, then the M tiles, then the K chunks, so that the tiles reading the
+// same rows of op(A) (and, within a K chunk, of op(B)) run at the same time on
+// one XCD and share its L2.  The map is a bijection for any grid.
+__device__ __forceinline__ void gemm_tile(int64_t& bx, int64_t& by, int64_t& bz) {
+    const uint32_t gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+    const uint32_t n = gx * gy * gz;
+    const uint32_t L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const uint32_t x8 = L & 7u, q = n >> 3, r = n & 7u;
+    const uint32_t P = x8 * q + (x8 < r ? x8 : r) + (L >> 3);
+    by = P % gy;
+    bx = (P / gy) % gx;
+    bz = P / (gx * gy);
+}
+
 // T: arithmetic (MFMA) type; TI: element type of A and B (converted to T on
 // load); TC: element type of C / of the split-K partials.
 template <typename T, bool TA, bool TB, int MB, int NB, int BK, typename TI, typename TC, bool AB>
@@ -87,8 +105,10 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int64_t m0 = (int64_t)blockIdx.x * BM;
-    const int64_t n0 = (int64_t)blockIdx.y * BN;
+    int64_t bx, by, bz;
+    gemm_tile(bx, by, bz);
+    const int64_t m0 = bx * BM;
+    const int64_t n0 = by * BN;
     // conditional product: when *gate is 0 nothing is computed; with gate_copy
     // the tile of op(A) is copied to C instead (the product with an identity)
     if (gate != nullptr && *gate == 0) {
@@ -103,7 +123,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
     // above the diagonal are skipped.  tri 2: op(B)(k, j) = 0 for k > j (B^T of a
     // lower triangular B), so the K range of a tile ends at its last column.
     if (tri == 1 && m0 + BM <= n0) return;
-    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kbeg = bz * kchunk;
     int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
     if (tri == 2 && kend > n0 + BN) kend = n0 + BN;
 
@@ -215,7 +235,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
 
     // ---- write C (or this split's partial); AB: C = alpha op(A) op(B) + beta C
     // for a product in one K split (C read only when beta != 0) ----
-    TC* Cs = C + (int64_t)blockIdx.z * split_stride;
+    TC* Cs = C + bz * split_stride;
 #pragma unroll
     for (int a = 0; a < MB; ++a)
 #pragma unroll
