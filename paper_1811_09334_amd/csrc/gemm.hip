@@ -79,8 +79,13 @@ __device__ __forceinline__ void gemm_tile(int64_t& bx, int64_t& by, int64_t& bz)
     bz = P / (gx * gy);
 }
 
-// T: arithmetic (MFMA) type; TI: element type of A and B (converted to T on
-// load); TC: element type of C / of the split-K partials.
+// Zero words that the product kernels load in place of elements outside
+// op(A) / op(B) (never written; not const, so that the load stays a load and
+// needs no select after it, which would make the prefetch wait at once).
+__device__ double g_gemm_zero[2];
+
+// T: arithmetic (MFMA) type; TI: element type of A and B (converted to T when
+// stored to LDS); TC: element type of C / of the split-K partials.
 template <typename T, bool TA, bool TB, int MB, int NB, int BK, typename TI, typename TC, bool AB>
 __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
     int64_t M, int64_t N, int64_t K, const TI* __restrict__ A, int64_t lda,
@@ -133,37 +138,67 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
-    T ra[A_PER_T];
-    T rb[B_PER_T];
+    TI ra[A_PER_T];
+    TI rb[B_PER_T];
+    const TI* zp = reinterpret_cast<const TI*>(g_gemm_zero);
 
     // ---- global -> registers for the tile starting at kt ----
+    // Per-thread element pointers at k = 0 are formed once; a K stage of a
+    // tile that lies wholly inside op(A) (op(B)) loads without bounds checks,
+    // otherwise every element is checked, and one outside the matrix is read
+    // from a zero word instead (an address select, not a branch per element).
+    const bool a_inside = m0 + BM <= M;
+    const bool b_inside = n0 + BN <= N;
+    const TI* pa;
+    const TI* pb;
+    if (!TA) pa = A + (m0 + (tid & 63)) + (int64_t)(tid >> 6) * lda;       // + 64 r + (kt + 4 c) lda
+    else     pa = A + (tid % BK) + (m0 + tid / BK) * lda;                 // + kt + KSTEP r lda
+    if (!TB) pb = B + (tid % BK) + (n0 + tid / BK) * ldb;                 // + kt + KSTEP r ldb
+    else     pb = B;
     auto load_tile = [&](int64_t kt) {
+        const bool kfull = kt + BK <= kend;
         if (!TA) {
-            // op(A) = A: i = tid % 64 + 64 r, k = tid / 64 + 4 c (runs along i)
+            const TI* p = pa + kt * lda;
+            if (a_inside && kfull) {
 #pragma unroll
-            for (int r = 0; r < MB; ++r)
+                for (int r = 0; r < MB; ++r)
 #pragma unroll
-                for (int c = 0; c < BK / 4; ++c) {
-                    const int64_t i = m0 + (tid & 63) + 64 * r;
-                    const int64_t k = kt + (tid >> 6) + 4 * c;
-                    ra[r * (BK / 4) + c] = (i < M && k < kend) ? (T)A[i + k * lda] : T(0);
-                }
+                    for (int c = 0; c < BK / 4; ++c) ra[r * (BK / 4) + c] = p[64 * r + (int64_t)(4 * c) * lda];
+            } else {
+#pragma unroll
+                for (int r = 0; r < MB; ++r)
+#pragma unroll
+                    for (int c = 0; c < BK / 4; ++c) {
+                        const bool ok = (m0 + (tid & 63) + 64 * r < M) && (kt + (tid >> 6) + 4 * c < kend);
+                        ra[r * (BK / 4) + c] = *(ok ? p + 64 * r + (int64_t)(4 * c) * lda : zp);
+                    }
+            }
         } else {
-            // op(A) = A^T: k = tid % BK, i = tid / BK + KSTEP r (runs along k)
+            const TI* p = pa + kt;
+            if (a_inside && kfull) {
 #pragma unroll
-            for (int r = 0; r < A_PER_T; ++r) {
-                const int64_t k = kt + (tid % BK);
-                const int64_t i = m0 + (tid / BK) + KSTEP * r;
-                ra[r] = (i < M && k < kend) ? (T)A[k + i * lda] : T(0);
+                for (int r = 0; r < A_PER_T; ++r) ra[r] = p[(int64_t)(KSTEP * r) * lda];
+            } else {
+                const bool kok = kt + (tid % BK) < kend;
+#pragma unroll
+                for (int r = 0; r < A_PER_T; ++r) {
+                    const bool ok = kok && (m0 + (tid / BK) + KSTEP * r < M);
+                    ra[r] = *(ok ? p + (int64_t)(KSTEP * r) * lda : zp);
+                }
             }
         }
         if (!TB) {
-            // op(B) = B (K x N): k = tid % BK, j = tid / BK + KSTEP r
+            const TI* p = pb + kt;
+            if (b_inside && kfull) {
 #pragma unroll
-            for (int r = 0; r < B_PER_T; ++r) {
-                const int64_t k = kt + (tid % BK);
-                const int64_t j = n0 + (tid / BK) + KSTEP * r;
-                rb[r] = (j < N && k < kend) ? (T)B[k + j * ldb] : T(0);
+                for (int r = 0; r < B_PER_T; ++r) rb[r] = p[(int64_t)(KSTEP * r) * ldb];
+            } else {
+                const bool kok = kt + (tid % BK) < kend;
+#pragma unroll
+                for (int r = 0; r < B_PER_T; ++r) {
+                    const bool ok = kok && (n0 + (tid / BK) + KSTEP * r < N);
+                    rb[r] = *(ok ? p + (int64_t)(KSTEP * r) * ldb : zp);
+                }
             }
         } else {
             // op(B) = B^T, B stored N x K: consecutive threads run along j
@@ -172,7 +207,8 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
                 const int e = tid + GEMM_THREADS * r;
                 const int64_t j = n0 + e % BN;
                 const int64_t k = kt + e / BN;
-                rb[r] = (j < N && k < kend) ? (T)B[j + k * ldb] : T(0);
+                const bool ok = j < N && k < kend;
+                rb[r] = *(ok ? pb + j + k * ldb : zp);
             }
         }
     };
@@ -184,19 +220,19 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
             for (int r = 0; r < MB; ++r)
 #pragma unroll
                 for (int c = 0; c < BK / 4; ++c)
-                    as[((tid >> 6) + 4 * c) * SA + (tid & 63) + 64 * r] = ra[r * (BK / 4) + c];
+                    as[((tid >> 6) + 4 * c) * SA + (tid & 63) + 64 * r] = (T)ra[r * (BK / 4) + c];
         } else {
 #pragma unroll
-            for (int r = 0; r < A_PER_T; ++r) as[((tid / BK) + KSTEP * r) * SA + (tid % BK)] = ra[r];
+            for (int r = 0; r < A_PER_T; ++r) as[((tid / BK) + KSTEP * r) * SA + (tid % BK)] = (T)ra[r];
         }
         if (!TB) {
 #pragma unroll
-            for (int r = 0; r < B_PER_T; ++r) bs[((tid / BK) + KSTEP * r) * SB + (tid % BK)] = rb[r];
+            for (int r = 0; r < B_PER_T; ++r) bs[((tid / BK) + KSTEP * r) * SB + (tid % BK)] = (T)rb[r];
         } else {
 #pragma unroll
             for (int r = 0; r < B_PER_T; ++r) {
                 const int e = tid + GEMM_THREADS * r;
-                bs[(e % BN) * SB + e / BN] = rb[r];
+                bs[(e % BN) * SB + e / BN] = (T)rb[r];
             }
         }
     };
