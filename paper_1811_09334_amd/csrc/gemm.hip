@@ -59,6 +59,11 @@ constexpr int GEMM_BK = 16;        // K depth of one LDS stage (two stages resid
 // ahead, and a 16-deep FP32 stage computes for less than a memory round trip
 template <typename T>
 constexpr int gemm_bk() { return sizeof(T) == 4 ? 2 * GEMM_BK : GEMM_BK; }
+constexpr int pow2_floor(int x) {
+    int p = 1;
+    while (2 * p <= x) p *= 2;
+    return p;
+}
 constexpr int GEMM_MAX_NB = 7;     // at most 7 blocks of 16 columns per tile: 3 workgroups per CU
 constexpr int GEMM_THREADS = 256;
 
@@ -87,7 +92,7 @@ __device__ double g_gemm_zero[2];
 // T: arithmetic (MFMA) type; TI: element type of A and B (converted to T when
 // stored to LDS); TC: element type of C / of the split-K partials.
 template <typename T, bool TA, bool TB, int MB, int NB, int BK, typename TI, typename TC, bool AB>
-__global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
+__global__ __launch_bounds__(GEMM_THREADS) __attribute__((amdgpu_waves_per_eu(std::is_same<T, TI>::value ? 1 : 3))) void gemm_skinny_kernel(
     int64_t M, int64_t N, int64_t K, const TI* __restrict__ A, int64_t lda,
     const TI* __restrict__ B, int64_t ldb, TC* __restrict__ C, int64_t ldc, int64_t split_stride,
     int64_t kchunk, const int32_t* __restrict__ gate, int gate_copy, int tri, T alpha, T beta) {
@@ -100,6 +105,14 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
     constexpr int A_PER_T = BM * BK / GEMM_THREADS;
     constexpr int B_PER_T = BN * BK / GEMM_THREADS;
     constexpr int KSTEP = GEMM_THREADS / BK;             // rows covered per pass of a k-contiguous load
+    // op(B) = B^T (B stored N x K, j contiguous): thread t < TBP BN takes
+    // column t % BN of the tile and k = t / BN + TBP e, e < TBE, so that its
+    // loads step through B with one stride and consecutive threads read
+    // consecutive columns
+    constexpr int TBP = pow2_floor(GEMM_THREADS / BN);
+    constexpr int TBE = BK / TBP;
+    constexpr int RB = TB ? TBE : B_PER_T;                // B elements staged per thread
+    static_assert(TBP * TBE == BK && TBP * BN <= GEMM_THREADS, "B^T staging must cover the stage once");
     static_assert(GEMM_THREADS % BK == 0 && BK % 4 == 0, "BK must divide the workgroup size");
     typedef typename Mfma<T>::acc_t acc_t;
 
@@ -139,7 +152,7 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
         for (int b = 0; b < NB; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
     TI ra[A_PER_T];
-    TI rb[B_PER_T];
+    TI rb[RB];
     const TI* zp = reinterpret_cast<const TI*>(g_gemm_zero);
 
     // ---- global -> registers for the tile starting at kt ----
@@ -154,7 +167,8 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
     if (!TA) pa = A + (m0 + (tid & 63)) + (int64_t)(tid >> 6) * lda;       // + 64 r + (kt + 4 c) lda
     else     pa = A + (tid % BK) + (m0 + tid / BK) * lda;                 // + kt + KSTEP r lda
     if (!TB) pb = B + (tid % BK) + (n0 + tid / BK) * ldb;                 // + kt + KSTEP r ldb
-    else     pb = B;
+    else     pb = B + (n0 + tid % BN) + (int64_t)(tid / BN) * ldb;         // + (kt + TBP e) ldb
+    const bool tb_act = tid < TBP * BN;
     auto load_tile = [&](int64_t kt) {
         const bool kfull = kt + BK <= kend;
         if (!TA) {
@@ -201,14 +215,19 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
                 }
             }
         } else {
-            // op(B) = B^T, B stored N x K: consecutive threads run along j
+            const TI* p = pb + kt * ldb;
+            if (b_inside && kfull) {
+                if (tb_act) {
 #pragma unroll
-            for (int r = 0; r < B_PER_T; ++r) {
-                const int e = tid + GEMM_THREADS * r;
-                const int64_t j = n0 + e % BN;
-                const int64_t k = kt + e / BN;
-                const bool ok = j < N && k < kend;
-                rb[r] = *(ok ? pb + j + k * ldb : zp);
+                    for (int e = 0; e < TBE; ++e) rb[e] = p[(int64_t)(TBP * e) * ldb];
+                }
+            } else {
+                const bool jok = tb_act && n0 + tid % BN < N;
+#pragma unroll
+                for (int e = 0; e < TBE; ++e) {
+                    const bool ok = jok && (kt + tid / BN + TBP * e < kend);
+                    rb[e] = *(ok ? p + (int64_t)(TBP * e) * ldb : zp);
+                }
             }
         }
     };
@@ -228,12 +247,9 @@ __global__ __launch_bounds__(GEMM_THREADS) void gemm_skinny_kernel(
         if (!TB) {
 #pragma unroll
             for (int r = 0; r < B_PER_T; ++r) bs[((tid / BK) + KSTEP * r) * SB + (tid % BK)] = (T)rb[r];
-        } else {
+        } else if (tb_act) {
 #pragma unroll
-            for (int r = 0; r < B_PER_T; ++r) {
-                const int e = tid + GEMM_THREADS * r;
-                bs[(e % BN) * SB + e / BN] = (T)rb[r];
-            }
+            for (int e = 0; e < TBE; ++e) bs[(tid % BN) * SB + tid / BN + TBP * e] = (T)rb[e];
         }
     };
 
