@@ -56,6 +56,36 @@ def test_sketch_and_projection_f32(gpu, m, n, c):
     assert torch.cuda.is_available()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_products_on_padded_offset_views(gpu, dtype):
+    """Sketch and projection on operands that are views into larger column-major
+    arrays (leading dimension above the row count, first element not at the start
+    of the allocation), with M, N and K ragged against the 64 x 112 tiles and the
+    K stages: interior tiles take the unchecked loads, the edges the checked ones."""
+    import torch
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    tol = 1e-13 if dtype == "f64" else 2e-6
+    rng = np.random.default_rng(11)
+    for m, n, c, pad, off in [(1000, 517, 130, 7, 3), (2311, 1033, 210, 1, 1), (640, 4101, 47, 64, 5)]:
+        A = rng.standard_normal((m, n)).astype(np.float32 if dtype == "f32" else np.float64)
+        X = rng.standard_normal((n, c)).astype(A.dtype)
+        V = rng.standard_normal((m, c)).astype(A.dtype)
+        big = torch.zeros((n, m + pad + off), dtype=tdt, device="cuda:0")
+        big[:, off:off + m] = torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda:0")
+        Ad = big.t()[off:off + m, :]                    # column-major view, lda = m + pad + off
+        assert Ad.stride() == (1, m + pad + off) and Ad.storage_offset() == off
+        bigx = torch.zeros((c, n + pad), dtype=tdt, device="cuda:0")
+        bigx[:, :n] = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda:0")
+        Xd = bigx.t()[:n, :]
+        Y = to_np(gpu.sketch(Ad, Xd)).astype(np.float64)
+        ref = A.astype(np.float64) @ X.astype(np.float64)
+        assert np.max(np.abs(Y - ref)) < tol * np.sqrt(n) * np.abs(ref).max() + tol
+        B = to_np(gpu.project(Ad, to_dev(V))).astype(np.float64)
+        refB = V.astype(np.float64).T @ A.astype(np.float64)
+        assert B.shape == (c, n)
+        assert np.max(np.abs(B - refB)) < tol * np.sqrt(m) * np.abs(refB).max() + tol
+
+
 @pytest.mark.parametrize("m,c,cond", [(2000, 25, 1e2), (5000, 210, 1e6), (333, 333, 1e3), (4096, 272, 1e4),
                                       (100, 7, 1.0)])
 def test_cholqr2_orthonormalizes(gpu, m, c, cond):
