@@ -28,7 +28,10 @@
 // both operands in flight.  K is split over workgroups (fixed-order
 // reduction in a second kernel, so results are reproducible), and the
 // workgroups sharing one K range of Y are placed on one XCD (blocks are
-// dealt round-robin to the 8 XCDs), so that slice of Y stays in that XCD's L2.
+// dealt round-robin to the 8 XCDs), so that slice of Y stays in that XCD's L2;
+// with several column tiles (l above 272) those of one row block run side by
+// side on one XCD, so that X is fetched from HBM about once, not once per
+// column tile.
 //
 // IEEE half has too little exponent range for typical matrix entries, so
 // the FP16 form stores A D^{-1} with D = diag(2^e_j) chosen per column
@@ -80,11 +83,13 @@ __global__ __launch_bounds__(LP_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
     constexpr int STAGE = NP * NB * LP_BLK;
     __shared__ __attribute__((aligned(16))) unsigned short Ls[NBUF * STAGE + LP_BLK];   // + a sink kilobyte
 
-    // tile of this workgroup: consecutive tiles (same K range first) on one XCD
+    // tile of this workgroup: consecutive tiles on one XCD, the column tiles of
+    // one row block adjacent (they read the same rows of X, which the XCD's L2
+    // then serves to all but the first), then the row blocks, then the K ranges
     const int64_t L = blockIdx.x, slot = L >> 3;
     const int64_t t = (L & 7) * g.per_xcd + slot;
     if (slot >= g.per_xcd || t >= g.T) return;
-    const int64_t bx = t % g.tm, by = (t / g.tm) % g.tn, bz = t / (g.tm * g.tn);
+    const int64_t by = t % g.tn, bx = (t / g.tn) % g.tm, bz = t / (g.tm * g.tn);
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
